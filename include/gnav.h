@@ -1,0 +1,236 @@
+/*
+ * gnav.h -- C ABI of the MI355X gamma-navigation library (libgnav.so).
+ *
+ * The library answers the two navigation questions stated in Sec. 3.2 of
+ * Seiskari, Kommeri, Niemi, "GPU in Physics Computation: Case Geant4
+ * Navigation" (which volumes hold a point; where a ray next crosses a volume
+ * boundary), and runs the photon free-path sampling of Sec. 3.1 (Alg. 1,
+ * Eqs. 1-8) repeated after every interaction as a gamma transport loop.  Its
+ * call sequence follows the benchmark phases of Sec. 3.4 (Alg. 2): upload the
+ * geometry once (phase 1), hand over primaries that already live in device
+ * memory (phases 2-4), transport them (phase 5, the timed part), read the
+ * results back (phase 6).
+ *
+ * Conventions
+ *   Units: mm, MeV, rad; densities in g/cm3.
+ *   "dev" pointers are HIP device pointers (e.g. a torch tensor's data_ptr on
+ *   ROCm); "host" pointers are ordinary host memory.  The caller owns every
+ *   pointer it passes; the library owns geometry tables, cross-section
+ *   tables, voxel tables and tally buffers.
+ *   Compute calls take a HIP stream as `void*` (NULL = the null stream), are
+ *   ordered on it, enqueue and return; device inputs must stay alive until the
+ *   stream has passed the call.
+ *   Errors are returned as a negative gnav_status; gnav_last_error() gives a
+ *   message.  Outputs are unspecified after an error.  After GNAV_EHIP the
+ *   context should be destroyed.  No exception or abort crosses the ABI.
+ *   One context per host thread; calls on one context are not thread safe.
+ */
+#ifndef GNAV_H
+#define GNAV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gnav_status;
+#define GNAV_OK 0
+#define GNAV_EINVAL (-1)       /* bad argument (null pointer, size, id) */
+#define GNAV_ENOMEM (-2)       /* device or host allocation failed */
+#define GNAV_EHIP (-3)         /* a HIP runtime call failed */
+#define GNAV_EGEOM (-4)        /* invalid geometry description */
+#define GNAV_ESTATE (-5)       /* call out of order (e.g. no geometry yet) */
+#define GNAV_EUNSUPPORTED (-6) /* valid request the library does not implement */
+
+/* Solid families (Sec. 3.5 names boxes, tubes, cones and balls).
+ * Parameters, 8 doubles per solid:
+ *   GNAV_BOX  hx, hy, hz                               (half lengths)
+ *   GNAV_TUBS rmin, rmax, dz, sphi, dphi               (tube section, half length dz)
+ *   GNAV_CONS rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi (cone section; 1 at -dz, 2 at +dz)
+ *   GNAV_ORB  r                                        (full ball)
+ * Sections need 0 <= rmin < rmax at both ends and dphi in (0, pi] or 2 pi. */
+#define GNAV_BOX 0
+#define GNAV_TUBS 1
+#define GNAV_CONS 2
+#define GNAV_ORB 3
+
+/* Surface tolerance (mm): points within half of it of a surface lie on it. */
+#define GNAV_TOLERANCE 1e-9
+
+/* Counter slots returned by gnav_read_tallies. */
+#define GNAV_C_STEPS 0          /* navigation steps (one per transport-loop iteration) */
+#define GNAV_C_PE 1             /* photoelectric absorptions */
+#define GNAV_C_COMPTON 2        /* Compton scatters */
+#define GNAV_C_PAIR 3           /* pair conversions */
+#define GNAV_C_CROSSINGS 4      /* geometry-limited steps */
+#define GNAV_C_ESCAPED 5        /* tracks that left the world */
+#define GNAV_C_CUTOFF 6         /* tracks ended below the energy cut */
+#define GNAV_C_PUSHES 7         /* zero-step pushes */
+#define GNAV_C_STUCK 8          /* tracks killed after repeated zero steps */
+#define GNAV_C_TRUNCATED 9      /* tracks stopped at max_steps_per_track */
+#define GNAV_C_TRACKS 10        /* tracks started (primaries + annihilation photons) */
+#define GNAV_C_SHORTCUTS 11     /* physics steps taken inside the safety (no ComputeStep) */
+#define GNAV_C_DIST_IN 12       /* daughter entry-distance evaluations */
+#define GNAV_C_DIST_OUT 13      /* mother exit-distance evaluations */
+#define GNAV_C_INSIDE 14        /* point-in-solid tests (locate / relocate) */
+#define GNAV_C_VOXEL_NODES 15   /* voxel nodes visited by the step walk */
+#define GNAV_C_INVALID 16       /* primaries skipped: bad event/geometry id, non-finite state, E <= 0 */
+#define GNAV_NCOUNTERS 17
+
+/* Limiter codes of a step. */
+#define GNAV_LIM_MOTHER (-1)    /* left the current volume (>= 0: entered that daughter slot) */
+#define GNAV_LIM_PE (-2)
+#define GNAV_LIM_COMPTON (-3)
+#define GNAV_LIM_PAIR (-4)
+
+/* Track fates in the per-track log. */
+#define GNAV_FATE_ABSORBED 1
+#define GNAV_FATE_ESCAPED 2
+#define GNAV_FATE_CUTOFF 3
+#define GNAV_FATE_STUCK 4
+#define GNAV_FATE_TRUNCATED 5
+#define GNAV_FATE_PAIR 6
+
+typedef struct gnav_ctx gnav_ctx;
+typedef struct gnav_tally gnav_tally;
+
+/* One step of a track in the optional parity log (32 bytes). */
+typedef struct {
+  int32_t touchable; /* touchable id (per geometry) where the step started */
+  int32_t code;      /* limiter code (see GNAV_LIM_*) */
+  double step;       /* step length, mm */
+  double edep;       /* energy deposited at the end of the step, MeV */
+  double energy;     /* photon energy after the step, MeV (0 when absorbed) */
+} gnav_logrec;
+
+/* Flat description of a placement hierarchy (Sec. 3.2: volumes nested in a
+ * hierarchy).  All arrays are host memory owned by the caller and copied
+ * before gnav_upload_geometry returns. */
+typedef struct {
+  int32_t n_solids;
+  const int32_t* solid_type; /* [n_solids] GNAV_BOX..GNAV_ORB */
+  const double* solid_par;   /* [n_solids][8] see above */
+  int32_t n_mats;
+  const double* mat_density; /* [n_mats] g/cm3, 0 = vacuum */
+  const int32_t* mat_el_off; /* [n_mats + 1] element ranges into el_* */
+  const int32_t* el_Z;       /* [mat_el_off[n_mats]] atomic number */
+  const double* el_A;        /* atomic mass, g/mol */
+  const double* el_wfrac;    /* mass fraction */
+  int32_t n_lv;
+  const int32_t* lv_solid;   /* [n_lv] solid index */
+  const int32_t* lv_mat;     /* [n_lv] material index */
+  const int32_t* lv_dau_off; /* [n_lv] first placement of the LV's daughters */
+  const int32_t* lv_dau_cnt; /* [n_lv] number of daughters (slots 0..cnt-1) */
+  const uint8_t* lv_voxelize;/* [n_lv] 1: build a voxel grid for this LV (NULL: all) */
+  int32_t n_pv;
+  const int32_t* pv_lv;      /* [n_pv] placed (child) LV */
+  const double* pv_rot;      /* [n_pv][9] row-major R, x_mother = R x_local + t */
+  const double* pv_trans;    /* [n_pv][3] t */
+  int32_t world_lv;          /* the unplaced top volume (its frame is the global frame) */
+} gnav_geometry_desc;
+
+/* Create a context on HIP device `device`. */
+gnav_status gnav_create(int32_t device, gnav_ctx** out);
+
+/* Destroy a context and every library-owned buffer (tallies included). */
+void gnav_destroy(gnav_ctx* ctx);
+
+/* Message of the last error on ctx (valid until the next call on ctx). */
+const char* gnav_last_error(const gnav_ctx* ctx);
+
+/* Validate a geometry, expand its touchables (distinct placement paths,
+ * numbered breadth first from the world = 0, children of touchable T at
+ * child_base[T] + slot), build voxel grids and attenuation tables, and copy
+ * everything to the device (Alg. 2, phase 1).  Several geometries may be
+ * resident; each gets an id.  Synchronous.  GNAV_EGEOM on bad parameters,
+ * indices or a touchable count above 2^30. */
+gnav_status gnav_upload_geometry(gnav_ctx* ctx, const gnav_geometry_desc* desc, int32_t* geom_id,
+                                 int32_t* n_touchables);
+
+/* Host copies of the touchable table of one geometry; each output may be
+ * NULL, otherwise it has n_touchables entries. */
+gnav_status gnav_touchables(gnav_ctx* ctx, int32_t geom_id, int32_t* parent, int32_t* pv,
+                            int32_t* lv, int32_t* depth);
+
+/* LocateGlobalPoint (Sec. 3.2, first question): the deepest touchable holding
+ * each point.  pos_dev [n][3]; dir_dev [n][3] or NULL.  On a surface a point
+ * belongs to a volume only when its direction points strictly inward through
+ * every face it lies on (without a direction, surface points count as in).
+ * touchable_dev [n] receives the per-geometry touchable id, -1 outside. */
+gnav_status gnav_locate(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                        const double* dir_dev, int32_t* touchable_dev, void* stream);
+
+/* ComputeStep (Sec. 3.2, second question): distance along dir to the next
+ * boundary from each point of its touchable: the smaller of the mother's exit
+ * distance and the daughters' entry distances, the mother winning ties, then
+ * the lowest daughter slot.  touchable_dev NULL: locate first.  Outputs:
+ * step_dev [n] (mm), limiter_dev [n] (GNAV_LIM_MOTHER or the daughter slot),
+ * next_touchable_dev [n] (touchable after relocation at the end point, -1 =
+ * left the world) which may be NULL. */
+gnav_status gnav_compute_step(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                              const double* dir_dev, const int32_t* touchable_dev,
+                              double* step_dev, int32_t* limiter_dev,
+                              int32_t* next_touchable_dev, void* stream);
+
+/* ComputeSafety: a lower bound >= 0 on the isotropic distance from each point
+ * to any boundary of its touchable (mother or daughter), limited to the
+ * point's voxel node.  touchable_dev NULL: locate first. */
+gnav_status gnav_compute_safety(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                                const int32_t* touchable_dev, double* safety_dev, void* stream);
+
+/* Device energy tallies, sized to every touchable resident at creation and to
+ * n_events events.  Created zeroed. */
+gnav_status gnav_tally_create(gnav_ctx* ctx, int32_t n_events, gnav_tally** out);
+gnav_status gnav_tally_reset(gnav_ctx* ctx, gnav_tally* tally, void* stream);
+gnav_status gnav_tally_free(gnav_ctx* ctx, gnav_tally* tally);
+
+/* One batch of primaries; every *_dev array is device memory of n_primaries
+ * entries (pos_dev and dir_dev [n][3]) owned by the caller. */
+typedef struct {
+  int64_t n_primaries;
+  const int32_t* event_dev;   /* event id of each primary, 0 <= id < n_events of the tally */
+  const int32_t* prim_id_dev; /* id of the primary inside its event (track key = id << 2) */
+  const double* pos_dev;
+  const double* dir_dev;      /* unit vectors */
+  const double* energy_dev;   /* MeV */
+  const int32_t* event_geom_dev; /* [n_events] geometry id of each event; NULL: geom_id for all */
+  int32_t geom_id;
+  uint64_t seed;              /* Philox key of the transport stream */
+  double e_cut;               /* MeV: photons below it deposit locally and stop */
+  int64_t max_steps_per_track;/* <= 0: 1e6 */
+  int32_t precision;          /* 0: FP64 distances */
+  int32_t block;              /* threads per block, 0 = library default */
+  int32_t grid;               /* blocks, 0 = library default (fills the device) */
+  gnav_logrec* log_dev;       /* optional per-track log: 3 slots per primary (primary and */
+  int64_t log_capacity;       /*   its two annihilation photons), log_capacity records each */
+  int32_t* log_n_dev;         /*   [3 n] records written per slot (may exceed the capacity) */
+  int32_t* log_fate_dev;      /*   [3 n] GNAV_FATE_* per slot (0 = slot unused) */
+} gnav_batch;
+
+/* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase
+ * 5): photoelectric absorption, Klein-Nishina Compton scattering and pair
+ * conversion, with deposits accumulated into `tally`.  Random numbers come
+ * from Philox4x32-10 keyed by (event, track key, draw), so results do not
+ * depend on launch shape or scheduling. */
+gnav_status gnav_transport_batch(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally,
+                                 void* stream);
+
+/* Copy tallies to host memory (Alg. 2, phase 6) after the stream passes the
+ * earlier calls; synchronises `stream`.  Outputs may be NULL:
+ * edep_touchable [total resident touchables, geometries in id order],
+ * edep_event and escaped_event [n_events], counters [GNAV_NCOUNTERS]. */
+gnav_status gnav_read_tallies(gnav_ctx* ctx, const gnav_tally* tally, double* edep_touchable,
+                              double* edep_event, double* escaped_event, uint64_t* counters,
+                              void* stream);
+
+/* Total touchables over all resident geometries, and the offset of one
+ * geometry's touchables in that concatenation. */
+gnav_status gnav_touchable_offset(gnav_ctx* ctx, int32_t geom_id, int32_t* offset,
+                                  int32_t* total);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNAV_H */

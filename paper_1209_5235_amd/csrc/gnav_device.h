@@ -1,0 +1,699 @@
+// gnav_device.h -- device-side geometry tables, solids and navigation for gfx950.
+//
+// Navigation answers the two questions of Sec. 3.2 (which volumes hold a
+// point; where a ray next meets a boundary) on a placement hierarchy.  The
+// paper's port kept a per-particle navigator with a stack of volumes and
+// dispatched solid calls through "fork" functions (Sec. 3.3), and named
+// register pressure from those structures as its GPU bottleneck (Sec. 5).
+// Here a track's navigation state is a single touchable id (a placement path
+// expanded on the host), every touchable carries its composed world->local
+// transform, and solid dispatch is a switch over a type code read from
+// structure-of-arrays tables.
+//
+// Solid rules (both entry points agree on surfaces): each solid is the
+// intersection of components with signed values negative inside; d(p) is
+// their maximum.  d < -tol/2 is inside, d > tol/2 outside, otherwise on the
+// surface, where a direction counts as entering only if it points strictly
+// inward through every face whose tolerance band holds the point.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gnav {
+
+constexpr double kTol = 1e-9;
+constexpr double kHalfTol = 0.5e-9;
+constexpr double kInf = __builtin_inf();
+constexpr double kMe = 0.51099895;  // electron rest energy, MeV (CODATA 2018)
+constexpr double kTwoPi = 6.283185307179586;
+constexpr int kNNode = 257;         // cross-section nodes, 1 keV .. 100 MeV
+constexpr int kZeroPush = 10;
+constexpr int kZeroKill = 25;
+constexpr int kMaxComptonTrials = 1000;
+
+enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3 };
+enum : int { kOut = -1, kIn = 1 };
+enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4 };
+
+// Solid info bits: type in the low nibble, then has_inner, has_phi.
+constexpr int kInfoInner = 1 << 4;
+constexpr int kInfoPhi = 1 << 5;
+
+// Radial-solid parameter slots (16 doubles per solid).
+enum : int { R_AO = 0, R_BO, R_CO, R_AI, R_BI, R_CI, R_DZ, R_NS0, R_NS1, R_NE0, R_NE1, kSolidStride = 16 };
+
+struct VoxHdr {
+  double lo[3];
+  double w[3];
+  double inv_w[3];
+  int n[3];
+  int node_base;
+};
+
+// All device tables, by value in kernel arguments.  Indices are global over
+// every resident geometry.
+struct DevGeom {
+  const int* t_parent;      // [T] parent touchable, -1 for a world
+  const int* t_lv;          // [T] logical volume
+  const int* t_child_base;  // [T] touchable of daughter slot 0
+  const int* t_slot;        // [T] slot in the parent LV
+  const double* t_xf;       // [T][12] world->local: M (row major) then t; local = M (g - t)
+  const uint8_t* t_kind;    // [T] 0: M is the identity
+  const int* lv_solid;      // [LV]
+  const int* lv_mat;        // [LV]
+  const int* lv_dau_base;   // [LV] first placement
+  const int* lv_dau_cnt;    // [LV]
+  const int* lv_vox;        // [LV] voxel header or -1
+  const double* pv_xf;      // [PV][12] mother->local: M = R^T, t
+  const uint8_t* pv_kind;   // [PV] 0: identity rotation
+  const int* pv_lv;         // [PV]
+  const double* sd_par;     // [S][16]
+  const int* sd_info;       // [S]
+  const VoxHdr* vox_hdr;
+  const int2* vox_node;     // {candidate offset, count}
+  const uint16_t* vox_cand; // daughter slots, ascending within a node
+  const double* xs;         // [mat][3][257] attenuation, 1/mm
+  double lnE0, dlnE;
+};
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+__device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
+
+struct V3 {
+  double x, y, z;
+};
+
+__device__ __forceinline__ V3 xf_point(const double* __restrict__ m, int kind, V3 p) {
+  double d0 = p.x - m[9], d1 = p.y - m[10], d2 = p.z - m[11];
+  if (kind == 0) return V3{d0, d1, d2};
+  return V3{m[0] * d0 + m[1] * d1 + m[2] * d2, m[3] * d0 + m[4] * d1 + m[5] * d2,
+            m[6] * d0 + m[7] * d1 + m[8] * d2};
+}
+
+__device__ __forceinline__ V3 xf_dir(const double* __restrict__ m, int kind, V3 v) {
+  if (kind == 0) return v;
+  return V3{m[0] * v.x + m[1] * v.y + m[2] * v.z, m[3] * v.x + m[4] * v.y + m[5] * v.z,
+            m[6] * v.x + m[7] * v.y + m[8] * v.z};
+}
+
+// ---------------------------------------------------------------------------
+// Box (half lengths h)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double box_d(const double* h, V3 p) {
+  return dmax(dmax(fabs(p.x) - h[0], fabs(p.y) - h[1]), fabs(p.z) - h[2]);
+}
+
+__device__ __forceinline__ int box_inside(const double* h, V3 p, bool has_v, V3 v) {
+  double sx = fabs(p.x) - h[0], sy = fabs(p.y) - h[1], sz = fabs(p.z) - h[2];
+  double d = dmax(dmax(sx, sy), sz);
+  if (d < -kHalfTol) return kIn;
+  if (d > kHalfTol) return kOut;
+  if (!has_v) return kIn;
+  if (fabs(sx) <= kHalfTol && p.x * v.x >= 0) return kOut;
+  if (fabs(sy) <= kHalfTol && p.y * v.y >= 0) return kOut;
+  if (fabs(sz) <= kHalfTol && p.z * v.z >= 0) return kOut;
+  return kIn;
+}
+
+// Slab entry: the ray enters when it is inside all three slabs.
+__device__ __forceinline__ double box_dist_in(const double* h, V3 p, V3 v) {
+  if (fabs(p.x) - h[0] >= -kHalfTol && p.x * v.x >= 0) return kInf;
+  if (fabs(p.y) - h[1] >= -kHalfTol && p.y * v.y >= 0) return kInf;
+  if (fabs(p.z) - h[2] >= -kHalfTol && p.z * v.z >= 0) return kInf;
+  double te = -kInf, tx = kInf;
+  const double pc[3] = {p.x, p.y, p.z};
+  const double vc[3] = {v.x, v.y, v.z};
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    if (vc[i] == 0.0) continue;
+    double t1 = (-h[i] - pc[i]) / vc[i];
+    double t2 = (h[i] - pc[i]) / vc[i];
+    te = dmax(te, dmin(t1, t2));
+    tx = dmin(tx, dmax(t1, t2));
+  }
+  if (te >= tx - kHalfTol) return kInf;
+  return te < kHalfTol ? 0.0 : te;
+}
+
+__device__ __forceinline__ double box_dist_out(const double* h, V3 p, V3 v) {
+  double t = kInf;
+  const double pc[3] = {p.x, p.y, p.z};
+  const double vc[3] = {v.x, v.y, v.z};
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    double sd;
+    if (vc[i] > 0) sd = h[i] - pc[i];
+    else if (vc[i] < 0) sd = h[i] + pc[i];
+    else continue;
+    if (sd <= kHalfTol) return 0.0;
+    t = dmin(t, sd / fabs(vc[i]));
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Orb (radius R)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double orb_d(double R, V3 p) {
+  return sqrt(p.x * p.x + p.y * p.y + p.z * p.z) - R;
+}
+
+__device__ __forceinline__ int orb_inside(double R, V3 p, bool has_v, V3 v) {
+  double d = orb_d(R, p);
+  if (d < -kHalfTol) return kIn;
+  if (d > kHalfTol) return kOut;
+  if (!has_v) return kIn;
+  return (p.x * v.x + p.y * v.y + p.z * v.z) < 0 ? kIn : kOut;
+}
+
+__device__ __forceinline__ double orb_dist_in(double R, V3 p, V3 v) {
+  double rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  double sd = sqrt(rr) - R;
+  double b = p.x * v.x + p.y * v.y + p.z * v.z;
+  if (sd < -kHalfTol) return 0.0;
+  if (b >= 0) return kInf;
+  double c = rr - R * R;
+  double disc = b * b - c;
+  if (disc <= 0) return kInf;
+  double sq = sqrt(disc);
+  double te = c / (sq - b);
+  double tx = sq - b;
+  if (te >= tx - kHalfTol) return kInf;
+  return te < kHalfTol ? 0.0 : te;
+}
+
+__device__ __forceinline__ double orb_dist_out(double R, V3 p, V3 v) {
+  double rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  double sd = sqrt(rr) - R;
+  double b = p.x * v.x + p.y * v.y + p.z * v.z;
+  if (sd >= -kHalfTol && b >= 0) return 0.0;
+  double c = rr - R * R;
+  double disc = b * b - c;
+  if (disc < 0) disc = 0;
+  double sq = sqrt(disc);
+  double t = (b > 0) ? -c / (b + sq) : sq - b;
+  return t > 0 ? t : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Tube and cone sections: outer surface rho = Ao + Bo z, inner rho = Ai + Bi
+// z (optional), slab |z| <= dz, phi wedge (optional, at most pi wide).
+// ---------------------------------------------------------------------------
+
+struct RadComps {
+  double ro, ri, z, pa, pb;
+};
+
+__device__ __forceinline__ RadComps rad_comps(const double* q, int info, V3 p) {
+  RadComps k;
+  double rho = sqrt(p.x * p.x + p.y * p.y);
+  k.ro = (rho - (q[R_AO] + q[R_BO] * p.z)) * q[R_CO];
+  k.ri = (info & kInfoInner) ? ((q[R_AI] + q[R_BI] * p.z) - rho) * q[R_CI] : -kInf;
+  k.z = fabs(p.z) - q[R_DZ];
+  if (info & kInfoPhi) {
+    k.pa = p.x * q[R_NS0] + p.y * q[R_NS1];
+    k.pb = p.x * q[R_NE0] + p.y * q[R_NE1];
+  } else {
+    k.pa = -kInf;
+    k.pb = -kInf;
+  }
+  return k;
+}
+
+__device__ __forceinline__ double rad_dmax(const RadComps& k) {
+  return dmax(dmax(dmax(k.ro, k.ri), dmax(k.z, k.pa)), k.pb);
+}
+
+__device__ __forceinline__ int rad_inside(const double* q, int info, V3 p, bool has_v, V3 v) {
+  RadComps k = rad_comps(q, info, p);
+  double d = rad_dmax(k);
+  if (d < -kHalfTol) return kIn;
+  if (d > kHalfTol) return kOut;
+  if (!has_v) return kIn;
+  double rho = sqrt(p.x * p.x + p.y * p.y);
+  double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
+  if (fabs(k.ro) <= kHalfTol && rv - q[R_BO] * v.z >= 0) return kOut;
+  if ((info & kInfoInner) && fabs(k.ri) <= kHalfTol && -rv + q[R_BI] * v.z >= 0) return kOut;
+  if (fabs(k.z) <= kHalfTol && p.z * v.z >= 0) return kOut;
+  if (info & kInfoPhi) {
+    if (fabs(k.pa) <= kHalfTol && v.x * q[R_NS0] + v.y * q[R_NS1] >= 0) return kOut;
+    if (fabs(k.pb) <= kHalfTol && v.x * q[R_NE0] + v.y * q[R_NE1] >= 0) return kOut;
+  }
+  return kIn;
+}
+
+// Roots of f(t) = rho(t)^2 - (A + B z(t))^2 = a t^2 + 2 b t + c on the real
+// sheet (A + B z >= 0); `want` selects the slope sign: +1 leaving rho <= R(z),
+// -1 entering it.  Returns the smallest such root that is >= lo.
+__device__ __forceinline__ double radial_root(double A, double B, V3 p, V3 v, int want, double lo) {
+  double R0 = A + B * p.z;
+  double Rv = B * v.z;
+  double a = v.x * v.x + v.y * v.y - Rv * Rv;
+  double b = p.x * v.x + p.y * v.y - R0 * Rv;
+  double c = p.x * p.x + p.y * p.y - R0 * R0;
+  double t0, t1;
+  int n;
+  if (a == 0.0) {
+    if (b == 0.0) return kInf;
+    t0 = -c / (2.0 * b);
+    t1 = kInf;
+    n = 1;
+  } else {
+    double disc = b * b - a * c;
+    if (disc < 0.0) return kInf;
+    double sq = sqrt(disc);
+    double qq = (b >= 0.0) ? -(b + sq) : (sq - b);
+    double r1 = qq / a;
+    double r2 = (qq != 0.0) ? c / qq : r1;
+    t0 = dmin(r1, r2);
+    t1 = dmax(r1, r2);
+    n = 2;
+  }
+  double best = kInf;
+  {
+    double s = a * t0 + b;
+    bool ok = want > 0 ? (s > 0) : (s < 0);
+    if (ok && R0 + Rv * t0 >= 0 && t0 >= lo) best = t0;
+  }
+  if (n == 2 && best == kInf) {
+    double s = a * t1 + b;
+    bool ok = want > 0 ? (s > 0) : (s < 0);
+    if (ok && R0 + Rv * t1 >= 0 && t1 >= lo) best = t1;
+  }
+  return best;
+}
+
+__device__ __forceinline__ bool rad_ok_except(const double* q, int info, V3 p, V3 v, double t,
+                                              int skip) {
+  V3 r{p.x + t * v.x, p.y + t * v.y, p.z + t * v.z};
+  RadComps k = rad_comps(q, info, r);
+  if (skip != 0 && k.ro > kHalfTol) return false;
+  if (skip != 1 && k.ri > kHalfTol) return false;
+  if (skip != 2 && k.z > kHalfTol) return false;
+  if (skip != 3 && k.pa > kHalfTol) return false;
+  if (skip != 4 && k.pb > kHalfTol) return false;
+  return true;
+}
+
+// Entry distance, surface by surface: a crossing through one face counts if
+// every other component holds at the crossing point.
+__device__ __noinline__ double rad_dist_in(const double* q, int info, V3 p, V3 v) {
+  RadComps k = rad_comps(q, info, p);
+  if (rad_dmax(k) < -kHalfTol) return 0.0;
+  double rho = sqrt(p.x * p.x + p.y * p.y);
+  double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
+  double best = kInf;
+  if (k.z >= -kHalfTol) {
+    if (p.z * v.z >= 0) return kInf;
+    double t = k.z / fabs(v.z);
+    if (t < 0) t = 0;
+    if (rad_ok_except(q, info, p, v, t, 2)) best = dmin(best, t);
+  }
+  if (k.ro >= -kHalfTol) {
+    if (rv - q[R_BO] * v.z >= 0) return kInf;
+    double t = radial_root(q[R_AO], q[R_BO], p, v, -1, -kInf);
+    if (t == kInf) return kInf;
+    if (t < 0) t = 0;
+    if (rad_ok_except(q, info, p, v, t, 0)) best = dmin(best, t);
+  }
+  if (info & kInfoInner) {
+    double t = -1.0;
+    if (fabs(k.ri) <= kHalfTol) {
+      double vn = -rv + q[R_BI] * v.z;
+      if (vn < 0) t = 0.0;
+      else if (vn > 0) t = radial_root(q[R_AI], q[R_BI], p, v, +1, 0.0);
+    } else {
+      t = radial_root(q[R_AI], q[R_BI], p, v, +1, 0.0);
+    }
+    if (t >= 0 && t < kInf && rad_ok_except(q, info, p, v, t, 1)) best = dmin(best, t);
+  }
+  if (info & kInfoPhi) {
+    if (k.pa >= -kHalfTol) {
+      double dv = v.x * q[R_NS0] + v.y * q[R_NS1];
+      if (dv >= 0) return kInf;
+      double t = k.pa / (-dv);
+      if (t < 0) t = 0;
+      if (rad_ok_except(q, info, p, v, t, 3)) best = dmin(best, t);
+    }
+    if (k.pb >= -kHalfTol) {
+      double dv = v.x * q[R_NE0] + v.y * q[R_NE1];
+      if (dv >= 0) return kInf;
+      double t = k.pb / (-dv);
+      if (t < 0) t = 0;
+      if (rad_ok_except(q, info, p, v, t, 4)) best = dmin(best, t);
+    }
+  }
+  return best < kHalfTol ? 0.0 : best;
+}
+
+__device__ __noinline__ double rad_dist_out(const double* q, int info, V3 p, V3 v) {
+  RadComps k = rad_comps(q, info, p);
+  double rho = sqrt(p.x * p.x + p.y * p.y);
+  double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
+  double t = kInf;
+  if (v.z != 0) {
+    double sd = v.z > 0 ? q[R_DZ] - p.z : q[R_DZ] + p.z;
+    if (sd <= kHalfTol) return 0.0;
+    t = dmin(t, sd / fabs(v.z));
+  }
+  if (k.ro >= -kHalfTol && rv - q[R_BO] * v.z >= 0) return 0.0;
+  t = dmin(t, radial_root(q[R_AO], q[R_BO], p, v, +1, 0.0));
+  if (info & kInfoInner) {
+    if (k.ri >= -kHalfTol && -rv + q[R_BI] * v.z >= 0) return 0.0;
+    t = dmin(t, radial_root(q[R_AI], q[R_BI], p, v, -1, 0.0));
+  }
+  if (info & kInfoPhi) {
+    double dv = v.x * q[R_NS0] + v.y * q[R_NS1];
+    if (k.pa >= -kHalfTol && dv >= 0) return 0.0;
+    if (dv > 0) t = dmin(t, dmax(-k.pa / dv, 0.0));
+    dv = v.x * q[R_NE0] + v.y * q[R_NE1];
+    if (k.pb >= -kHalfTol && dv >= 0) return 0.0;
+    if (dv > 0) t = dmin(t, dmax(-k.pb / dv, 0.0));
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over solid families ("fork" by type code)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int solid_inside(const DevGeom& G, int s, V3 p, bool has_v, V3 v) {
+  int info = G.sd_info[s];
+  const double* q = G.sd_par + (size_t)s * kSolidStride;
+  switch (info & 15) {
+    case kBox: return box_inside(q, p, has_v, v);
+    case kOrb: return orb_inside(q[0], p, has_v, v);
+    default: return rad_inside(q, info, p, has_v, v);
+  }
+}
+
+__device__ __forceinline__ double solid_d(const DevGeom& G, int s, V3 p) {
+  int info = G.sd_info[s];
+  const double* q = G.sd_par + (size_t)s * kSolidStride;
+  switch (info & 15) {
+    case kBox: return box_d(q, p);
+    case kOrb: return orb_d(q[0], p);
+    default: return rad_dmax(rad_comps(q, info, p));
+  }
+}
+
+__device__ __forceinline__ double solid_dist_in(const DevGeom& G, int s, V3 p, V3 v) {
+  int info = G.sd_info[s];
+  const double* q = G.sd_par + (size_t)s * kSolidStride;
+  switch (info & 15) {
+    case kBox: return box_dist_in(q, p, v);
+    case kOrb: return orb_dist_in(q[0], p, v);
+    default: return rad_dist_in(q, info, p, v);
+  }
+}
+
+__device__ __forceinline__ double solid_dist_out(const DevGeom& G, int s, V3 p, V3 v) {
+  int info = G.sd_info[s];
+  const double* q = G.sd_par + (size_t)s * kSolidStride;
+  switch (info & 15) {
+    case kBox: return box_dist_out(q, p, v);
+    case kOrb: return orb_dist_out(q[0], p, v);
+    default: return rad_dist_out(q, info, p, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Voxel grids: a uniform grid per mother LV over its extent; each node lists
+// the daughters whose padded bounding box meets the node, in slot order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int vox_axis_index(double p, double lo, double inv_w, int n) {
+  double x = (p - lo) * inv_w;
+  x = dmin(dmax(x, 0.0), (double)(n - 1));
+  return (int)x;
+}
+
+// Per-evaluation counters (optional, for the roofline's work accounting).
+struct NavCount {
+  unsigned dist_in, dist_out, inside, nodes;
+};
+
+// Daughters of touchable-LV `lv` holding (pl, vl), first match in slot order.
+__device__ __forceinline__ int find_daughter(const DevGeom& G, int lv, V3 pl, bool has_v, V3 vl,
+                                             int blocked, NavCount& nc) {
+  int cnt = G.lv_dau_cnt[lv];
+  if (cnt == 0) return -1;
+  int base = G.lv_dau_base[lv];
+  int vh = G.lv_vox[lv];
+  if (vh < 0) {
+    for (int k = 0; k < cnt; k++) {
+      if (k == blocked) continue;
+      int pv = base + k;
+      int kind = G.pv_kind[pv];
+      const double* m = G.pv_xf + (size_t)pv * 12;
+      V3 pd = xf_point(m, kind, pl);
+      V3 vd = xf_dir(m, kind, vl);
+      nc.inside++;
+      if (solid_inside(G, G.lv_solid[G.pv_lv[pv]], pd, has_v, vd) == kIn) return k;
+    }
+    return -1;
+  }
+  const VoxHdr& h = G.vox_hdr[vh];
+  int ix = vox_axis_index(pl.x, h.lo[0], h.inv_w[0], h.n[0]);
+  int iy = vox_axis_index(pl.y, h.lo[1], h.inv_w[1], h.n[1]);
+  int iz = vox_axis_index(pl.z, h.lo[2], h.inv_w[2], h.n[2]);
+  int2 nd = G.vox_node[h.node_base + (ix * h.n[1] + iy) * h.n[2] + iz];
+  for (int c = 0; c < nd.y; c++) {
+    int k = G.vox_cand[nd.x + c];
+    if (k == blocked) continue;
+    int pv = base + k;
+    int kind = G.pv_kind[pv];
+    const double* m = G.pv_xf + (size_t)pv * 12;
+    V3 pd = xf_point(m, kind, pl);
+    V3 vd = xf_dir(m, kind, vl);
+    nc.inside++;
+    if (solid_inside(G, G.lv_solid[G.pv_lv[pv]], pd, has_v, vd) == kIn) return k;
+  }
+  return -1;
+}
+
+// Descend from touchable T (holding the point) to the deepest holder.
+__device__ __forceinline__ int descend(const DevGeom& G, int T, V3 pg, bool has_v, V3 vg, int blocked,
+                                       NavCount& nc) {
+  const double* m = G.t_xf + (size_t)T * 12;
+  int kind = G.t_kind[T];
+  V3 pl = xf_point(m, kind, pg);
+  V3 vl = xf_dir(m, kind, vg);
+  for (;;) {
+    int lv = G.t_lv[T];
+    int k = find_daughter(G, lv, pl, has_v, vl, blocked, nc);
+    if (k < 0) return T;
+    int pv = G.lv_dau_base[lv] + k;
+    int pk = G.pv_kind[pv];
+    const double* mm = G.pv_xf + (size_t)pv * 12;
+    pl = xf_point(mm, pk, pl);
+    vl = xf_dir(mm, pk, vl);
+    T = G.t_child_base[T] + k;
+    blocked = -1;
+  }
+}
+
+// LocateGlobalPoint from the world touchable W.
+__device__ __forceinline__ int locate(const DevGeom& G, int W, V3 pg, bool has_v, V3 vg, NavCount& nc) {
+  nc.inside++;
+  if (solid_inside(G, G.lv_solid[G.t_lv[W]], pg, has_v, vg) == kOut) return -1;
+  return descend(G, W, pg, has_v, vg, -1, nc);
+}
+
+__device__ __forceinline__ void touchable_frame(const DevGeom& G, int T, V3 pg, V3 vg, V3& pl, V3& vl) {
+  const double* m = G.t_xf + (size_t)T * 12;
+  int kind = G.t_kind[T];
+  pl = xf_point(m, kind, pg);
+  vl = xf_dir(m, kind, vg);
+}
+
+// Relocation after a geometry step: enter daughter `lim`, or climb out of
+// the volume(s) left and search the parent with the left volume excluded.
+__device__ __forceinline__ int relocate(const DevGeom& G, int T, V3 pg, V3 vg, int lim, NavCount& nc) {
+  if (lim >= 0) return descend(G, G.t_child_base[T] + lim, pg, true, vg, -1, nc);
+  int left = T;
+  int P = G.t_parent[T];
+  while (P >= 0) {
+    V3 pl, vl;
+    touchable_frame(G, P, pg, vg, pl, vl);
+    nc.inside++;
+    if (solid_inside(G, G.lv_solid[G.t_lv[P]], pl, true, vl) != kOut) break;
+    left = P;
+    P = G.t_parent[P];
+  }
+  if (P < 0) return -1;
+  return descend(G, P, pg, true, vg, G.t_slot[left], nc);
+}
+
+// Entry distance of daughter slot k of mother LV (base = first placement).
+__device__ __forceinline__ double daughter_dist_in(const DevGeom& G, int base, int k, V3 pl, V3 vl) {
+  int pv = base + k;
+  int kind = G.pv_kind[pv];
+  const double* m = G.pv_xf + (size_t)pv * 12;
+  V3 pd = xf_point(m, kind, pl);
+  V3 vd = xf_dir(m, kind, vl);
+  return solid_dist_in(G, G.lv_solid[G.pv_lv[pv]], pd, vd);
+}
+
+__device__ __forceinline__ double daughter_safety_in(const DevGeom& G, int base, int k, V3 pl) {
+  int pv = base + k;
+  int kind = G.pv_kind[pv];
+  const double* m = G.pv_xf + (size_t)pv * 12;
+  V3 pd = xf_point(m, kind, pl);
+  double d = solid_d(G, G.lv_solid[G.pv_lv[pv]], pd);
+  return d > 0 ? d : 0.0;
+}
+
+// ComputeStep in the mother frame (pl, vl) of a touchable with LV `lv`:
+// the mother's exit distance against daughter entry distances, collected by
+// walking the voxel nodes along the ray until the best distance lies strictly
+// inside the current node.  The mother wins ties, then the lowest slot.
+// Also returns the voxel-limited safety at the start point.
+__device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, V3 vl, int& lim,
+                                               double& safety, NavCount& nc) {
+  int ms = G.lv_solid[lv];
+  double s = solid_dist_out(G, ms, pl, vl);
+  double md = solid_d(G, ms, pl);
+  double saf = md < 0 ? -md : 0.0;
+  nc.dist_out++;
+  lim = kLimMother;
+  int cnt = G.lv_dau_cnt[lv];
+  if (cnt == 0) {
+    safety = saf;
+    return s;
+  }
+  int base = G.lv_dau_base[lv];
+  int vh = G.lv_vox[lv];
+  if (vh < 0) {
+    for (int k = 0; k < cnt; k++) {
+      double t = daughter_dist_in(G, base, k, pl, vl);
+      saf = dmin(saf, daughter_safety_in(G, base, k, pl));
+      nc.dist_in++;
+      if (t < s) {
+        s = t;
+        lim = k;
+      }
+    }
+    safety = saf;
+    return s;
+  }
+  const VoxHdr& h = G.vox_hdr[vh];
+  int idx[3] = {vox_axis_index(pl.x, h.lo[0], h.inv_w[0], h.n[0]),
+                vox_axis_index(pl.y, h.lo[1], h.inv_w[1], h.n[1]),
+                vox_axis_index(pl.z, h.lo[2], h.inv_w[2], h.n[2])};
+  const double pc[3] = {pl.x, pl.y, pl.z};
+  const double vc[3] = {vl.x, vl.y, vl.z};
+  // safety also limited by the start node's faces (not beyond the grid edge)
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    double lo = h.lo[a] + idx[a] * h.w[a];
+    double hi = h.lo[a] + (idx[a] + 1) * h.w[a];
+    if (idx[a] > 0) saf = dmin(saf, dmax(pc[a] - lo, 0.0));
+    if (idx[a] < h.n[a] - 1) saf = dmin(saf, dmax(hi - pc[a], 0.0));
+  }
+  bool first = true;
+  for (;;) {
+    int2 nd = G.vox_node[h.node_base + (idx[0] * h.n[1] + idx[1]) * h.n[2] + idx[2]];
+    nc.nodes++;
+    for (int c = 0; c < nd.y; c++) {
+      int k = G.vox_cand[nd.x + c];
+      double t = daughter_dist_in(G, base, k, pl, vl);
+      nc.dist_in++;
+      if (first) saf = dmin(saf, daughter_safety_in(G, base, k, pl));
+      if (t < s || (t == s && lim >= 0 && k < lim)) {
+        s = t;
+        lim = k;
+      }
+    }
+    first = false;
+    // distance to the node's exit plane along each axis
+    double tx = kInf;
+    int ax = -1;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (vc[a] == 0.0) continue;
+      double plane = h.lo[a] + (idx[a] + (vc[a] > 0 ? 1 : 0)) * h.w[a];
+      double ta = (plane - pc[a]) / vc[a];
+      if (ta < tx) {
+        tx = ta;
+        ax = a;
+      }
+    }
+    if (ax < 0 || s < tx) break;
+    idx[ax] += vc[ax] > 0 ? 1 : -1;
+    if (idx[ax] < 0 || idx[ax] >= h.n[ax]) break;
+  }
+  safety = saf;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Random numbers: Philox4x32-10 keyed by (event, track key, draw)
+// ---------------------------------------------------------------------------
+
+struct Philox {
+  uint32_t key0, key1;  // seed
+  uint32_t event, tkey;
+  uint32_t draw;
+  uint32_t cached_block;
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+__device__ __forceinline__ void rng_start(Philox& r, uint64_t seed, uint32_t event, uint32_t tkey) {
+  r.key0 = (uint32_t)seed;
+  r.key1 = (uint32_t)(seed >> 32);
+  r.event = event;
+  r.tkey = tkey;
+  r.draw = 0;
+  r.cached_block = 0xFFFFFFFFu;
+}
+
+// Uniform in (0, 1]: 53 bits from two words, plus one.
+__device__ __forceinline__ double rng_next(Philox& r) {
+  uint32_t blk = r.draw >> 1;
+  if (blk != r.cached_block) {
+    philox_block(blk, r.tkey, r.event, 0u, r.key0, r.key1, r.w);
+    r.cached_block = blk;
+  }
+  uint32_t lo, hi;
+  if (r.draw & 1u) {
+    lo = r.w[2];
+    hi = r.w[3];
+  } else {
+    lo = r.w[0];
+    hi = r.w[1];
+  }
+  r.draw++;
+  uint64_t m = ((((uint64_t)hi) << 32) | (uint64_t)lo) >> 11;
+  return (double)(m + 1u) * 0x1p-53;
+}
+
+}  // namespace gnav

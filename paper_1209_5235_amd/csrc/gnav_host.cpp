@@ -1,0 +1,966 @@
+// gnav_host.cpp -- host runtime behind the C ABI: geometry validation and
+// flattening, touchable expansion, voxel grids, attenuation tables, device
+// buffers, tallies and launches.
+//
+// Alg. 2 (Sec. 3.4) of the paper loads the geometry and copies it to the GPU
+// once (phase 1) and times only the parallel phase; the same split holds here:
+// everything in this file runs at upload time or around a launch, never per
+// step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gnav.h"
+#include "gnav_device.h"
+#include "gnav_internal.h"
+
+using namespace gnav;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Device buffer
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t upload(const void* src, size_t n) {
+    release();
+    if (n == 0) n = 8;  // keep a valid pointer for empty tables
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    if (src) return hipMemcpy(p, src, n, hipMemcpyHostToDevice);
+    return hipMemset(p, 0, n);
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+template <class T>
+hipError_t up(DevBuf& b, const std::vector<T>& v) {
+  return b.upload(v.empty() ? nullptr : v.data(), v.size() * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// Attenuation tables (per material, photoelectric / Compton / pair)
+// ---------------------------------------------------------------------------
+
+constexpr long double kRe = 2.8179403262e-13L;  // classical electron radius, cm
+constexpr long double kNA = 6.02214076e23L;     // 1/mol
+constexpr long double kAlpha = 1.0L / 137.035999084L;
+constexpr long double kPi = 3.141592653589793238462643383279502884L;
+constexpr long double kPeScale = 4.0e-32L;      // cm2 MeV^3 (4.0e-8 barn MeV^3)
+
+// Klein-Nishina total cross section per electron (cm2), k = E / m_e c^2,
+// evaluated in extended precision because its terms cancel at small k.
+long double kn_total(long double k) {
+  long double two_k = 2.0L * k;
+  long double lg = log1pl(two_k);
+  long double inv = 1.0L / (1.0L + two_k);
+  long double t1 = (1.0L + k) / (k * k) * (2.0L * (1.0L + k) * inv - lg / k);
+  long double t2 = lg / two_k;
+  long double t3 = (1.0L + 3.0L * k) * inv * inv;
+  return 2.0L * kPi * kRe * kRe * (t1 + t2 - t3);
+}
+
+// Per-atom cross sections (cm2): photoelectric K Z^4/E^3, Compton Z sigma_KN,
+// and nuclear-field pair production alpha r_e^2 Z^2 F(k) with F the
+// unscreened Bethe-Heitler form, raised to the near-threshold (k-2)^3 term and
+// capped by complete screening.
+void atom_xs(int Z, long double E, long double out[3]) {
+  long double z = (long double)Z;
+  long double k = E / (long double)kMe;
+  out[0] = kPeScale * (z * z) * (z * z) / (E * E * E);
+  out[1] = z * kn_total(k);
+  out[2] = 0.0L;
+  if (k > 2.0L) {
+    long double r = 1.0L - 2.0L / k;
+    long double thr = (2.0L * kPi / 3.0L) * r * r * r;
+    long double bh = (28.0L / 9.0L) * logl(2.0L * k) - 218.0L / 27.0L;
+    long double cs = (28.0L / 9.0L) * logl(183.0L / cbrtl(z)) - 2.0L / 27.0L;
+    long double f = std::min(cs, std::max(thr, bh));
+    out[2] = kAlpha * kRe * kRe * z * z * f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solid preprocessing and extents
+// ---------------------------------------------------------------------------
+
+struct Box3 {
+  double lo[3], hi[3];
+};
+
+// Extent of a tube/cone section (local frame): the corners of the annular
+// sector at its smallest and largest radius plus its axis crossings.
+void sector_extent(double rmin1, double rmax1, double rmin2, double rmax2, double dz, double sphi,
+                   double dphi, Box3* ext) {
+  double rlo = std::min(rmin1, rmin2), rhi = std::max(rmax1, rmax2);
+  ext->lo[2] = -dz;
+  ext->hi[2] = dz;
+  if (!(dphi < 2.0 * M_PI)) {
+    ext->lo[0] = ext->lo[1] = -rhi;
+    ext->hi[0] = ext->hi[1] = rhi;
+    return;
+  }
+  double lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
+  for (double r : {rlo, rhi}) {
+    for (double a : {sphi, sphi + dphi}) {
+      lx = std::min(lx, r * std::cos(a));
+      hx = std::max(hx, r * std::cos(a));
+      ly = std::min(ly, r * std::sin(a));
+      hy = std::max(hy, r * std::sin(a));
+    }
+  }
+  for (int k = -8; k <= 8; k++) {
+    double a = k * 0.5 * M_PI;
+    if (a > sphi && a < sphi + dphi) {
+      lx = std::min(lx, rhi * std::cos(a));
+      hx = std::max(hx, rhi * std::cos(a));
+      ly = std::min(ly, rhi * std::sin(a));
+      hy = std::max(hy, rhi * std::sin(a));
+    }
+  }
+  ext->lo[0] = lx;
+  ext->hi[0] = hx;
+  ext->lo[1] = ly;
+  ext->hi[1] = hy;
+}
+
+bool solid_prep(int type, const double* par, double* q /*16*/, int* info, Box3* ext, std::string& why) {
+  for (int i = 0; i < kSolidStride; i++) q[i] = 0.0;
+  for (int i = 0; i < 8; i++) {
+    if (!std::isfinite(par[i])) {
+      why = "non-finite solid parameter";
+      return false;
+    }
+  }
+  if (type == kBox) {
+    if (!(par[0] > 0 && par[1] > 0 && par[2] > 0)) {
+      why = "box half lengths must be positive";
+      return false;
+    }
+    q[0] = par[0];
+    q[1] = par[1];
+    q[2] = par[2];
+    *info = kBox;
+    for (int a = 0; a < 3; a++) {
+      ext->lo[a] = -par[a];
+      ext->hi[a] = par[a];
+    }
+    return true;
+  }
+  if (type == kOrb) {
+    if (!(par[0] > 0)) {
+      why = "orb radius must be positive";
+      return false;
+    }
+    q[0] = par[0];
+    *info = kOrb;
+    for (int a = 0; a < 3; a++) {
+      ext->lo[a] = -par[0];
+      ext->hi[a] = par[0];
+    }
+    return true;
+  }
+  double rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi;
+  if (type == kTubs) {
+    rmin1 = rmin2 = par[0];
+    rmax1 = rmax2 = par[1];
+    dz = par[2];
+    sphi = par[3];
+    dphi = par[4];
+  } else if (type == kCons) {
+    rmin1 = par[0];
+    rmax1 = par[1];
+    rmin2 = par[2];
+    rmax2 = par[3];
+    dz = par[4];
+    sphi = par[5];
+    dphi = par[6];
+  } else {
+    why = "unknown solid type";
+    return false;
+  }
+  if (!(dz > 0) || !(rmin1 >= 0) || !(rmin2 >= 0) || !(rmax1 > rmin1) || !(rmax2 > rmin2)) {
+    why = "section radii/half length out of range";
+    return false;
+  }
+  if ((rmin1 > 0 && rmin1 < kTol) || (rmin2 > 0 && rmin2 < kTol)) {
+    why = "inner radius below the surface tolerance";
+    return false;
+  }
+  const double twopi = 2.0 * M_PI;
+  if (!(dphi > 0) || dphi > twopi || (dphi < twopi && dphi > M_PI)) {
+    why = "phi sections must span (0, pi] or the full 2 pi";
+    return false;
+  }
+  q[R_AO] = 0.5 * (rmax1 + rmax2);
+  q[R_BO] = (rmax2 - rmax1) / (2.0 * dz);
+  q[R_CO] = 1.0 / std::sqrt(1.0 + q[R_BO] * q[R_BO]);
+  q[R_AI] = 0.5 * (rmin1 + rmin2);
+  q[R_BI] = (rmin2 - rmin1) / (2.0 * dz);
+  q[R_CI] = 1.0 / std::sqrt(1.0 + q[R_BI] * q[R_BI]);
+  q[R_DZ] = dz;
+  int inf = type;
+  if (rmin1 > 0 || rmin2 > 0) inf |= kInfoInner;
+  bool phi = dphi < twopi;
+  if (phi) {
+    inf |= kInfoPhi;
+    double ephi = sphi + dphi;
+    q[R_NS0] = std::sin(sphi);
+    q[R_NS1] = -std::cos(sphi);
+    q[R_NE0] = -std::sin(ephi);
+    q[R_NE1] = std::cos(ephi);
+  }
+  *info = inf;
+  sector_extent(rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi, ext);
+  return true;
+}
+
+// Extent of a placed solid in its mother frame: the 8 transformed corners of
+// the local extent (exact for axis-aligned placements, conservative otherwise).
+Box3 place_box(const Box3& b, const double* R, const double* t) {
+  Box3 o;
+  for (int a = 0; a < 3; a++) {
+    o.lo[a] = INFINITY;
+    o.hi[a] = -INFINITY;
+  }
+  for (int c = 0; c < 8; c++) {
+    double p[3] = {(c & 1) ? b.hi[0] : b.lo[0], (c & 2) ? b.hi[1] : b.lo[1], (c & 4) ? b.hi[2] : b.lo[2]};
+    for (int a = 0; a < 3; a++) {
+      double x = R[3 * a] * p[0] + R[3 * a + 1] * p[1] + R[3 * a + 2] * p[2] + t[a];
+      o.lo[a] = std::min(o.lo[a], x);
+      o.hi[a] = std::max(o.hi[a], x);
+    }
+  }
+  return o;
+}
+
+// Tighter placed extent: a tube/cone section turned about z is the same
+// section with its start angle shifted, so its extent is recomputed exactly.
+Box3 place_solid(int type, const double* par, const Box3& local, const double* R, const double* t) {
+  bool zrot = R[2] == 0.0 && R[5] == 0.0 && R[6] == 0.0 && R[7] == 0.0 && R[8] == 1.0;
+  if (zrot && (type == kTubs || type == kCons)) {
+    double th = std::atan2(R[3], R[0]);
+    Box3 e;
+    if (type == kTubs) sector_extent(par[0], par[1], par[0], par[1], par[2], par[3] + th, par[4], &e);
+    else sector_extent(par[0], par[1], par[2], par[3], par[4], par[5] + th, par[6], &e);
+    // guard against rounding of the shifted angle
+    for (int a = 0; a < 3; a++) {
+      double pad = 1e-9 * std::max(1.0, std::max(std::fabs(e.lo[a]), std::fabs(e.hi[a])));
+      e.lo[a] += t[a] - pad;
+      e.hi[a] += t[a] + pad;
+    }
+    Box3 loose = place_box(local, R, t);
+    for (int a = 0; a < 3; a++) {
+      e.lo[a] = std::max(e.lo[a], loose.lo[a]);
+      e.hi[a] = std::min(e.hi[a], loose.hi[a]);
+    }
+    return e;
+  }
+  return place_box(local, R, t);
+}
+
+// True when the placement's extent is exact (axis-permuting rotation or a
+// z-turned section), so a protrusion beyond the mother's extent is real.
+bool extent_is_tight(int type, const double* R) {
+  bool zrot = R[2] == 0.0 && R[5] == 0.0 && R[6] == 0.0 && R[7] == 0.0 && R[8] == 1.0;
+  if (zrot && (type == kTubs || type == kCons)) return true;
+  for (int i = 0; i < 9; i++)
+    if (R[i] != 0.0 && R[i] != 1.0 && R[i] != -1.0) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Voxel grid choice: per axis a slice count from a small candidate set; the
+// score is the mean number of candidates per node (separable per daughter:
+// sum of slice spans products / nodes) plus a small per-slice walk cost.
+// ---------------------------------------------------------------------------
+
+struct VoxBuild {
+  VoxHdr hdr;
+  std::vector<std::vector<uint16_t>> nodes;
+};
+
+int span_lo(double x, double lo, double w, int n) {
+  double f = std::floor((x - lo) / w);
+  if (f < 0) return 0;
+  if (f > n - 1) return n - 1;
+  return (int)f;
+}
+
+VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
+  const int cnt = (int)dau.size();
+  Box3 g = mother;
+  for (const Box3& d : dau) {
+    for (int a = 0; a < 3; a++) {
+      g.lo[a] = std::min(g.lo[a], d.lo[a]);
+      g.hi[a] = std::max(g.hi[a], d.hi[a]);
+    }
+  }
+  // pad the grid box slightly so points on its faces map inside
+  for (int a = 0; a < 3; a++) {
+    double s = 1e-9 * std::max(1.0, std::max(std::fabs(g.lo[a]), std::fabs(g.hi[a])));
+    g.lo[a] -= s;
+    g.hi[a] += s;
+  }
+  const int max_nodes = std::max(64, std::min(1 << 18, 8 * cnt));
+  std::vector<int> opts[3];
+  for (int a = 0; a < 3; a++) {
+    std::vector<double> w;
+    for (const Box3& d : dau) w.push_back(d.hi[a] - d.lo[a]);
+    std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
+    double med = std::max(w[w.size() / 2], 1e-6);
+    double L = g.hi[a] - g.lo[a];
+    std::vector<int> o = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+    for (double f : {1.0, 2.0}) {
+      long m = std::lround(f * L / med);
+      if (m >= 1 && m <= 256) o.push_back((int)m);
+    }
+    std::sort(o.begin(), o.end());
+    o.erase(std::unique(o.begin(), o.end()), o.end());
+    opts[a] = o;
+  }
+  // spans[a][option][daughter]
+  std::vector<std::vector<std::vector<int>>> spans(3);
+  for (int a = 0; a < 3; a++) {
+    for (int n : opts[a]) {
+      double w = (g.hi[a] - g.lo[a]) / n;
+      std::vector<int> s(cnt);
+      for (int d = 0; d < cnt; d++) {
+        s[d] = span_lo(dau[d].hi[a], g.lo[a], w, n) - span_lo(dau[d].lo[a], g.lo[a], w, n) + 1;
+      }
+      spans[a].push_back(std::move(s));
+    }
+  }
+  double best = INFINITY;
+  int bi[3] = {0, 0, 0};
+  for (size_t i = 0; i < opts[0].size(); i++)
+    for (size_t j = 0; j < opts[1].size(); j++)
+      for (size_t k = 0; k < opts[2].size(); k++) {
+        long nodes = (long)opts[0][i] * opts[1][j] * opts[2][k];
+        if (nodes > max_nodes) continue;
+        double tot = 0;
+        for (int d = 0; d < cnt; d++)
+          tot += (double)spans[0][i][d] * spans[1][j][d] * spans[2][k][d];
+        double score = tot / nodes + 0.02 * (opts[0][i] + opts[1][j] + opts[2][k]);
+        if (score < best - 1e-12) {
+          best = score;
+          bi[0] = (int)i;
+          bi[1] = (int)j;
+          bi[2] = (int)k;
+        }
+      }
+  VoxBuild vb;
+  for (int a = 0; a < 3; a++) {
+    int n = opts[a][bi[a]];
+    vb.hdr.n[a] = n;
+    vb.hdr.lo[a] = g.lo[a];
+    vb.hdr.w[a] = (g.hi[a] - g.lo[a]) / n;
+    vb.hdr.inv_w[a] = 1.0 / vb.hdr.w[a];
+  }
+  const int nx = vb.hdr.n[0], ny = vb.hdr.n[1], nz = vb.hdr.n[2];
+  vb.nodes.assign((size_t)nx * ny * nz, {});
+  for (int d = 0; d < cnt; d++) {
+    int l[3], h[3];
+    for (int a = 0; a < 3; a++) {
+      l[a] = span_lo(dau[d].lo[a], g.lo[a], vb.hdr.w[a], vb.hdr.n[a]);
+      h[a] = span_lo(dau[d].hi[a], g.lo[a], vb.hdr.w[a], vb.hdr.n[a]);
+    }
+    for (int i = l[0]; i <= h[0]; i++)
+      for (int j = l[1]; j <= h[1]; j++)
+        for (int k = l[2]; k <= h[2]; k++) vb.nodes[((size_t)i * ny + j) * nz + k].push_back((uint16_t)d);
+  }
+  return vb;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+struct GeomRec {
+  int t_base, n_t;
+  int lv_base, pv_base, solid_base, mat_base;
+  std::vector<int> h_parent, h_pv, h_lv, h_depth;  // per-geometry ids
+};
+
+}  // namespace
+
+struct gnav_ctx {
+  int device = 0;
+  int n_cu = 256;
+  std::string err;
+  // concatenated host tables
+  std::vector<int> t_parent, t_lv, t_child_base, t_slot;
+  std::vector<double> t_xf;
+  std::vector<uint8_t> t_kind;
+  std::vector<int> lv_solid, lv_mat, lv_dau_base, lv_dau_cnt, lv_vox;
+  std::vector<double> pv_xf;
+  std::vector<uint8_t> pv_kind;
+  std::vector<int> pv_lv;
+  std::vector<double> sd_par;
+  std::vector<int> sd_info;
+  std::vector<VoxHdr> vox_hdr;
+  std::vector<int2> vox_node;
+  std::vector<uint16_t> vox_cand;
+  std::vector<double> xs;
+  std::vector<GeomRec> geoms;
+  std::vector<int> geom_tbase;
+  double lnE0 = 0, dlnE = 0;
+  // device copies
+  DevBuf d_t_parent, d_t_lv, d_t_child_base, d_t_slot, d_t_xf, d_t_kind;
+  DevBuf d_lv_solid, d_lv_mat, d_lv_dau_base, d_lv_dau_cnt, d_lv_vox;
+  DevBuf d_pv_xf, d_pv_kind, d_pv_lv, d_sd_par, d_sd_info;
+  DevBuf d_vox_hdr, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
+  DevBuf d_queue;
+  DevGeom G{};
+};
+
+struct gnav_tally {
+  int n_events = 0;
+  int n_touch = 0;
+  DevBuf edep_t, edep_ev, esc_ev, counters;
+};
+
+namespace {
+
+gnav_status fail(gnav_ctx* c, gnav_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+gnav_status hip_fail(gnav_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? GNAV_ENOMEM : GNAV_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                     \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+hipError_t upload_all(gnav_ctx* c) {
+  hipError_t e;
+#define UP(buf, vec) \
+  if ((e = up(c->buf, c->vec)) != hipSuccess) return e;
+  UP(d_t_parent, t_parent)
+  UP(d_t_lv, t_lv)
+  UP(d_t_child_base, t_child_base)
+  UP(d_t_slot, t_slot)
+  UP(d_t_xf, t_xf)
+  UP(d_t_kind, t_kind)
+  UP(d_lv_solid, lv_solid)
+  UP(d_lv_mat, lv_mat)
+  UP(d_lv_dau_base, lv_dau_base)
+  UP(d_lv_dau_cnt, lv_dau_cnt)
+  UP(d_lv_vox, lv_vox)
+  UP(d_pv_xf, pv_xf)
+  UP(d_pv_kind, pv_kind)
+  UP(d_pv_lv, pv_lv)
+  UP(d_sd_par, sd_par)
+  UP(d_sd_info, sd_info)
+  UP(d_vox_hdr, vox_hdr)
+  UP(d_vox_node, vox_node)
+  UP(d_vox_cand, vox_cand)
+  UP(d_xs, xs)
+  UP(d_geom_tbase, geom_tbase)
+#undef UP
+  DevGeom& G = c->G;
+  G.t_parent = c->d_t_parent.as<int>();
+  G.t_lv = c->d_t_lv.as<int>();
+  G.t_child_base = c->d_t_child_base.as<int>();
+  G.t_slot = c->d_t_slot.as<int>();
+  G.t_xf = c->d_t_xf.as<double>();
+  G.t_kind = c->d_t_kind.as<uint8_t>();
+  G.lv_solid = c->d_lv_solid.as<int>();
+  G.lv_mat = c->d_lv_mat.as<int>();
+  G.lv_dau_base = c->d_lv_dau_base.as<int>();
+  G.lv_dau_cnt = c->d_lv_dau_cnt.as<int>();
+  G.lv_vox = c->d_lv_vox.as<int>();
+  G.pv_xf = c->d_pv_xf.as<double>();
+  G.pv_kind = c->d_pv_kind.as<uint8_t>();
+  G.pv_lv = c->d_pv_lv.as<int>();
+  G.sd_par = c->d_sd_par.as<double>();
+  G.sd_info = c->d_sd_info.as<int>();
+  G.vox_hdr = c->d_vox_hdr.as<VoxHdr>();
+  G.vox_node = c->d_vox_node.as<int2>();
+  G.vox_cand = c->d_vox_cand.as<uint16_t>();
+  G.xs = c->d_xs.as<double>();
+  G.lnE0 = c->lnE0;
+  G.dlnE = c->dlnE;
+  return hipSuccess;
+}
+
+bool is_identity(const double* R) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      if (R[3 * i + j] != (i == j ? 1.0 : 0.0)) return false;
+  return true;
+}
+
+gnav_status check_geom(gnav_ctx* c, int geom_id) {
+  if (!c) return GNAV_EINVAL;
+  if (c->geoms.empty()) return fail(c, GNAV_ESTATE, "no geometry uploaded");
+  if (geom_id < 0 || geom_id >= (int)c->geoms.size()) return fail(c, GNAV_EINVAL, "bad geometry id");
+  return GNAV_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+gnav_status gnav_create(int32_t device, gnav_ctx** out) {
+  if (!out) return GNAV_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GNAV_EHIP;
+  if (device < 0 || device >= ndev) return GNAV_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return GNAV_EHIP;
+  gnav_ctx* c = new (std::nothrow) gnav_ctx();
+  if (!c) return GNAV_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  if (c->d_queue.upload(nullptr, 64) != hipSuccess) {
+    delete c;
+    return GNAV_ENOMEM;
+  }
+  c->lnE0 = std::log(1e-3);
+  c->dlnE = std::log(1e5) / 256.0;
+  *out = c;
+  return GNAV_OK;
+}
+
+void gnav_destroy(gnav_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+}
+
+const char* gnav_last_error(const gnav_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32_t* geom_id,
+                                 int32_t* n_touchables) {
+  if (!c || !d) return GNAV_EINVAL;
+  c->err.clear();
+  if (d->n_solids <= 0 || d->n_lv <= 0 || d->n_mats <= 0 || d->n_pv < 0)
+    return fail(c, GNAV_EGEOM, "empty geometry");
+  if (!d->solid_type || !d->solid_par || !d->mat_density || !d->mat_el_off || !d->lv_solid ||
+      !d->lv_mat || !d->lv_dau_off || !d->lv_dau_cnt || (d->n_pv > 0 && (!d->pv_lv || !d->pv_rot ||
+                                                                          !d->pv_trans)))
+    return fail(c, GNAV_EINVAL, "null array in geometry description");
+  if (d->world_lv < 0 || d->world_lv >= d->n_lv) return fail(c, GNAV_EGEOM, "bad world LV");
+  // solids
+  std::vector<double> q(d->n_solids * kSolidStride);
+  std::vector<int> info(d->n_solids);
+  std::vector<Box3> ext(d->n_solids);
+  for (int s = 0; s < d->n_solids; s++) {
+    std::string why;
+    if (!solid_prep(d->solid_type[s], d->solid_par + 8 * s, &q[s * kSolidStride], &info[s], &ext[s], why))
+      return fail(c, GNAV_EGEOM, "solid " + std::to_string(s) + ": " + why);
+  }
+  // materials
+  int n_el = d->mat_el_off[d->n_mats];
+  if (d->mat_el_off[0] != 0 || n_el < 0) return fail(c, GNAV_EGEOM, "bad material element ranges");
+  if (n_el > 0 && (!d->el_Z || !d->el_A || !d->el_wfrac)) return fail(c, GNAV_EINVAL, "null element arrays");
+  for (int m = 0; m < d->n_mats; m++) {
+    if (!(d->mat_density[m] >= 0) || !std::isfinite(d->mat_density[m]))
+      return fail(c, GNAV_EGEOM, "bad density");
+    if (d->mat_el_off[m + 1] < d->mat_el_off[m]) return fail(c, GNAV_EGEOM, "bad material element ranges");
+  }
+  for (int e = 0; e < n_el; e++) {
+    if (d->el_Z[e] < 1 || d->el_Z[e] > 120 || !(d->el_A[e] > 0) || !(d->el_wfrac[e] >= 0))
+      return fail(c, GNAV_EGEOM, "bad element");
+  }
+  // LVs and PVs
+  for (int l = 0; l < d->n_lv; l++) {
+    if (d->lv_solid[l] < 0 || d->lv_solid[l] >= d->n_solids || d->lv_mat[l] < 0 || d->lv_mat[l] >= d->n_mats)
+      return fail(c, GNAV_EGEOM, "LV " + std::to_string(l) + ": bad solid or material index");
+    if (d->lv_dau_cnt[l] < 0 || d->lv_dau_off[l] < 0 || d->lv_dau_off[l] + d->lv_dau_cnt[l] > d->n_pv)
+      return fail(c, GNAV_EGEOM, "LV " + std::to_string(l) + ": daughter range out of bounds");
+    if (d->lv_dau_cnt[l] > 65535) return fail(c, GNAV_EGEOM, "more than 65535 daughters in one LV");
+  }
+  for (int p = 0; p < d->n_pv; p++) {
+    if (d->pv_lv[p] < 0 || d->pv_lv[p] >= d->n_lv) return fail(c, GNAV_EGEOM, "PV: bad LV index");
+    const double* R = d->pv_rot + 9 * p;
+    for (int i = 0; i < 3; i++) {
+      if (!std::isfinite(d->pv_trans[3 * p + i])) return fail(c, GNAV_EGEOM, "PV: non-finite translation");
+      for (int j = 0; j < 3; j++) {
+        double dot = 0;
+        for (int k = 0; k < 3; k++) dot += R[3 * k + i] * R[3 * k + j];
+        if (!(std::fabs(dot - (i == j ? 1.0 : 0.0)) < 1e-9))
+          return fail(c, GNAV_EGEOM, "PV " + std::to_string(p) + ": rotation is not orthonormal");
+      }
+    }
+  }
+  // daughters must lie inside their mother's extent (conservative check)
+  for (int l = 0; l < d->n_lv; l++) {
+    const Box3& M = ext[d->lv_solid[l]];
+    for (int k = 0; k < d->lv_dau_cnt[l]; k++) {
+      int p = d->lv_dau_off[l] + k;
+      int ds = d->lv_solid[d->pv_lv[p]];
+      if (!extent_is_tight(d->solid_type[ds], d->pv_rot + 9 * p)) continue;
+      Box3 b = place_solid(d->solid_type[ds], d->solid_par + 8 * ds, ext[ds], d->pv_rot + 9 * p,
+                           d->pv_trans + 3 * p);
+      for (int a = 0; a < 3; a++) {
+        double slack = 1e-6 * std::max(1.0, std::fabs(M.hi[a] - M.lo[a]));
+        if (b.lo[a] < M.lo[a] - slack || b.hi[a] > M.hi[a] + slack)
+          return fail(c, GNAV_EGEOM, "LV " + std::to_string(l) + ": daughter " + std::to_string(k) +
+                                         " protrudes from its mother");
+      }
+    }
+  }
+  // touchable count (fails on cycles / explosion)
+  std::vector<long long> cnt(d->n_lv, 0);
+  for (int it = 0; it <= d->n_lv + 1; it++) {
+    bool changed = false;
+    for (int l = 0; l < d->n_lv; l++) {
+      long long s = 1;
+      for (int k = 0; k < d->lv_dau_cnt[l]; k++) s += cnt[d->pv_lv[d->lv_dau_off[l] + k]];
+      s = std::min(s, 1LL << 40);
+      if (s != cnt[l]) {
+        cnt[l] = s;
+        changed = true;
+      }
+    }
+    if (!changed) break;
+    if (it == d->n_lv + 1) return fail(c, GNAV_EGEOM, "placement cycle");
+  }
+  long long nt_ll = cnt[d->world_lv];
+  long long total_t = (long long)c->t_parent.size() + nt_ll;
+  if (nt_ll > (1LL << 30) || total_t > (1LL << 30)) return fail(c, GNAV_EGEOM, "too many touchables");
+  const int nt = (int)nt_ll;
+
+  GeomRec gr;
+  gr.t_base = (int)c->t_parent.size();
+  gr.n_t = nt;
+  gr.lv_base = (int)c->lv_solid.size();
+  gr.pv_base = (int)c->pv_lv.size();
+  gr.solid_base = (int)c->sd_info.size();
+  gr.mat_base = (int)(c->xs.size() / (3 * kNNode));
+
+  // solids, materials
+  c->sd_par.insert(c->sd_par.end(), q.begin(), q.end());
+  c->sd_info.insert(c->sd_info.end(), info.begin(), info.end());
+  for (int m = 0; m < d->n_mats; m++) {
+    for (int p = 0; p < 3; p++) {
+      for (int i = 0; i < kNNode; i++) {
+        long double E = expl((long double)c->lnE0 + (long double)i * (long double)c->dlnE);
+        long double mu = 0.0L;
+        for (int e = d->mat_el_off[m]; e < d->mat_el_off[m + 1]; e++) {
+          long double xsv[3];
+          atom_xs(d->el_Z[e], (long double)(double)E, xsv);
+          long double n_at = (long double)d->mat_density[m] * kNA * (long double)d->el_wfrac[e] /
+                             (long double)d->el_A[e];
+          mu += n_at * xsv[p];
+        }
+        c->xs.push_back((double)(mu * 0.1L));  // 1/cm -> 1/mm
+      }
+    }
+  }
+  // PVs
+  for (int p = 0; p < d->n_pv; p++) {
+    const double* R = d->pv_rot + 9 * p;
+    const double* t = d->pv_trans + 3 * p;
+    // M = R^T (row major): M[i][j] = R[j][i]
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) c->pv_xf.push_back(R[3 * j + i]);
+    c->pv_xf.push_back(t[0]);
+    c->pv_xf.push_back(t[1]);
+    c->pv_xf.push_back(t[2]);
+    c->pv_kind.push_back(is_identity(R) ? 0 : 1);
+    c->pv_lv.push_back(gr.lv_base + d->pv_lv[p]);
+  }
+  // LVs and voxels
+  for (int l = 0; l < d->n_lv; l++) {
+    c->lv_solid.push_back(gr.solid_base + d->lv_solid[l]);
+    c->lv_mat.push_back(gr.mat_base + d->lv_mat[l]);
+    c->lv_dau_base.push_back(gr.pv_base + d->lv_dau_off[l]);
+    c->lv_dau_cnt.push_back(d->lv_dau_cnt[l]);
+    int vh = -1;
+    bool want = d->lv_voxelize ? d->lv_voxelize[l] != 0 : true;
+    if (want && d->lv_dau_cnt[l] >= 3) {
+      std::vector<Box3> db;
+      for (int k = 0; k < d->lv_dau_cnt[l]; k++) {
+        int p = d->lv_dau_off[l] + k;
+        int ds = d->lv_solid[d->pv_lv[p]];
+        Box3 b = place_solid(d->solid_type[ds], d->solid_par + 8 * ds, ext[ds], d->pv_rot + 9 * p,
+                             d->pv_trans + 3 * p);
+        for (int a = 0; a < 3; a++) {
+          double pad = 1e-7 + 1e-12 * std::max(std::fabs(b.lo[a]), std::fabs(b.hi[a]));
+          b.lo[a] -= pad;
+          b.hi[a] += pad;
+        }
+        db.push_back(b);
+      }
+      VoxBuild vb = build_voxels(ext[d->lv_solid[l]], db);
+      vb.hdr.node_base = (int)c->vox_node.size();
+      std::map<std::vector<uint16_t>, int> dedup;
+      for (auto& nd : vb.nodes) {
+        auto it = dedup.find(nd);
+        int off;
+        if (it == dedup.end()) {
+          off = (int)c->vox_cand.size();
+          c->vox_cand.insert(c->vox_cand.end(), nd.begin(), nd.end());
+          dedup.emplace(nd, off);
+        } else {
+          off = it->second;
+        }
+        c->vox_node.push_back(int2{off, (int)nd.size()});
+      }
+      vh = (int)c->vox_hdr.size();
+      c->vox_hdr.push_back(vb.hdr);
+    }
+    c->lv_vox.push_back(vh);
+  }
+  // touchables: breadth first from the world
+  gr.h_parent.assign(nt, -1);
+  gr.h_pv.assign(nt, -1);
+  gr.h_lv.assign(nt, 0);
+  gr.h_depth.assign(nt, 0);
+  std::vector<int> slot(nt, -1), child(nt, 0);
+  std::vector<long double> Rg((size_t)nt * 9), tg((size_t)nt * 3);
+  gr.h_lv[0] = d->world_lv;
+  for (int i = 0; i < 9; i++) Rg[i] = (i % 4 == 0) ? 1.0L : 0.0L;
+  for (int i = 0; i < 3; i++) tg[i] = 0.0L;
+  int n = 1;
+  for (int i = 0; i < n; i++) {
+    int l = gr.h_lv[i];
+    child[i] = n;
+    for (int k = 0; k < d->lv_dau_cnt[l]; k++) {
+      int p = d->lv_dau_off[l] + k;
+      gr.h_parent[n] = i;
+      gr.h_pv[n] = p;
+      gr.h_lv[n] = d->pv_lv[p];
+      gr.h_depth[n] = gr.h_depth[i] + 1;
+      slot[n] = k;
+      const double* R = d->pv_rot + 9 * p;
+      const double* t = d->pv_trans + 3 * p;
+      // x_world = Rg_parent (R x + t) + tg_parent
+      for (int a = 0; a < 3; a++) {
+        for (int b = 0; b < 3; b++) {
+          long double s = 0;
+          for (int m = 0; m < 3; m++) s += Rg[(size_t)i * 9 + 3 * a + m] * (long double)R[3 * m + b];
+          Rg[(size_t)n * 9 + 3 * a + b] = s;
+        }
+        long double s = tg[(size_t)i * 3 + a];
+        for (int m = 0; m < 3; m++) s += Rg[(size_t)i * 9 + 3 * a + m] * (long double)t[m];
+        tg[(size_t)n * 3 + a] = s;
+      }
+      n++;
+    }
+  }
+  for (int i = 0; i < nt; i++) {
+    c->t_parent.push_back(gr.h_parent[i] < 0 ? -1 : gr.t_base + gr.h_parent[i]);
+    c->t_lv.push_back(gr.lv_base + gr.h_lv[i]);
+    c->t_child_base.push_back(gr.t_base + child[i]);
+    c->t_slot.push_back(slot[i]);
+    bool ident = true;
+    double M[9];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        M[3 * a + b] = (double)Rg[(size_t)i * 9 + 3 * b + a];  // transpose
+        if (M[3 * a + b] != (a == b ? 1.0 : 0.0)) ident = false;
+      }
+    c->t_xf.insert(c->t_xf.end(), M, M + 9);
+    for (int a = 0; a < 3; a++) c->t_xf.push_back((double)tg[(size_t)i * 3 + a]);
+    c->t_kind.push_back(ident ? 0 : 1);
+  }
+  c->geom_tbase.push_back(gr.t_base);
+  int id = (int)c->geoms.size();
+  c->geoms.push_back(std::move(gr));
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  hipError_t e = upload_all(c);
+  if (e != hipSuccess) return hip_fail(c, e, "geometry upload");
+  if (geom_id) *geom_id = id;
+  if (n_touchables) *n_touchables = nt;
+  return GNAV_OK;
+}
+
+gnav_status gnav_touchables(gnav_ctx* c, int32_t geom_id, int32_t* parent, int32_t* pv, int32_t* lv,
+                            int32_t* depth) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  const GeomRec& g = c->geoms[geom_id];
+  for (int i = 0; i < g.n_t; i++) {
+    if (parent) parent[i] = g.h_parent[i];
+    if (pv) pv[i] = g.h_pv[i];
+    if (lv) lv[i] = g.h_lv[i];
+    if (depth) depth[i] = g.h_depth[i];
+  }
+  return GNAV_OK;
+}
+
+gnav_status gnav_touchable_offset(gnav_ctx* c, int32_t geom_id, int32_t* offset, int32_t* total) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (offset) *offset = c->geoms[geom_id].t_base;
+  if (total) *total = (int32_t)c->t_parent.size();
+  return GNAV_OK;
+}
+
+gnav_status gnav_locate(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
+                        int32_t* out, void* stream) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (n < 0 || (n > 0 && (!pos || !out))) return fail(c, GNAV_EINVAL, "bad locate arguments");
+  int tb = c->geoms[geom_id].t_base;
+  HIP_TRY(c, launch_locate(c->G, tb, tb, n, pos, dir, out, (hipStream_t)stream), "locate launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_compute_step(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
+                              const int32_t* touch, double* step, int32_t* lim, int32_t* next,
+                              void* stream) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (n < 0 || (n > 0 && (!pos || !dir || !step || !lim))) return fail(c, GNAV_EINVAL, "bad step arguments");
+  int tb = c->geoms[geom_id].t_base;
+  HIP_TRY(c, launch_step(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, dir, touch, step, lim, next,
+                         (hipStream_t)stream),
+          "step launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_compute_safety(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos,
+                                const int32_t* touch, double* out, void* stream) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (n < 0 || (n > 0 && (!pos || !out))) return fail(c, GNAV_EINVAL, "bad safety arguments");
+  int tb = c->geoms[geom_id].t_base;
+  HIP_TRY(c, launch_safety(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, touch, out, (hipStream_t)stream),
+          "safety launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_tally_create(gnav_ctx* c, int32_t n_events, gnav_tally** out) {
+  if (!c || !out || n_events < 0) return GNAV_EINVAL;
+  *out = nullptr;
+  if (c->geoms.empty()) return fail(c, GNAV_ESTATE, "no geometry uploaded");
+  gnav_tally* t = new (std::nothrow) gnav_tally();
+  if (!t) return fail(c, GNAV_ENOMEM, "tally");
+  t->n_events = n_events;
+  t->n_touch = (int)c->t_parent.size();
+  hipError_t e;
+  if ((e = t->edep_t.upload(nullptr, sizeof(double) * t->n_touch)) != hipSuccess ||
+      (e = t->edep_ev.upload(nullptr, sizeof(double) * (size_t)n_events)) != hipSuccess ||
+      (e = t->esc_ev.upload(nullptr, sizeof(double) * (size_t)n_events)) != hipSuccess ||
+      (e = t->counters.upload(nullptr, sizeof(unsigned long long) * GNAV_NCOUNTERS)) != hipSuccess) {
+    delete t;
+    return hip_fail(c, e, "tally allocation");
+  }
+  *out = t;
+  return GNAV_OK;
+}
+
+gnav_status gnav_tally_reset(gnav_ctx* c, gnav_tally* t, void* stream) {
+  if (!c || !t) return GNAV_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, launch_zero(t->edep_t.p, t->edep_t.bytes / 8, st), "tally reset");
+  HIP_TRY(c, launch_zero(t->edep_ev.p, t->edep_ev.bytes / 8, st), "tally reset");
+  HIP_TRY(c, launch_zero(t->esc_ev.p, t->esc_ev.bytes / 8, st), "tally reset");
+  HIP_TRY(c, launch_zero(t->counters.p, t->counters.bytes / 8, st), "tally reset");
+  return GNAV_OK;
+}
+
+gnav_status gnav_tally_free(gnav_ctx* c, gnav_tally* t) {
+  if (!c) return GNAV_EINVAL;
+  delete t;
+  return GNAV_OK;
+}
+
+gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream) {
+  if (!c || !b || !t) return GNAV_EINVAL;
+  gnav_status s = check_geom(c, b->geom_id);
+  if (s) return s;
+  if (b->n_primaries < 0) return fail(c, GNAV_EINVAL, "negative primary count");
+  if (b->n_primaries > 0 && (!b->event_dev || !b->prim_id_dev || !b->pos_dev || !b->dir_dev || !b->energy_dev))
+    return fail(c, GNAV_EINVAL, "null primary array");
+  if (t->n_touch != (int)c->t_parent.size())
+    return fail(c, GNAV_ESTATE, "tally was created before the last geometry upload");
+  if (b->precision != 0) return fail(c, GNAV_EUNSUPPORTED, "precision mode not available");
+  if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
+    return fail(c, GNAV_EINVAL, "log buffers incomplete");
+  if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
+  int block = b->block > 0 ? b->block : 256;
+  if (block % 64 != 0 || block > 256) return fail(c, GNAV_EINVAL, "block must be a multiple of 64, <= 256");
+  long need = (b->n_primaries + block - 1) / block;
+  int grid = b->grid > 0 ? b->grid : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 8);
+  TransportLaunch L{};
+  L.G = c->G;
+  L.n = b->n_primaries;
+  L.event = b->event_dev;
+  L.prim_id = b->prim_id_dev;
+  L.pos = b->pos_dev;
+  L.dir = b->dir_dev;
+  L.energy = b->energy_dev;
+  L.event_geom = b->event_geom_dev;
+  L.geom_default = b->geom_id;
+  L.geom_tbase = c->d_geom_tbase.as<int>();
+  L.n_geoms = (int)c->geoms.size();
+  L.n_events = t->n_events;
+  L.seed = b->seed;
+  L.ecut = b->e_cut;
+  L.max_steps = b->max_steps_per_track > 0 ? b->max_steps_per_track : 1000000;
+  L.edep_t = t->edep_t.as<double>();
+  L.edep_ev = t->edep_ev.as<double>();
+  L.esc_ev = t->esc_ev.as<double>();
+  L.counters = t->counters.as<unsigned long long>();
+  L.queue = c->d_queue.as<unsigned long long>();
+  L.log = b->log_dev;
+  L.log_cap = b->log_capacity;
+  L.log_n = b->log_n_dev;
+  L.log_fate = b->log_fate_dev;
+  L.block = block;
+  L.grid = grid;
+  HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_read_tallies(gnav_ctx* c, const gnav_tally* t, double* edep_t, double* edep_ev,
+                              double* esc_ev, uint64_t* counters, void* stream) {
+  if (!c || !t) return GNAV_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, hipStreamSynchronize(st), "synchronize");
+  if (edep_t) HIP_TRY(c, hipMemcpy(edep_t, t->edep_t.p, sizeof(double) * t->n_touch, hipMemcpyDeviceToHost), "read");
+  if (edep_ev)
+    HIP_TRY(c, hipMemcpy(edep_ev, t->edep_ev.p, sizeof(double) * t->n_events, hipMemcpyDeviceToHost), "read");
+  if (esc_ev)
+    HIP_TRY(c, hipMemcpy(esc_ev, t->esc_ev.p, sizeof(double) * t->n_events, hipMemcpyDeviceToHost), "read");
+  if (counters)
+    HIP_TRY(c, hipMemcpy(counters, t->counters.p, sizeof(uint64_t) * GNAV_NCOUNTERS, hipMemcpyDeviceToHost),
+            "read");
+  return GNAV_OK;
+}
+
+}  // extern "C"

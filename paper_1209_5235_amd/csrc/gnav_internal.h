@@ -1,0 +1,50 @@
+// gnav_internal.h -- declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gnav.h"
+#include "gnav_device.h"
+
+namespace gnav {
+
+struct TransportLaunch {
+  DevGeom G;
+  long n;
+  const int* event;
+  const int* prim_id;
+  const double* pos;
+  const double* dir;
+  const double* energy;
+  const int* event_geom;
+  int geom_default;
+  const int* geom_tbase;
+  int n_geoms;
+  int n_events;
+  uint64_t seed;
+  double ecut;
+  long max_steps;
+  double* edep_t;
+  double* edep_ev;
+  double* esc_ev;
+  unsigned long long* counters;
+  unsigned long long* queue;
+  gnav_logrec* log;
+  long log_cap;
+  int* log_n;
+  int* log_fate;
+  int block;
+  int grid;
+};
+
+hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const double* pos,
+                         const double* dir, int* out, hipStream_t st);
+hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
+                       const double* dir, const int* touch, double* step, int* lim, int* next, hipStream_t st);
+hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
+                         const int* touch, double* out, hipStream_t st);
+hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);
+// Zero `words` 8-byte words with a kernel (graph-capture safe, no memset node).
+hipError_t launch_zero(void* p, size_t words, hipStream_t st);
+
+}  // namespace gnav

@@ -1,0 +1,310 @@
+"""ctypes binding of libgnav.so (argument marshalling only).
+
+Every function keeps the C name and signature of include/gnav.h; all work
+runs in the HIP library.  Device buffers are plain device pointers, e.g.
+``tensor.data_ptr()`` of a torch tensor on the ROCm device; streams are raw
+``hipStream_t`` values such as ``torch.cuda.current_stream().cuda_stream``.
+
+The ``Context`` class is a convenience layer that marshals torch tensors
+into those calls.  Importing this module fails loudly when the compiled
+library is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgnav.so")
+
+GNAV_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGEOM", -5: "ESTATE",
+          -6: "EUNSUPPORTED"}
+COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
+            "truncated", "tracks", "shortcuts", "dist_in", "dist_out", "inside", "voxel_nodes",
+            "invalid"]
+NCOUNTERS = len(COUNTERS)
+LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
+                      ("edep", np.float64), ("energy", np.float64)])
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class gnav_geometry_desc(C.Structure):
+    _fields_ = [
+        ("n_solids", C.c_int32), ("solid_type", _i32p), ("solid_par", _f64p),
+        ("n_mats", C.c_int32), ("mat_density", _f64p), ("mat_el_off", _i32p),
+        ("el_Z", _i32p), ("el_A", _f64p), ("el_wfrac", _f64p),
+        ("n_lv", C.c_int32), ("lv_solid", _i32p), ("lv_mat", _i32p), ("lv_dau_off", _i32p),
+        ("lv_dau_cnt", _i32p), ("lv_voxelize", _u8p),
+        ("n_pv", C.c_int32), ("pv_lv", _i32p), ("pv_rot", _f64p), ("pv_trans", _f64p),
+        ("world_lv", C.c_int32),
+    ]
+
+
+class gnav_batch(C.Structure):
+    _fields_ = [
+        ("n_primaries", C.c_int64), ("event_dev", C.c_void_p), ("prim_id_dev", C.c_void_p),
+        ("pos_dev", C.c_void_p), ("dir_dev", C.c_void_p), ("energy_dev", C.c_void_p),
+        ("event_geom_dev", C.c_void_p), ("geom_id", C.c_int32), ("seed", C.c_uint64),
+        ("e_cut", C.c_double), ("max_steps_per_track", C.c_int64), ("precision", C.c_int32),
+        ("block", C.c_int32), ("grid", C.c_int32), ("log_dev", C.c_void_p),
+        ("log_capacity", C.c_int64), ("log_n_dev", C.c_void_p), ("log_fate_dev", C.c_void_p),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1209_5235_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "gnav_create": ([C.c_int32, C.POINTER(P)], C.c_int32),
+        "gnav_destroy": ([P], None),
+        "gnav_last_error": ([P], C.c_char_p),
+        "gnav_upload_geometry": ([P, C.POINTER(gnav_geometry_desc), _i32p, _i32p], C.c_int32),
+        "gnav_touchables": ([P, C.c_int32, P, P, P, P], C.c_int32),
+        "gnav_touchable_offset": ([P, C.c_int32, _i32p, _i32p], C.c_int32),
+        "gnav_locate": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_compute_step": ([P, C.c_int32, C.c_int64, P, P, P, P, P, P, P], C.c_int32),
+        "gnav_compute_safety": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_tally_create": ([P, C.c_int32, C.POINTER(P)], C.c_int32),
+        "gnav_tally_reset": ([P, P, P], C.c_int32),
+        "gnav_tally_free": ([P, P], C.c_int32),
+        "gnav_transport_batch": ([P, C.POINTER(gnav_batch), P, P], C.c_int32),
+        "gnav_read_tallies": ([P, P, P, P, P, P, P], C.c_int32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+# --- thin wrappers with the C names ---------------------------------------
+gnav_create = lib.gnav_create
+gnav_destroy = lib.gnav_destroy
+gnav_last_error = lib.gnav_last_error
+gnav_upload_geometry = lib.gnav_upload_geometry
+gnav_touchables = lib.gnav_touchables
+gnav_touchable_offset = lib.gnav_touchable_offset
+gnav_locate = lib.gnav_locate
+gnav_compute_step = lib.gnav_compute_step
+gnav_compute_safety = lib.gnav_compute_safety
+gnav_tally_create = lib.gnav_tally_create
+gnav_tally_reset = lib.gnav_tally_reset
+gnav_tally_free = lib.gnav_tally_free
+gnav_transport_batch = lib.gnav_transport_batch
+gnav_read_tallies = lib.gnav_read_tallies
+
+
+class GnavError(RuntimeError):
+    pass
+
+
+# --- convenience layer over torch tensors -----------------------------------
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Context:
+    """One library context on a device; owns uploaded geometries and tallies."""
+
+    def __init__(self, device=0):
+        h = C.c_void_p()
+        st = gnav_create(int(device), C.byref(h))
+        if st != GNAV_OK:
+            raise GnavError(f"gnav_create failed: {STATUS.get(st, st)}")
+        self.h = h
+        self.device = device
+        self.geoms = []
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            gnav_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st, what):
+        if st != GNAV_OK:
+            msg = gnav_last_error(self.h).decode(errors="replace")
+            raise GnavError(f"{what}: {STATUS.get(st, st)}: {msg}")
+
+    def upload_geometry(self, desc):
+        """Upload a workloads.GeometryDesc; returns (geom_id, n_touchables)."""
+        arrs = dict(
+            solid_type=_np(desc.solid_type, np.int32), solid_par=_np(desc.solid_par, np.float64),
+            mat_density=_np(desc.mat_density, np.float64), mat_el_off=_np(desc.mat_el_off, np.int32),
+            el_Z=_np(desc.el_Z, np.int32), el_A=_np(desc.el_A, np.float64),
+            el_wfrac=_np(desc.el_wfrac, np.float64), lv_solid=_np(desc.lv_solid, np.int32),
+            lv_mat=_np(desc.lv_mat, np.int32), lv_dau_off=_np(desc.lv_dau_off, np.int32),
+            lv_dau_cnt=_np(desc.lv_dau_cnt, np.int32), lv_voxelize=_np(desc.lv_voxelize, np.uint8),
+            pv_lv=_np(desc.pv_lv, np.int32), pv_rot=_np(desc.pv_rot, np.float64),
+            pv_trans=_np(desc.pv_trans, np.float64),
+        )
+
+        def p(name, ct):
+            a = arrs[name]
+            return a.ctypes.data_as(C.POINTER(ct)) if a.size else None
+
+        d = gnav_geometry_desc(
+            desc.n_solids, p("solid_type", C.c_int32), p("solid_par", C.c_double),
+            desc.n_mats, p("mat_density", C.c_double), p("mat_el_off", C.c_int32),
+            p("el_Z", C.c_int32), p("el_A", C.c_double), p("el_wfrac", C.c_double),
+            desc.n_lv, p("lv_solid", C.c_int32), p("lv_mat", C.c_int32),
+            p("lv_dau_off", C.c_int32), p("lv_dau_cnt", C.c_int32), p("lv_voxelize", C.c_uint8),
+            desc.n_pv, p("pv_lv", C.c_int32), p("pv_rot", C.c_double), p("pv_trans", C.c_double),
+            int(desc.world_lv))
+        gid = C.c_int32()
+        nt = C.c_int32()
+        self._check(gnav_upload_geometry(self.h, C.byref(d), C.byref(gid), C.byref(nt)),
+                    "gnav_upload_geometry")
+        self.geoms.append((desc, nt.value))
+        return gid.value, nt.value
+
+    def touchables(self, geom_id):
+        n = self.geoms[geom_id][1]
+        out = [np.zeros(n, np.int32) for _ in range(4)]
+        self._check(gnav_touchables(self.h, geom_id, *[o.ctypes.data_as(C.c_void_p) for o in out]),
+                    "gnav_touchables")
+        return out
+
+    def touchable_offset(self, geom_id):
+        off, tot = C.c_int32(), C.c_int32()
+        self._check(gnav_touchable_offset(self.h, geom_id, C.byref(off), C.byref(tot)),
+                    "gnav_touchable_offset")
+        return off.value, tot.value
+
+    def locate(self, geom_id, pos, dirs=None, out=None, stream=None):
+        import torch
+        n = pos.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=pos.device)
+        self._check(gnav_locate(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(out), _stream(stream)),
+                    "gnav_locate")
+        return out
+
+    def compute_step(self, geom_id, pos, dirs, touch=None, with_next=True, stream=None):
+        import torch
+        n = pos.shape[0]
+        step = torch.empty(n, dtype=torch.float64, device=pos.device)
+        lim = torch.empty(n, dtype=torch.int32, device=pos.device)
+        nxt = torch.empty(n, dtype=torch.int32, device=pos.device) if with_next else None
+        self._check(gnav_compute_step(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
+                                      _ptr(step), _ptr(lim), _ptr(nxt), _stream(stream)),
+                    "gnav_compute_step")
+        return step, lim, nxt
+
+    def compute_safety(self, geom_id, pos, touch=None, stream=None):
+        import torch
+        n = pos.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device=pos.device)
+        self._check(gnav_compute_safety(self.h, geom_id, n, _ptr(pos), _ptr(touch), _ptr(out),
+                                        _stream(stream)), "gnav_compute_safety")
+        return out
+
+    def tally_create(self, n_events):
+        t = C.c_void_p()
+        self._check(gnav_tally_create(self.h, int(n_events), C.byref(t)), "gnav_tally_create")
+        return Tally(self, t, n_events)
+
+    def transport_batch(self, geom_id, prim, tally, seed=0, e_cut=1e-3, max_steps=0, precision=0,
+                        block=0, grid=0, log=None, event_geom=None, stream=None):
+        """prim: dict of device tensors event, prim_id, pos, dir, energy."""
+        b = gnav_batch()
+        b.n_primaries = prim["energy"].shape[0]
+        b.event_dev = prim["event"].data_ptr()
+        b.prim_id_dev = prim["prim_id"].data_ptr()
+        b.pos_dev = prim["pos"].data_ptr()
+        b.dir_dev = prim["dir"].data_ptr()
+        b.energy_dev = prim["energy"].data_ptr()
+        b.event_geom_dev = event_geom.data_ptr() if event_geom is not None else None
+        b.geom_id = geom_id
+        b.seed = seed
+        b.e_cut = e_cut
+        b.max_steps_per_track = max_steps
+        b.precision = precision
+        b.block = block
+        b.grid = grid
+        if log is not None:
+            b.log_dev = log["rec"].data_ptr()
+            b.log_capacity = log["cap"]
+            b.log_n_dev = log["n"].data_ptr()
+            b.log_fate_dev = log["fate"].data_ptr()
+        self._check(gnav_transport_batch(self.h, C.byref(b), tally.h, _stream(stream)),
+                    "gnav_transport_batch")
+
+
+class Tally:
+    def __init__(self, ctx, h, n_events):
+        self.ctx = ctx
+        self.h = h
+        self.n_events = n_events
+
+    def reset(self, stream=None):
+        self.ctx._check(gnav_tally_reset(self.ctx.h, self.h, _stream(stream)), "gnav_tally_reset")
+
+    def read(self, stream=None):
+        _, tot = self.ctx.touchable_offset(0)
+        et = np.zeros(tot)
+        ee = np.zeros(self.n_events)
+        es = np.zeros(self.n_events)
+        cn = np.zeros(NCOUNTERS, np.uint64)
+        self.ctx._check(gnav_read_tallies(self.ctx.h, self.h, et.ctypes.data_as(C.c_void_p),
+                                          ee.ctypes.data_as(C.c_void_p),
+                                          es.ctypes.data_as(C.c_void_p),
+                                          cn.ctypes.data_as(C.c_void_p), _stream(stream)),
+                        "gnav_read_tallies")
+        return dict(edep_touchable=et, edep_event=ee, escaped_event=es,
+                    counters=dict(zip(COUNTERS, (int(c) for c in cn))))
+
+    def free(self):
+        if self.h:
+            gnav_tally_free(self.ctx.h, self.h)
+            self.h = None
+
+
+def primaries_to_device(prim, device="cuda"):
+    """Copy a workloads.Primaries set into device tensors."""
+    import torch
+    return dict(
+        event=torch.from_numpy(np.ascontiguousarray(prim.event, np.int32)).to(device),
+        prim_id=torch.from_numpy(np.ascontiguousarray(prim.prim_id, np.int32)).to(device),
+        pos=torch.from_numpy(np.ascontiguousarray(prim.pos, np.float64)).to(device),
+        dir=torch.from_numpy(np.ascontiguousarray(prim.dir, np.float64)).to(device),
+        energy=torch.from_numpy(np.ascontiguousarray(prim.energy, np.float64)).to(device),
+    )
+
+
+def make_log(n_primaries, cap, device="cuda"):
+    import torch
+    return dict(rec=torch.zeros((3 * n_primaries, cap, 4), dtype=torch.float64, device=device),
+                cap=cap, n=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device),
+                fate=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device))
+
+
+def log_to_numpy(log):
+    rec = log["rec"].cpu().numpy().view(LOG_DTYPE).reshape(log["n"].shape[0], log["cap"])
+    return rec, log["n"].cpu().numpy(), log["fate"].cpu().numpy()

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Touchable ids, limiters, fates and step counts must match exactly; lengths and
+deposits within 1e-9 relative (plus 1e-12 mm absolute for zero-length steps).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+ATOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_1209_5235_amd import gnav
+    c = gnav.Context(0)
+    yield c
+    c.close()
+
+
+GEOMS = {
+    "tiny": lambda: W.geometry.tiny(),
+    "tiny_rot": lambda: W.geometry.tiny(rotated=True),
+    "zoo": lambda: W.geometry.solids_zoo(),
+    "calorimeter": lambda: W.geometry.calorimeter(),
+    "barrel": lambda: W.geometry.barrel(),
+    "barrel_v103": lambda: W.geometry.barrel_variant(103),
+}
+
+_cache = {}
+
+
+def geom(ctx, name, oracle_lib):
+    key = (id(ctx), name)
+    if key not in _cache:
+        desc = GEOMS[name]()
+        gid, nt = ctx.upload_geometry(desc)
+        _cache[key] = (desc, gid, nt, oracle_lib.Geometry(desc))
+    return _cache[key]
+
+
+def sample_points(desc, rng, n):
+    """Points spread over the world plus points on daughter faces and near centres."""
+    s = desc.lv_solid[desc.world_lv]
+    par = desc.solid_par[s]
+    half = par[:3] if desc.solid_type[s] == 0 else np.array([1600, 1600, 3000.0])
+    pts = rng.uniform(-1.02, 1.02, size=(n, 3)) * half
+    m = n // 3
+    if desc.n_pv:
+        pv = rng.integers(0, desc.n_pv, m)
+        pts[:m] = desc.pv_trans[pv] + rng.normal(0, 30, size=(m, 3))
+    return pts
+
+
+def print_case(*a):
+    print("CASE", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_locate_parity(ctx, torch_dev, oracle_lib, name):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("locate", name)
+    rng = np.random.Generator(np.random.Philox(key=1000))
+    n = 20000
+    pts = sample_points(desc, rng, n)
+    dirs = W.primaries.isotropic(rng, n)
+    ref = og.locate(pts)
+    ref_d = og.locate(pts, dirs)
+    p_t = torch.from_numpy(pts).cuda()
+    d_t = torch.from_numpy(dirs).cuda()
+    got = ctx.locate(gid, p_t).cpu().numpy()
+    got_d = ctx.locate(gid, p_t, d_t).cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert np.array_equal(got_d, ref_d)
+
+
+def surface_points(desc, og, rng, n):
+    """Points exactly on the boundary of random steps (end points of oracle steps)."""
+    pts = sample_points(desc, rng, n)
+    dirs = W.primaries.isotropic(rng, n)
+    T = og.locate(pts, dirs)
+    ok = T >= 0
+    pts, dirs, T = pts[ok], dirs[ok], T[ok]
+    step, lim, nxt = og.compute_step(pts, dirs, T)
+    end = pts + step[:, None] * dirs
+    return end, dirs, nxt
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_locate_parity_on_surfaces(ctx, torch_dev, oracle_lib, name):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("locate_surface", name)
+    rng = np.random.Generator(np.random.Philox(key=1001))
+    end, dirs, nxt = surface_points(desc, og, rng, 8000)
+    new_dirs = W.primaries.isotropic(rng, len(end))
+    for d in (dirs, new_dirs):
+        ref = og.locate(end, d)
+        got = ctx.locate(gid, torch.from_numpy(end).cuda(), torch.from_numpy(d).cuda()).cpu().numpy()
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_compute_step_parity(ctx, torch_dev, oracle_lib, name):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("step", name)
+    rng = np.random.Generator(np.random.Philox(key=1002))
+    n = 20000
+    pts = sample_points(desc, rng, n)
+    dirs = W.primaries.isotropic(rng, n)
+    # include starts on surfaces (the usual case inside transport)
+    end, d2, nxt = surface_points(desc, og, rng, 6000)
+    keep = nxt >= 0
+    pts = np.concatenate([pts, end[keep]])
+    dirs = np.concatenate([dirs, d2[keep]])
+    T = og.locate(pts, dirs)
+    ok = T >= 0
+    pts, dirs, T = pts[ok], dirs[ok], T[ok]
+    s_ref, l_ref, n_ref = og.compute_step(pts, dirs, T)
+    s, l, nx = ctx.compute_step(gid, torch.from_numpy(pts).cuda(), torch.from_numpy(dirs).cuda(),
+                                torch.from_numpy(T.astype(np.int32)).cuda())
+    s, l, nx = s.cpu().numpy(), l.cpu().numpy(), nx.cpu().numpy()
+    assert np.array_equal(l, l_ref)
+    assert np.allclose(s, s_ref, rtol=RTOL, atol=ATOL)
+    assert np.array_equal(nx, n_ref)
+    # without a given touchable the library locates first
+    s2, l2, _ = ctx.compute_step(gid, torch.from_numpy(pts).cuda(), torch.from_numpy(dirs).cuda())
+    assert np.array_equal(l2.cpu().numpy(), l_ref)
+
+
+@pytest.mark.parametrize("name", ["tiny_rot", "zoo", "calorimeter", "barrel"])
+def test_safety_is_lower_bound(ctx, torch_dev, oracle_lib, name):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("safety", name)
+    rng = np.random.Generator(np.random.Philox(key=1003))
+    pts = sample_points(desc, rng, 400)
+    T = og.locate(pts)
+    ok = T >= 0
+    pts, T = pts[ok], T[ok]
+    saf = ctx.compute_safety(gid, torch.from_numpy(pts).cuda()).cpu().numpy()
+    ref = og.compute_safety(pts, T)
+    assert np.all(saf >= 0)
+    sph = W.primaries.isotropic(rng, 128)
+    for p, t, s in zip(pts, T, saf):
+        if s <= 1e-6:
+            continue
+        q = p + s * (1 - 1e-9) * sph
+        loc = og.locate(q)
+        # every point strictly within the safety is in the same touchable
+        d = og.compute_safety(q, loc)
+        assert np.all((loc == t) | (d < 1e-6))
+    assert np.mean(saf > 0) > 0.5 * np.mean(ref > 0)
+
+
+def compare_logs(rec, n, fate, ref, cap):
+    """Number of track slots whose logs disagree, and the first disagreement."""
+    bad = []
+    nslots = len(n)
+    for s in range(nslots):
+        if n[s] != ref["log_n"][s] or fate[s] != ref["log_fate"][s]:
+            bad.append((s, "count/fate", int(n[s]), int(ref["log_n"][s]), int(fate[s]),
+                        int(ref["log_fate"][s])))
+            continue
+        k = min(int(n[s]), cap)
+        a, b = rec[s, :k], ref["log"][s, :k]
+        if not (np.array_equal(a["touchable"], b["touchable"]) and np.array_equal(a["code"], b["code"])):
+            i = int(np.nonzero((a["touchable"] != b["touchable"]) | (a["code"] != b["code"]))[0][0])
+            bad.append((s, "volume", i))
+            continue
+        for f in ("step", "edep", "energy"):
+            if not np.allclose(a[f], b[f], rtol=RTOL, atol=ATOL):
+                bad.append((s, f))
+                break
+    return bad
+
+
+def run_transport(ctx, torch, gid, prim, cap, seed=0, **kw):
+    from paper_1209_5235_amd import gnav
+    tally = ctx.tally_create(prim.n_events)
+    dev = gnav.primaries_to_device(prim, "cuda")
+    log = gnav.make_log(prim.n, cap, "cuda") if cap else None
+    ctx.transport_batch(gid, dev, tally, seed=seed, log=log, **kw)
+    torch.cuda.synchronize()
+    got = tally.read()
+    tally.free()
+    off, _ = ctx.touchable_offset(gid)
+    nt = ctx.geoms[gid][1]
+    got["edep_touchable"] = got["edep_touchable"][off:off + nt]
+    if cap:
+        got["log"], got["log_n"], got["log_fate"] = gnav.log_to_numpy(log)
+    return got
+
+
+EXACT = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
+         "truncated", "tracks"]
+
+
+@pytest.mark.parametrize("name,n,cap", [("tiny", 10000, 64), ("calorimeter", 4000, 400),
+                                        ("barrel", 3000, 512)])
+def test_transport_parity_per_track(ctx, torch_dev, oracle_lib, name, n, cap):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("transport", name, n)
+    _, prim, _ = W.WORKLOADS[name](n=n)
+    got = run_transport(ctx, torch, gid, prim, cap)
+    ref = og.transport(prim, seed=0, log_cap=cap)
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, cap)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert got["counters"]["invalid"] == 0
+    assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
+    assert np.allclose(got["escaped_event"], ref["escaped_event"], rtol=RTOL, atol=1e-15)
+    assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
+
+
+def test_transport_launch_shape_independent(ctx, torch_dev, oracle_lib):
+    """Counter-keyed random numbers: any block/grid gives the same tracks."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("launch_shape")
+    _, prim, _ = W.calorimeter(n=3000)
+    a = run_transport(ctx, torch, gid, prim, 200, block=64, grid=3)
+    b = run_transport(ctx, torch, gid, prim, 200, block=256, grid=97)
+    assert np.array_equal(a["log_n"], b["log_n"])
+    for f in ("touchable", "code", "step", "edep", "energy"):
+        assert np.array_equal(a["log"][f], b["log"][f])
+
+
+def test_transport_full_calorimeter_sampled(ctx, torch_dev, oracle_lib):
+    """The bench workload (1e6 photons) at its launch shape: energy conservation
+    per event on every track, and 1000 sampled tracks against the oracle."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("calorimeter_full")
+    _, prim, _ = W.calorimeter()
+    got = run_transport(ctx, torch, gid, prim, 0)
+    assert got["counters"]["truncated"] == 0 and got["counters"]["invalid"] == 0
+    tot = got["edep_event"] + got["escaped_event"]
+    assert np.allclose(tot, prim.energy, rtol=1e-12, atol=0)
+    rng = np.random.Generator(np.random.Philox(key=5))
+    idx = np.sort(rng.choice(prim.n, 1000, replace=False))
+    sub = prim.subset(idx)
+    ref = og.transport(sub, seed=0, log_cap=0, n_events=prim.n_events)
+    assert np.allclose(got["edep_event"][idx], ref["edep_event"][idx], rtol=RTOL, atol=1e-15)
+    assert np.allclose(got["escaped_event"][idx], ref["escaped_event"][idx], rtol=RTOL, atol=1e-15)
+
+
+def test_invalid_primaries_are_skipped(ctx, torch_dev, oracle_lib):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "tiny", oracle_lib)
+    print_case("invalid")
+    _, prim, _ = W.tiny(n=64)
+    prim.energy[3] = np.nan
+    prim.event[5] = 10_000  # outside the tally's events
+    prim.energy[7] = -1.0
+    got = run_transport(ctx, torch, gid, prim, 0)
+    assert got["counters"]["invalid"] == 3
+    assert got["counters"]["tracks"] + 3 >= 64
