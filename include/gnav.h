@@ -185,6 +185,18 @@ gnav_status gnav_tally_create(gnav_ctx* ctx, int32_t n_events, gnav_tally** out)
 gnav_status gnav_tally_reset(gnav_ctx* ctx, gnav_tally* tally, void* stream);
 gnav_status gnav_tally_free(gnav_ctx* ctx, gnav_tally* tally);
 
+/* One recorded crossing: a ComputeStep limited by a daughter whose start
+ * voxel node holds 2 or more candidates, the daughter being candidate number
+ * `label` (< 64) of that node.  x = point in the mother frame divided by the
+ * mother's voxel-grid half size (relative to the grid centre), v = direction
+ * in the mother frame, cls = the mother's ordering class (32 bytes). */
+typedef struct gnav_crossing {
+  int32_t cls;
+  float x[3];
+  float v[3];
+  int32_t label;
+} gnav_crossing;
+
 /* One batch of primaries; every *_dev array is device memory of n_primaries
  * entries (pos_dev and dir_dev [n][3]) owned by the caller. */
 typedef struct {
@@ -200,8 +212,14 @@ typedef struct {
   double e_cut;               /* MeV: photons below it deposit locally and stop */
   int64_t max_steps_per_track;/* <= 0: 1e6 */
   int32_t precision;          /* 0: FP64 distances */
-  int32_t block;              /* threads per block, 0 = library default */
+  int32_t block;              /* threads per block (multiple of 64, <= 256), 0 = default */
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
+  int32_t count_work;         /* 1: also count navigation work (GNAV_C_DIST_IN..VOXEL_NODES) */
+  int32_t order;              /* start-node candidate order: 0 slot order, 1 smallest lower bound
+                                 first, 2 learned (network set with gnav_set_mlp); same results */
+  struct gnav_crossing* record_dev; /* optional recorder of daughter-limited steps (training data) */
+  int64_t record_capacity;
+  uint64_t* record_count_dev; /* crossings seen (may exceed the capacity; extra ones dropped) */
   gnav_logrec* log_dev;       /* optional per-track log: 3 slots per primary (primary and */
   int64_t log_capacity;       /*   its two annihilation photons), log_capacity records each */
   int32_t* log_n_dev;         /*   [3 n] records written per slot (may exceed the capacity) */
@@ -223,6 +241,49 @@ gnav_status gnav_transport_batch(gnav_ctx* ctx, const gnav_batch* batch, gnav_ta
 gnav_status gnav_read_tallies(gnav_ctx* ctx, const gnav_tally* tally, double* edep_touchable,
                               double* edep_event, double* escaped_event, uint64_t* counters,
                               void* stream);
+
+/* Repeated batches as one HIP graph: {zero the tally, reset the work queue,
+ * transport} captured once for a batch description (same device buffers,
+ * same tally) and replayed with gnav_graph_launch.  The graph holds only
+ * kernel nodes (no memset nodes).  The batch's buffers and the tally must
+ * outlive the graph; the call synchronises `stream` while capturing. */
+typedef struct gnav_graph gnav_graph;
+gnav_status gnav_graph_create(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally, void* stream,
+                              gnav_graph** out);
+gnav_status gnav_graph_launch(gnav_ctx* ctx, gnav_graph* graph, void* stream);
+gnav_status gnav_graph_free(gnav_ctx* ctx, gnav_graph* graph);
+
+/* Candidate-ordering MLP (learned part).  Inputs per sample: 6 floats (point
+ * in the mother frame divided by the mother's voxel-grid half size, then the
+ * direction) and a mother class id in [0, n_class); two hidden layers of 128
+ * ReLU units; 64 logits, one per candidate position of the start voxel node.
+ * Parameters are float32 in the order w1x [128][6], w1m [n_class][128],
+ * b1 [128], w2 [128][128], b2 [128], w3 [64][128], b3 [64]; matrix products
+ * run on bf16 MFMA with float32 accumulation.  Batches are multiples of 16
+ * up to max_batch.  x_dev [B][6] float, cls_dev / label_dev [B] int32. */
+typedef struct gnav_mlp gnav_mlp;
+gnav_status gnav_mlp_create(gnav_ctx* ctx, int32_t n_class, int32_t max_batch, const float* params_host,
+                            gnav_mlp** out);
+int64_t gnav_mlp_n_params(const gnav_mlp* mlp);
+/* Softmax cross-entropy gradient of the mean loss over the batch; optional
+ * copies of the gradient (float [n_params]) and of the loss (one float). */
+gnav_status gnav_mlp_grad(gnav_ctx* ctx, gnav_mlp* mlp, int64_t batch, const float* x_dev,
+                          const int32_t* cls_dev, const int32_t* label_dev, float* grad_dev,
+                          float* loss_dev, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the last gradient. */
+gnav_status gnav_mlp_adam(gnav_ctx* ctx, gnav_mlp* mlp, float lr, void* stream);
+/* Logits [B][64] (float). */
+gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* mlp, int64_t batch, const float* x_dev,
+                             const int32_t* cls_dev, float* logits_dev, void* stream);
+/* Host copy of the float parameters (synchronous). */
+gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* mlp, float* params_host);
+gnav_status gnav_mlp_free(gnav_ctx* ctx, gnav_mlp* mlp);
+
+/* Number of ordering classes (voxelised mothers) of a geometry. */
+gnav_status gnav_ordering_classes(gnav_ctx* ctx, int32_t geom_id, int32_t* n_class);
+/* Use `mlp` (NULL to clear) for order 2 on geometry geom_id; its class count
+ * must equal the geometry's.  The network must outlive its use. */
+gnav_status gnav_set_mlp(gnav_ctx* ctx, int32_t geom_id, gnav_mlp* mlp);
 
 /* Total touchables over all resident geometries, and the offset of one
  * geometry's touchables in that concatenation. */

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgnav.so")
 
-SOURCES = ["gnav_host.cpp", "gnav_kernels.hip"]
+SOURCES = ["gnav_host.cpp", "gnav_kernels.hip", "gnav_mlp.hip"]
 
 # -ffp-contract=off: no fused multiply-add contraction, so each distance is
 # rounded operation by operation.  The packed-fp32 feature is disabled for all
@@ -34,26 +34,28 @@ def hipcc():
     return h
 
 
-def build(verbose=False):
+def build(verbose=False, defines=(), out=None):
+    """Compile the sources; `defines` adds -D flags, `out` overrides the library path."""
     objs = []
     tmpdir = os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(tmpdir, src + ".o")
         lang = ["-x", "hip"]
-        cmd = [hipcc()] + lang + HIPFLAGS + ["-I", INCLUDE, "-I", CSRC, "-c",
+        cmd = [hipcc()] + lang + HIPFLAGS + [f"-D{d}" for d in defines] + ["-I", INCLUDE, "-I", CSRC, "-c",
                                              os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -40,37 +40,54 @@ enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4 };
 constexpr int kInfoInner = 1 << 4;
 constexpr int kInfoPhi = 1 << 5;
 
-// Radial-solid parameter slots (16 doubles per solid).
-enum : int { R_AO = 0, R_BO, R_CO, R_AI, R_BI, R_CI, R_DZ, R_NS0, R_NS1, R_NE0, R_NE1, kSolidStride = 16 };
+// Radial-solid parameter slots (12 doubles per solid).
+enum : int { R_AO = 0, R_BO, R_CO, R_AI, R_BI, R_CI, R_DZ, R_NS0, R_NS1, R_NE0, R_NE1, kSolidPar = 12 };
 
-struct VoxHdr {
-  double lo[3];
-  double w[3];
-  double inv_w[3];
-  int n[3];
+// Touchable record: everything a step needs about the current volume except
+// its transform, in one 16-byte load.
+struct TRec {
+  int lv;          // logical volume (global)
+  int parent;      // parent touchable, -1 for a world
+  int child_base;  // touchable of daughter slot 0
+  int slot_kind;   // slot in the parent LV (low 16 bits) | transform kind << 16
+};
+
+// Logical-volume record: solid, material, daughters and voxel grid together,
+// so a mother's exit distance, safety and daughter search start from one
+// record (256 bytes).
+struct LRec {
+  int info;        // solid type | kInfoInner | kInfoPhi
+  int mat;
+  int dau_base;    // first placement
+  int dau_cnt;
+  int vox;         // 1: voxel grid present
+  int n[3];        // grid counts
   int node_base;
+  int lclass;      // candidate-ordering class of a voxelised mother (-1: none)
+  int pad_i[6];
+  double par[kSolidPar];  // solid parameters
+  double vlo[3], vinv[3], vw[3];
+  double pad_d[3];
+};
+
+// Placement record: mother->local transform (M = R^T row major, then t),
+// the placed solid's bounding box in the mother frame, child LV and whether
+// M is the identity (176 bytes).
+struct PRec {
+  double m[12];
+  double box_lo[3], box_hi[3];  // placed solid's bounding box in the mother frame
+  int lv;
+  int kind;
+  int pad[6];
 };
 
 // All device tables, by value in kernel arguments.  Indices are global over
 // every resident geometry.
 struct DevGeom {
-  const int* t_parent;      // [T] parent touchable, -1 for a world
-  const int* t_lv;          // [T] logical volume
-  const int* t_child_base;  // [T] touchable of daughter slot 0
-  const int* t_slot;        // [T] slot in the parent LV
-  const double* t_xf;       // [T][12] world->local: M (row major) then t; local = M (g - t)
-  const uint8_t* t_kind;    // [T] 0: M is the identity
-  const int* lv_solid;      // [LV]
-  const int* lv_mat;        // [LV]
-  const int* lv_dau_base;   // [LV] first placement
-  const int* lv_dau_cnt;    // [LV]
-  const int* lv_vox;        // [LV] voxel header or -1
-  const double* pv_xf;      // [PV][12] mother->local: M = R^T, t
-  const uint8_t* pv_kind;   // [PV] 0: identity rotation
-  const int* pv_lv;         // [PV]
-  const double* sd_par;     // [S][16]
-  const int* sd_info;       // [S]
-  const VoxHdr* vox_hdr;
+  const TRec* t;            // [T]
+  const double* t_xf;       // [T][12] world->local: M (row major) then t
+  const LRec* lv;           // [LV]
+  const PRec* pv;           // [PV]
   const int2* vox_node;     // {candidate offset, count}
   const uint16_t* vox_cand; // daughter slots, ascending within a node
   const double* xs;         // [mat][3][257] attenuation, 1/mm
@@ -304,7 +321,7 @@ __device__ __forceinline__ bool rad_ok_except(const double* q, int info, V3 p, V
 
 // Entry distance, surface by surface: a crossing through one face counts if
 // every other component holds at the crossing point.
-__device__ __noinline__ double rad_dist_in(const double* q, int info, V3 p, V3 v) {
+__device__ __forceinline__ double rad_dist_in(const double* q, int info, V3 p, V3 v) {
   RadComps k = rad_comps(q, info, p);
   if (rad_dmax(k) < -kHalfTol) return 0.0;
   double rho = sqrt(p.x * p.x + p.y * p.y);
@@ -353,7 +370,7 @@ __device__ __noinline__ double rad_dist_in(const double* q, int info, V3 p, V3 v
   return best < kHalfTol ? 0.0 : best;
 }
 
-__device__ __noinline__ double rad_dist_out(const double* q, int info, V3 p, V3 v) {
+__device__ __forceinline__ double rad_dist_out(const double* q, int info, V3 p, V3 v) {
   RadComps k = rad_comps(q, info, p);
   double rho = sqrt(p.x * p.x + p.y * p.y);
   double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
@@ -384,9 +401,7 @@ __device__ __noinline__ double rad_dist_out(const double* q, int info, V3 p, V3 
 // Dispatch over solid families ("fork" by type code)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int solid_inside(const DevGeom& G, int s, V3 p, bool has_v, V3 v) {
-  int info = G.sd_info[s];
-  const double* q = G.sd_par + (size_t)s * kSolidStride;
+__device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, bool has_v, V3 v) {
   switch (info & 15) {
     case kBox: return box_inside(q, p, has_v, v);
     case kOrb: return orb_inside(q[0], p, has_v, v);
@@ -394,9 +409,7 @@ __device__ __forceinline__ int solid_inside(const DevGeom& G, int s, V3 p, bool 
   }
 }
 
-__device__ __forceinline__ double solid_d(const DevGeom& G, int s, V3 p) {
-  int info = G.sd_info[s];
-  const double* q = G.sd_par + (size_t)s * kSolidStride;
+__device__ __forceinline__ double solid_d(int info, const double* q, V3 p) {
   switch (info & 15) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
@@ -404,9 +417,7 @@ __device__ __forceinline__ double solid_d(const DevGeom& G, int s, V3 p) {
   }
 }
 
-__device__ __forceinline__ double solid_dist_in(const DevGeom& G, int s, V3 p, V3 v) {
-  int info = G.sd_info[s];
-  const double* q = G.sd_par + (size_t)s * kSolidStride;
+__device__ __forceinline__ double solid_dist_in(int info, const double* q, V3 p, V3 v) {
   switch (info & 15) {
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
@@ -414,9 +425,7 @@ __device__ __forceinline__ double solid_dist_in(const DevGeom& G, int s, V3 p, V
   }
 }
 
-__device__ __forceinline__ double solid_dist_out(const DevGeom& G, int s, V3 p, V3 v) {
-  int info = G.sd_info[s];
-  const double* q = G.sd_par + (size_t)s * kSolidStride;
+__device__ __forceinline__ double solid_dist_out(int info, const double* q, V3 p, V3 v) {
   switch (info & 15) {
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
@@ -435,147 +444,251 @@ __device__ __forceinline__ int vox_axis_index(double p, double lo, double inv_w,
   return (int)x;
 }
 
-// Per-evaluation counters (optional, for the roofline's work accounting).
+// Work counters for the roofline accounting; compiled out when not wanted.
+template <bool ON>
 struct NavCount {
-  unsigned dist_in, dist_out, inside, nodes;
+  unsigned dist_in = 0, dist_out = 0, inside = 0, nodes = 0;
+  __device__ __forceinline__ void in() { if (ON) dist_in++; }
+  __device__ __forceinline__ void out() { if (ON) dist_out++; }
+  __device__ __forceinline__ void ins() { if (ON) inside++; }
+  __device__ __forceinline__ void node() { if (ON) nodes++; }
 };
 
-// Daughters of touchable-LV `lv` holding (pl, vl), first match in slot order.
-__device__ __forceinline__ int find_daughter(const DevGeom& G, int lv, V3 pl, bool has_v, V3 vl,
-                                             int blocked, NavCount& nc) {
-  int cnt = G.lv_dau_cnt[lv];
+template <bool C>
+__device__ __forceinline__ bool daughter_holds(const DevGeom& G, int pv, V3 pl, bool has_v, V3 vl,
+                                               NavCount<C>& nc) {
+  const PRec& P = G.pv[pv];
+  int kind = P.kind;
+  V3 pd = xf_point(P.m, kind, pl);
+  V3 vd = xf_dir(P.m, kind, vl);
+  const LRec& L = G.lv[P.lv];
+  nc.ins();
+  return solid_inside(L.info, L.par, pd, has_v, vd) == kIn;
+}
+
+// Daughter slot of mother record L holding (pl, vl): first match in slot order.
+template <bool C>
+__device__ __forceinline__ int find_daughter(const DevGeom& G, const LRec& L, V3 pl, bool has_v, V3 vl,
+                                             int blocked, NavCount<C>& nc) {
+  int cnt = L.dau_cnt;
   if (cnt == 0) return -1;
-  int base = G.lv_dau_base[lv];
-  int vh = G.lv_vox[lv];
-  if (vh < 0) {
+  int base = L.dau_base;
+  if (!L.vox) {
     for (int k = 0; k < cnt; k++) {
       if (k == blocked) continue;
-      int pv = base + k;
-      int kind = G.pv_kind[pv];
-      const double* m = G.pv_xf + (size_t)pv * 12;
-      V3 pd = xf_point(m, kind, pl);
-      V3 vd = xf_dir(m, kind, vl);
-      nc.inside++;
-      if (solid_inside(G, G.lv_solid[G.pv_lv[pv]], pd, has_v, vd) == kIn) return k;
+      if (daughter_holds(G, base + k, pl, has_v, vl, nc)) return k;
     }
     return -1;
   }
-  const VoxHdr& h = G.vox_hdr[vh];
-  int ix = vox_axis_index(pl.x, h.lo[0], h.inv_w[0], h.n[0]);
-  int iy = vox_axis_index(pl.y, h.lo[1], h.inv_w[1], h.n[1]);
-  int iz = vox_axis_index(pl.z, h.lo[2], h.inv_w[2], h.n[2]);
-  int2 nd = G.vox_node[h.node_base + (ix * h.n[1] + iy) * h.n[2] + iz];
+  int ix = vox_axis_index(pl.x, L.vlo[0], L.vinv[0], L.n[0]);
+  int iy = vox_axis_index(pl.y, L.vlo[1], L.vinv[1], L.n[1]);
+  int iz = vox_axis_index(pl.z, L.vlo[2], L.vinv[2], L.n[2]);
+  int2 nd = G.vox_node[L.node_base + (ix * L.n[1] + iy) * L.n[2] + iz];
   for (int c = 0; c < nd.y; c++) {
     int k = G.vox_cand[nd.x + c];
     if (k == blocked) continue;
-    int pv = base + k;
-    int kind = G.pv_kind[pv];
-    const double* m = G.pv_xf + (size_t)pv * 12;
-    V3 pd = xf_point(m, kind, pl);
-    V3 vd = xf_dir(m, kind, vl);
-    nc.inside++;
-    if (solid_inside(G, G.lv_solid[G.pv_lv[pv]], pd, has_v, vd) == kIn) return k;
+    if (daughter_holds(G, base + k, pl, has_v, vl, nc)) return k;
   }
   return -1;
 }
 
-// Descend from touchable T (holding the point) to the deepest holder.
-__device__ __forceinline__ int descend(const DevGeom& G, int T, V3 pg, bool has_v, V3 vg, int blocked,
-                                       NavCount& nc) {
-  const double* m = G.t_xf + (size_t)T * 12;
-  int kind = G.t_kind[T];
-  V3 pl = xf_point(m, kind, pg);
-  V3 vl = xf_dir(m, kind, vg);
+__device__ __forceinline__ int trec_kind(const TRec& r) { return r.slot_kind >> 16; }
+__device__ __forceinline__ int trec_slot(const TRec& r) { return r.slot_kind & 0xFFFF; }
+
+// Descend from touchable T (holding the point, given in T's frame).  Also
+// reports the LV of the touchable found and its transform kind, packed as
+// (lv << 1) | kind.
+template <bool C>
+__device__ __forceinline__ int descend_local(const DevGeom& G, int T, V3 pl, bool has_v, V3 vl, int blocked,
+                                             NavCount<C>& nc, int* lv_out = nullptr) {
   for (;;) {
-    int lv = G.t_lv[T];
-    int k = find_daughter(G, lv, pl, has_v, vl, blocked, nc);
-    if (k < 0) return T;
-    int pv = G.lv_dau_base[lv] + k;
-    int pk = G.pv_kind[pv];
-    const double* mm = G.pv_xf + (size_t)pv * 12;
-    pl = xf_point(mm, pk, pl);
-    vl = xf_dir(mm, pk, vl);
-    T = G.t_child_base[T] + k;
+    TRec tr = G.t[T];
+    const LRec& L = G.lv[tr.lv];
+    int k = find_daughter(G, L, pl, has_v, vl, blocked, nc);
+    if (k < 0) {
+      if (lv_out) *lv_out = (tr.lv << 1) | trec_kind(tr);
+      return T;
+    }
+    const PRec& P = G.pv[L.dau_base + k];
+    int pk = P.kind;
+    pl = xf_point(P.m, pk, pl);
+    vl = xf_dir(P.m, pk, vl);
+    T = tr.child_base + k;
     blocked = -1;
   }
 }
 
-// LocateGlobalPoint from the world touchable W.
-__device__ __forceinline__ int locate(const DevGeom& G, int W, V3 pg, bool has_v, V3 vg, NavCount& nc) {
-  nc.inside++;
-  if (solid_inside(G, G.lv_solid[G.t_lv[W]], pg, has_v, vg) == kOut) return -1;
-  return descend(G, W, pg, has_v, vg, -1, nc);
-}
-
-__device__ __forceinline__ void touchable_frame(const DevGeom& G, int T, V3 pg, V3 vg, V3& pl, V3& vl) {
+__device__ __forceinline__ void touchable_frame(const DevGeom& G, int T, int kind, V3 pg, V3 vg, V3& pl,
+                                                V3& vl) {
   const double* m = G.t_xf + (size_t)T * 12;
-  int kind = G.t_kind[T];
   pl = xf_point(m, kind, pg);
   vl = xf_dir(m, kind, vg);
 }
 
+template <bool C>
+__device__ __forceinline__ int descend(const DevGeom& G, int T, V3 pg, bool has_v, V3 vg, int blocked,
+                                       NavCount<C>& nc) {
+  V3 pl, vl;
+  touchable_frame(G, T, trec_kind(G.t[T]), pg, vg, pl, vl);
+  return descend_local(G, T, pl, has_v, vl, blocked, nc);
+}
+
+// LocateGlobalPoint from the world touchable W.
+template <bool C>
+__device__ __forceinline__ int locate(const DevGeom& G, int W, V3 pg, bool has_v, V3 vg, NavCount<C>& nc) {
+  const LRec& L = G.lv[G.t[W].lv];
+  nc.ins();
+  if (solid_inside(L.info, L.par, pg, has_v, vg) == kOut) return -1;
+  return descend_local(G, W, pg, has_v, vg, -1, nc);
+}
+
 // Relocation after a geometry step: enter daughter `lim`, or climb out of
 // the volume(s) left and search the parent with the left volume excluded.
-__device__ __forceinline__ int relocate(const DevGeom& G, int T, V3 pg, V3 vg, int lim, NavCount& nc) {
-  if (lim >= 0) return descend(G, G.t_child_base[T] + lim, pg, true, vg, -1, nc);
-  int left = T;
-  int P = G.t_parent[T];
+template <bool C>
+__device__ __forceinline__ int relocate(const DevGeom& G, int T, const TRec& tr, V3 pg, V3 vg, int lim,
+                                        NavCount<C>& nc) {
+  if (lim >= 0) return descend(G, tr.child_base + lim, pg, true, vg, -1, nc);
+  int left_slot = trec_slot(tr);
+  int P = tr.parent;
   while (P >= 0) {
+    TRec pr = G.t[P];
     V3 pl, vl;
-    touchable_frame(G, P, pg, vg, pl, vl);
-    nc.inside++;
-    if (solid_inside(G, G.lv_solid[G.t_lv[P]], pl, true, vl) != kOut) break;
-    left = P;
-    P = G.t_parent[P];
+    touchable_frame(G, P, trec_kind(pr), pg, vg, pl, vl);
+    const LRec& L = G.lv[pr.lv];
+    nc.ins();
+    if (solid_inside(L.info, L.par, pl, true, vl) != kOut)
+      return descend_local(G, P, pl, true, vl, left_slot, nc);
+    left_slot = trec_slot(pr);
+    P = pr.parent;
   }
-  if (P < 0) return -1;
-  return descend(G, P, pg, true, vg, G.t_slot[left], nc);
+  return -1;
 }
 
-// Entry distance of daughter slot k of mother LV (base = first placement).
-__device__ __forceinline__ double daughter_dist_in(const DevGeom& G, int base, int k, V3 pl, V3 vl) {
-  int pv = base + k;
-  int kind = G.pv_kind[pv];
-  const double* m = G.pv_xf + (size_t)pv * 12;
-  V3 pd = xf_point(m, kind, pl);
-  V3 vd = xf_dir(m, kind, vl);
-  return solid_dist_in(G, G.lv_solid[G.pv_lv[pv]], pd, vd);
+// One navigation fix-up shared by every way a track reaches a new position:
+// starting (locate from the world touchable T), entering daughter `lim` of
+// T, or leaving T (climb while outside the parent, then search it with the
+// left volume excluded).  Returns the new touchable (-1: outside the world)
+// and (its LV << 1) | transform kind.
+enum : int { kNavStart = 1, kNavEnter = 2, kNavExit = 3 };
+
+template <bool C>
+__device__ __forceinline__ int navigate(const DevGeom& G, int mode, int T, int lim, V3 x, V3 v, int& lvk_out,
+                                        NavCount<C>& nc) {
+  int cur = -1, blocked = -1;
+  V3 pl = x, vl = v;
+  if (mode == kNavStart) {
+    const LRec& L = G.lv[G.t[T].lv];
+    nc.ins();
+    if (solid_inside(L.info, L.par, x, true, v) != kOut) cur = T;  // world frame = global frame
+  } else if (mode == kNavEnter) {
+    cur = G.t[T].child_base + lim;
+    touchable_frame(G, cur, trec_kind(G.t[cur]), x, v, pl, vl);
+  } else {
+    TRec tr = G.t[T];
+    int left_slot = trec_slot(tr);
+    int P = tr.parent;
+    while (P >= 0) {
+      TRec pr = G.t[P];
+      touchable_frame(G, P, trec_kind(pr), x, v, pl, vl);
+      const LRec& L = G.lv[pr.lv];
+      nc.ins();
+      if (solid_inside(L.info, L.par, pl, true, vl) != kOut) {
+        cur = P;
+        blocked = left_slot;
+        break;
+      }
+      left_slot = trec_slot(pr);
+      P = pr.parent;
+    }
+  }
+  if (cur < 0) return -1;
+  return descend_local(G, cur, pl, true, vl, blocked, nc, &lvk_out);
 }
 
-__device__ __forceinline__ double daughter_safety_in(const DevGeom& G, int base, int k, V3 pl) {
-  int pv = base + k;
-  int kind = G.pv_kind[pv];
-  const double* m = G.pv_xf + (size_t)pv * 12;
-  V3 pd = xf_point(m, kind, pl);
-  double d = solid_d(G, G.lv_solid[G.pv_lv[pv]], pd);
+// Entry distance and safety of daughter placement pv, mother frame (pl, vl).
+__device__ __forceinline__ double daughter_dist_in(const DevGeom& G, int pv, V3 pl, V3 vl) {
+  const PRec& P = G.pv[pv];
+  int kind = P.kind;
+  V3 pd = xf_point(P.m, kind, pl);
+  V3 vd = xf_dir(P.m, kind, vl);
+  const LRec& L = G.lv[P.lv];
+  return solid_dist_in(L.info, L.par, pd, vd);
+}
+
+__device__ __forceinline__ double daughter_safety_in(const DevGeom& G, int pv, V3 pl) {
+  const PRec& P = G.pv[pv];
+  V3 pd = xf_point(P.m, P.kind, pl);
+  const LRec& L = G.lv[P.lv];
+  double d = solid_d(L.info, L.par, pd);
   return d > 0 ? d : 0.0;
 }
 
-// ComputeStep in the mother frame (pl, vl) of a touchable with LV `lv`:
+// Lower bound on the entry distance of placement pv from (pl, vl) in the
+// mother frame: the larger of the ray's entry into the placed bounding box
+// (+inf on a miss) and the daughter's isotropic safety.  `saf` receives the
+// safety alone.
+__device__ __forceinline__ double daughter_lower_bound(const DevGeom& G, int pv, V3 pl, V3 vl, double& saf) {
+  const PRec& P = G.pv[pv];
+  const double pc[3] = {pl.x, pl.y, pl.z};
+  const double vc[3] = {vl.x, vl.y, vl.z};
+  double te = 0.0, tx = kInf;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    double lo = P.box_lo[a], hi = P.box_hi[a];
+    if (vc[a] == 0.0) {
+      if (pc[a] < lo || pc[a] > hi) tx = -1.0;
+      continue;
+    }
+    double t1 = (lo - pc[a]) / vc[a], t2 = (hi - pc[a]) / vc[a];
+    te = dmax(te, dmin(t1, t2));
+    tx = dmin(tx, dmax(t1, t2));
+  }
+  V3 pd = xf_point(P.m, P.kind, pl);
+  const LRec& L = G.lv[P.lv];
+  double d = solid_d(L.info, L.par, pd);
+  saf = d > 0 ? d : 0.0;
+  if (te > tx) return kInf;
+  return dmax(te, saf);
+}
+
+// Candidate orders for the start node of a step walk.
+enum : int { kOrderPlain = 0, kOrderBound = 1, kOrderLearned = 2 };
+
+// ComputeStep in the mother frame (pl, vl) of a touchable with LV record L:
 // the mother's exit distance against daughter entry distances, collected by
 // walking the voxel nodes along the ray until the best distance lies strictly
 // inside the current node.  The mother wins ties, then the lowest slot.
-// Also returns the voxel-limited safety at the start point.
-__device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, V3 vl, int& lim,
-                                               double& safety, NavCount& nc) {
-  int ms = G.lv_solid[lv];
-  double s = solid_dist_out(G, ms, pl, vl);
-  double md = solid_d(G, ms, pl);
+// Also returns the voxel-limited safety at the start point and the start
+// node {candidate offset, count} (count 0 without voxels).
+//
+// ORDER changes only the order in which the start node's candidates are
+// examined, never the result: the bound order evaluates the candidate with
+// the smallest lower bound first, the learned order the candidate position
+// `pred`; the others are then evaluated only when their lower bound (with a
+// rounding margin) does not exceed the best distance so far, so a skipped
+// candidate can neither beat nor tie it.
+template <bool C, int ORDER = kOrderPlain>
+__device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, V3 pl, V3 vl, int& lim,
+                                               double& safety, NavCount<C>& nc, int pred = -1,
+                                               int2* start_node = nullptr) {
+  const int info = L.info;
+  double s = solid_dist_out(info, L.par, pl, vl);
+  double md = solid_d(info, L.par, pl);
   double saf = md < 0 ? -md : 0.0;
-  nc.dist_out++;
+  nc.out();
   lim = kLimMother;
-  int cnt = G.lv_dau_cnt[lv];
+  if (start_node) *start_node = int2{0, 0};
+  int cnt = L.dau_cnt;
   if (cnt == 0) {
     safety = saf;
     return s;
   }
-  int base = G.lv_dau_base[lv];
-  int vh = G.lv_vox[lv];
-  if (vh < 0) {
+  int base = L.dau_base;
+  if (!L.vox) {
     for (int k = 0; k < cnt; k++) {
-      double t = daughter_dist_in(G, base, k, pl, vl);
-      saf = dmin(saf, daughter_safety_in(G, base, k, pl));
-      nc.dist_in++;
+      double t = daughter_dist_in(G, base + k, pl, vl);
+      saf = dmin(saf, daughter_safety_in(G, base + k, pl));
+      nc.in();
       if (t < s) {
         s = t;
         lim = k;
@@ -584,32 +697,73 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, 
     safety = saf;
     return s;
   }
-  const VoxHdr& h = G.vox_hdr[vh];
-  int idx[3] = {vox_axis_index(pl.x, h.lo[0], h.inv_w[0], h.n[0]),
-                vox_axis_index(pl.y, h.lo[1], h.inv_w[1], h.n[1]),
-                vox_axis_index(pl.z, h.lo[2], h.inv_w[2], h.n[2])};
   const double pc[3] = {pl.x, pl.y, pl.z};
   const double vc[3] = {vl.x, vl.y, vl.z};
+  int idx[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) idx[a] = vox_axis_index(pc[a], L.vlo[a], L.vinv[a], L.n[a]);
   // safety also limited by the start node's faces (not beyond the grid edge)
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    double lo = h.lo[a] + idx[a] * h.w[a];
-    double hi = h.lo[a] + (idx[a] + 1) * h.w[a];
+    double lo = L.vlo[a] + idx[a] * L.vw[a];
+    double hi = L.vlo[a] + (idx[a] + 1) * L.vw[a];
     if (idx[a] > 0) saf = dmin(saf, dmax(pc[a] - lo, 0.0));
-    if (idx[a] < h.n[a] - 1) saf = dmin(saf, dmax(hi - pc[a], 0.0));
+    if (idx[a] < L.n[a] - 1) saf = dmin(saf, dmax(hi - pc[a], 0.0));
   }
   bool first = true;
   for (;;) {
-    int2 nd = G.vox_node[h.node_base + (idx[0] * h.n[1] + idx[1]) * h.n[2] + idx[2]];
-    nc.nodes++;
-    for (int c = 0; c < nd.y; c++) {
-      int k = G.vox_cand[nd.x + c];
-      double t = daughter_dist_in(G, base, k, pl, vl);
-      nc.dist_in++;
-      if (first) saf = dmin(saf, daughter_safety_in(G, base, k, pl));
-      if (t < s || (t == s && lim >= 0 && k < lim)) {
-        s = t;
-        lim = k;
+    int2 nd = G.vox_node[L.node_base + (idx[0] * L.n[1] + idx[1]) * L.n[2] + idx[2]];
+    nc.node();
+    if (first && start_node) *start_node = nd;
+    if (ORDER != kOrderPlain && first && nd.y >= 2) {
+      int lead = -1;
+      if (ORDER == kOrderLearned && pred >= 0 && pred < nd.y) lead = pred;
+      if (lead < 0) {
+        double lbmin = kInf;
+        for (int c = 0; c < nd.y; c++) {
+          double sf;
+          double lb = daughter_lower_bound(G, base + G.vox_cand[nd.x + c], pl, vl, sf);
+          if (lb < lbmin) {
+            lbmin = lb;
+            lead = c;
+          }
+        }
+        if (lead < 0) lead = 0;
+      }
+      {
+        int k = G.vox_cand[nd.x + lead];
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        saf = dmin(saf, daughter_safety_in(G, base + k, pl));
+        nc.in();
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+      for (int c = 0; c < nd.y; c++) {
+        if (c == lead) continue;
+        int k = G.vox_cand[nd.x + c];
+        double sf;
+        double lb = daughter_lower_bound(G, base + k, pl, vl, sf);
+        saf = dmin(saf, sf);
+        if (lb * (1.0 - 1e-12) - kTol > s) continue;
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        nc.in();
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+    } else {
+      for (int c = 0; c < nd.y; c++) {
+        int k = G.vox_cand[nd.x + c];
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        nc.in();
+        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl));
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
       }
     }
     first = false;
@@ -619,7 +773,7 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, 
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       if (vc[a] == 0.0) continue;
-      double plane = h.lo[a] + (idx[a] + (vc[a] > 0 ? 1 : 0)) * h.w[a];
+      double plane = L.vlo[a] + (idx[a] + (vc[a] > 0 ? 1 : 0)) * L.vw[a];
       double ta = (plane - pc[a]) / vc[a];
       if (ta < tx) {
         tx = ta;
@@ -628,7 +782,7 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, 
     }
     if (ax < 0 || s < tx) break;
     idx[ax] += vc[ax] > 0 ? 1 : -1;
-    if (idx[ax] < 0 || idx[ax] >= h.n[ax]) break;
+    if (idx[ax] < 0 || idx[ax] >= L.n[ax]) break;
   }
   safety = saf;
   return s;
@@ -639,11 +793,10 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, int lv, V3 pl, 
 // ---------------------------------------------------------------------------
 
 struct Philox {
-  uint32_t key0, key1;  // seed
   uint32_t event, tkey;
   uint32_t draw;
-  uint32_t cached_block;
-  uint32_t w[4];
+  uint32_t blk = 0xFFFFFFFFu;  // block index held in w (draws 2k and 2k+1 share a block)
+  uint32_t w[4] = {0, 0, 0, 0};
 };
 
 __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -667,30 +820,22 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint32_t 
   out[3] = c3;
 }
 
-__device__ __forceinline__ void rng_start(Philox& r, uint64_t seed, uint32_t event, uint32_t tkey) {
-  r.key0 = (uint32_t)seed;
-  r.key1 = (uint32_t)(seed >> 32);
+__device__ __forceinline__ void rng_start(Philox& r, uint32_t event, uint32_t tkey) {
   r.event = event;
   r.tkey = tkey;
   r.draw = 0;
-  r.cached_block = 0xFFFFFFFFu;
 }
 
-// Uniform in (0, 1]: 53 bits from two words, plus one.
-__device__ __forceinline__ double rng_next(Philox& r) {
-  uint32_t blk = r.draw >> 1;
-  if (blk != r.cached_block) {
-    philox_block(blk, r.tkey, r.event, 0u, r.key0, r.key1, r.w);
-    r.cached_block = blk;
+// Uniform in (0, 1]: draw n uses words 2(n&1), 2(n&1)+1 of Philox block n/2
+// (counter {n/2, track key, event, 0}, key = seed); 53 bits plus one.
+__device__ __forceinline__ double rng_next(Philox& r, uint32_t seed_lo, uint32_t seed_hi) {
+  uint32_t b = r.draw >> 1;
+  if (b != r.blk) {
+    philox_block(b, r.tkey, r.event, 0u, seed_lo, seed_hi, r.w);
+    r.blk = b;
   }
-  uint32_t lo, hi;
-  if (r.draw & 1u) {
-    lo = r.w[2];
-    hi = r.w[3];
-  } else {
-    lo = r.w[0];
-    hi = r.w[1];
-  }
+  uint32_t lo = (r.draw & 1u) ? r.w[2] : r.w[0];
+  uint32_t hi = (r.draw & 1u) ? r.w[3] : r.w[1];
   r.draw++;
   uint64_t m = ((((uint64_t)hi) << 32) | (uint64_t)lo) >> 11;
   return (double)(m + 1u) * 0x1p-53;

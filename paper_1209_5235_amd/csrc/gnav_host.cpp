@@ -23,6 +23,8 @@
 
 using namespace gnav;
 
+static constexpr int kSolidStride = 16;  // host-side staging of solid parameters
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -302,7 +304,8 @@ bool extent_is_tight(int type, const double* R) {
 // ---------------------------------------------------------------------------
 
 struct VoxBuild {
-  VoxHdr hdr;
+  double lo[3], w[3], inv_w[3];
+  int n[3];
   std::vector<std::vector<uint16_t>> nodes;
 };
 
@@ -378,18 +381,18 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
   VoxBuild vb;
   for (int a = 0; a < 3; a++) {
     int n = opts[a][bi[a]];
-    vb.hdr.n[a] = n;
-    vb.hdr.lo[a] = g.lo[a];
-    vb.hdr.w[a] = (g.hi[a] - g.lo[a]) / n;
-    vb.hdr.inv_w[a] = 1.0 / vb.hdr.w[a];
+    vb.n[a] = n;
+    vb.lo[a] = g.lo[a];
+    vb.w[a] = (g.hi[a] - g.lo[a]) / n;
+    vb.inv_w[a] = 1.0 / vb.w[a];
   }
-  const int nx = vb.hdr.n[0], ny = vb.hdr.n[1], nz = vb.hdr.n[2];
+  const int nx = vb.n[0], ny = vb.n[1], nz = vb.n[2];
   vb.nodes.assign((size_t)nx * ny * nz, {});
   for (int d = 0; d < cnt; d++) {
     int l[3], h[3];
     for (int a = 0; a < 3; a++) {
-      l[a] = span_lo(dau[d].lo[a], g.lo[a], vb.hdr.w[a], vb.hdr.n[a]);
-      h[a] = span_lo(dau[d].hi[a], g.lo[a], vb.hdr.w[a], vb.hdr.n[a]);
+      l[a] = span_lo(dau[d].lo[a], g.lo[a], vb.w[a], vb.n[a]);
+      h[a] = span_lo(dau[d].hi[a], g.lo[a], vb.w[a], vb.n[a]);
     }
     for (int i = l[0]; i <= h[0]; i++)
       for (int j = l[1]; j <= h[1]; j++)
@@ -403,7 +406,9 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
 // ---------------------------------------------------------------------------
 
 struct GeomRec {
+  gnav_mlp* mlp = nullptr;  // network for the learned candidate order
   int t_base, n_t;
+  int n_class = 0;  // voxelised mothers (candidate-ordering classes)
   int lv_base, pv_base, solid_base, mat_base;
   std::vector<int> h_parent, h_pv, h_lv, h_depth;  // per-geometry ids
 };
@@ -414,29 +419,21 @@ struct gnav_ctx {
   int device = 0;
   int n_cu = 256;
   std::string err;
-  // concatenated host tables
-  std::vector<int> t_parent, t_lv, t_child_base, t_slot;
+  // concatenated host tables (records)
+  std::vector<TRec> t_rec;
   std::vector<double> t_xf;
-  std::vector<uint8_t> t_kind;
-  std::vector<int> lv_solid, lv_mat, lv_dau_base, lv_dau_cnt, lv_vox;
-  std::vector<double> pv_xf;
-  std::vector<uint8_t> pv_kind;
-  std::vector<int> pv_lv;
-  std::vector<double> sd_par;
-  std::vector<int> sd_info;
-  std::vector<VoxHdr> vox_hdr;
+  std::vector<LRec> lv_rec;
+  std::vector<PRec> pv_rec;
   std::vector<int2> vox_node;
   std::vector<uint16_t> vox_cand;
   std::vector<double> xs;
   std::vector<GeomRec> geoms;
   std::vector<int> geom_tbase;
+  int n_mats_total = 0;
   double lnE0 = 0, dlnE = 0;
   // device copies
-  DevBuf d_t_parent, d_t_lv, d_t_child_base, d_t_slot, d_t_xf, d_t_kind;
-  DevBuf d_lv_solid, d_lv_mat, d_lv_dau_base, d_lv_dau_cnt, d_lv_vox;
-  DevBuf d_pv_xf, d_pv_kind, d_pv_lv, d_sd_par, d_sd_info;
-  DevBuf d_vox_hdr, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
-  DevBuf d_queue;
+  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
+  DevBuf d_queue, d_pend;
   DevGeom G{};
 };
 
@@ -468,46 +465,20 @@ hipError_t upload_all(gnav_ctx* c) {
   hipError_t e;
 #define UP(buf, vec) \
   if ((e = up(c->buf, c->vec)) != hipSuccess) return e;
-  UP(d_t_parent, t_parent)
-  UP(d_t_lv, t_lv)
-  UP(d_t_child_base, t_child_base)
-  UP(d_t_slot, t_slot)
+  UP(d_t_rec, t_rec)
   UP(d_t_xf, t_xf)
-  UP(d_t_kind, t_kind)
-  UP(d_lv_solid, lv_solid)
-  UP(d_lv_mat, lv_mat)
-  UP(d_lv_dau_base, lv_dau_base)
-  UP(d_lv_dau_cnt, lv_dau_cnt)
-  UP(d_lv_vox, lv_vox)
-  UP(d_pv_xf, pv_xf)
-  UP(d_pv_kind, pv_kind)
-  UP(d_pv_lv, pv_lv)
-  UP(d_sd_par, sd_par)
-  UP(d_sd_info, sd_info)
-  UP(d_vox_hdr, vox_hdr)
+  UP(d_lv_rec, lv_rec)
+  UP(d_pv_rec, pv_rec)
   UP(d_vox_node, vox_node)
   UP(d_vox_cand, vox_cand)
   UP(d_xs, xs)
   UP(d_geom_tbase, geom_tbase)
 #undef UP
   DevGeom& G = c->G;
-  G.t_parent = c->d_t_parent.as<int>();
-  G.t_lv = c->d_t_lv.as<int>();
-  G.t_child_base = c->d_t_child_base.as<int>();
-  G.t_slot = c->d_t_slot.as<int>();
+  G.t = c->d_t_rec.as<TRec>();
   G.t_xf = c->d_t_xf.as<double>();
-  G.t_kind = c->d_t_kind.as<uint8_t>();
-  G.lv_solid = c->d_lv_solid.as<int>();
-  G.lv_mat = c->d_lv_mat.as<int>();
-  G.lv_dau_base = c->d_lv_dau_base.as<int>();
-  G.lv_dau_cnt = c->d_lv_dau_cnt.as<int>();
-  G.lv_vox = c->d_lv_vox.as<int>();
-  G.pv_xf = c->d_pv_xf.as<double>();
-  G.pv_kind = c->d_pv_kind.as<uint8_t>();
-  G.pv_lv = c->d_pv_lv.as<int>();
-  G.sd_par = c->d_sd_par.as<double>();
-  G.sd_info = c->d_sd_info.as<int>();
-  G.vox_hdr = c->d_vox_hdr.as<VoxHdr>();
+  G.lv = c->d_lv_rec.as<LRec>();
+  G.pv = c->d_pv_rec.as<PRec>();
   G.vox_node = c->d_vox_node.as<int2>();
   G.vox_cand = c->d_vox_cand.as<uint16_t>();
   G.xs = c->d_xs.as<double>();
@@ -657,21 +628,19 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
     if (it == d->n_lv + 1) return fail(c, GNAV_EGEOM, "placement cycle");
   }
   long long nt_ll = cnt[d->world_lv];
-  long long total_t = (long long)c->t_parent.size() + nt_ll;
+  long long total_t = (long long)c->t_rec.size() + nt_ll;
   if (nt_ll > (1LL << 30) || total_t > (1LL << 30)) return fail(c, GNAV_EGEOM, "too many touchables");
   const int nt = (int)nt_ll;
 
   GeomRec gr;
-  gr.t_base = (int)c->t_parent.size();
+  gr.t_base = (int)c->t_rec.size();
   gr.n_t = nt;
-  gr.lv_base = (int)c->lv_solid.size();
-  gr.pv_base = (int)c->pv_lv.size();
-  gr.solid_base = (int)c->sd_info.size();
-  gr.mat_base = (int)(c->xs.size() / (3 * kNNode));
+  gr.lv_base = (int)c->lv_rec.size();
+  gr.pv_base = (int)c->pv_rec.size();
+  gr.solid_base = 0;
+  gr.mat_base = c->n_mats_total;
 
-  // solids, materials
-  c->sd_par.insert(c->sd_par.end(), q.begin(), q.end());
-  c->sd_info.insert(c->sd_info.end(), info.begin(), info.end());
+  // attenuation tables per material
   for (int m = 0; m < d->n_mats; m++) {
     for (int p = 0; p < 3; p++) {
       for (int i = 0; i < kNNode; i++) {
@@ -688,26 +657,43 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       }
     }
   }
-  // PVs
+  c->n_mats_total += d->n_mats;
+  // placements: M = R^T (row major, M[i][j] = R[j][i]) and t
   for (int p = 0; p < d->n_pv; p++) {
     const double* R = d->pv_rot + 9 * p;
     const double* t = d->pv_trans + 3 * p;
-    // M = R^T (row major): M[i][j] = R[j][i]
+    PRec pr;
+    std::memset(&pr, 0, sizeof(pr));
     for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++) c->pv_xf.push_back(R[3 * j + i]);
-    c->pv_xf.push_back(t[0]);
-    c->pv_xf.push_back(t[1]);
-    c->pv_xf.push_back(t[2]);
-    c->pv_kind.push_back(is_identity(R) ? 0 : 1);
-    c->pv_lv.push_back(gr.lv_base + d->pv_lv[p]);
+      for (int j = 0; j < 3; j++) pr.m[3 * i + j] = R[3 * j + i];
+    pr.m[9] = t[0];
+    pr.m[10] = t[1];
+    pr.m[11] = t[2];
+    pr.kind = is_identity(R) ? 0 : 1;
+    pr.lv = gr.lv_base + d->pv_lv[p];
+    {
+      int ds = d->lv_solid[d->pv_lv[p]];
+      Box3 b = place_solid(d->solid_type[ds], d->solid_par + 8 * ds, ext[ds], R, t);
+      for (int a = 0; a < 3; a++) {
+        double pad = 1e-7 + 1e-12 * std::max(std::fabs(b.lo[a]), std::fabs(b.hi[a]));
+        pr.box_lo[a] = b.lo[a] - pad;
+        pr.box_hi[a] = b.hi[a] + pad;
+      }
+    }
+    c->pv_rec.push_back(pr);
   }
-  // LVs and voxels
+  // logical volumes with their solid and voxel grid
   for (int l = 0; l < d->n_lv; l++) {
-    c->lv_solid.push_back(gr.solid_base + d->lv_solid[l]);
-    c->lv_mat.push_back(gr.mat_base + d->lv_mat[l]);
-    c->lv_dau_base.push_back(gr.pv_base + d->lv_dau_off[l]);
-    c->lv_dau_cnt.push_back(d->lv_dau_cnt[l]);
-    int vh = -1;
+    LRec lr;
+    std::memset(&lr, 0, sizeof(lr));
+    int s = d->lv_solid[l];
+    lr.info = info[s];
+    for (int k = 0; k < kSolidPar; k++) lr.par[k] = q[(size_t)s * kSolidStride + k];
+    lr.mat = gr.mat_base + d->lv_mat[l];
+    lr.dau_base = gr.pv_base + d->lv_dau_off[l];
+    lr.dau_cnt = d->lv_dau_cnt[l];
+    lr.vox = 0;
+    lr.lclass = -1;
     bool want = d->lv_voxelize ? d->lv_voxelize[l] != 0 : true;
     if (want && d->lv_dau_cnt[l] >= 3) {
       std::vector<Box3> db;
@@ -724,7 +710,15 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
         db.push_back(b);
       }
       VoxBuild vb = build_voxels(ext[d->lv_solid[l]], db);
-      vb.hdr.node_base = (int)c->vox_node.size();
+      lr.vox = 1;
+      lr.lclass = gr.n_class++;
+      lr.node_base = (int)c->vox_node.size();
+      for (int a = 0; a < 3; a++) {
+        lr.n[a] = vb.n[a];
+        lr.vlo[a] = vb.lo[a];
+        lr.vw[a] = vb.w[a];
+        lr.vinv[a] = vb.inv_w[a];
+      }
       std::map<std::vector<uint16_t>, int> dedup;
       for (auto& nd : vb.nodes) {
         auto it = dedup.find(nd);
@@ -738,17 +732,15 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
         }
         c->vox_node.push_back(int2{off, (int)nd.size()});
       }
-      vh = (int)c->vox_hdr.size();
-      c->vox_hdr.push_back(vb.hdr);
     }
-    c->lv_vox.push_back(vh);
+    c->lv_rec.push_back(lr);
   }
   // touchables: breadth first from the world
   gr.h_parent.assign(nt, -1);
   gr.h_pv.assign(nt, -1);
   gr.h_lv.assign(nt, 0);
   gr.h_depth.assign(nt, 0);
-  std::vector<int> slot(nt, -1), child(nt, 0);
+  std::vector<int> slot(nt, 0), child(nt, 0);
   std::vector<long double> Rg((size_t)nt * 9), tg((size_t)nt * 3);
   gr.h_lv[0] = d->world_lv;
   for (int i = 0; i < 9; i++) Rg[i] = (i % 4 == 0) ? 1.0L : 0.0L;
@@ -769,22 +761,18 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       // x_world = Rg_parent (R x + t) + tg_parent
       for (int a = 0; a < 3; a++) {
         for (int b = 0; b < 3; b++) {
-          long double s = 0;
-          for (int m = 0; m < 3; m++) s += Rg[(size_t)i * 9 + 3 * a + m] * (long double)R[3 * m + b];
-          Rg[(size_t)n * 9 + 3 * a + b] = s;
+          long double sum = 0;
+          for (int m = 0; m < 3; m++) sum += Rg[(size_t)i * 9 + 3 * a + m] * (long double)R[3 * m + b];
+          Rg[(size_t)n * 9 + 3 * a + b] = sum;
         }
-        long double s = tg[(size_t)i * 3 + a];
-        for (int m = 0; m < 3; m++) s += Rg[(size_t)i * 9 + 3 * a + m] * (long double)t[m];
-        tg[(size_t)n * 3 + a] = s;
+        long double sum = tg[(size_t)i * 3 + a];
+        for (int m = 0; m < 3; m++) sum += Rg[(size_t)i * 9 + 3 * a + m] * (long double)t[m];
+        tg[(size_t)n * 3 + a] = sum;
       }
       n++;
     }
   }
   for (int i = 0; i < nt; i++) {
-    c->t_parent.push_back(gr.h_parent[i] < 0 ? -1 : gr.t_base + gr.h_parent[i]);
-    c->t_lv.push_back(gr.lv_base + gr.h_lv[i]);
-    c->t_child_base.push_back(gr.t_base + child[i]);
-    c->t_slot.push_back(slot[i]);
     bool ident = true;
     double M[9];
     for (int a = 0; a < 3; a++)
@@ -794,7 +782,12 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       }
     c->t_xf.insert(c->t_xf.end(), M, M + 9);
     for (int a = 0; a < 3; a++) c->t_xf.push_back((double)tg[(size_t)i * 3 + a]);
-    c->t_kind.push_back(ident ? 0 : 1);
+    TRec tr;
+    tr.lv = gr.lv_base + gr.h_lv[i];
+    tr.parent = gr.h_parent[i] < 0 ? -1 : gr.t_base + gr.h_parent[i];
+    tr.child_base = gr.t_base + child[i];
+    tr.slot_kind = (slot[i] & 0xFFFF) | ((ident ? 0 : 1) << 16);
+    c->t_rec.push_back(tr);
   }
   c->geom_tbase.push_back(gr.t_base);
   int id = (int)c->geoms.size();
@@ -821,11 +814,29 @@ gnav_status gnav_touchables(gnav_ctx* c, int32_t geom_id, int32_t* parent, int32
   return GNAV_OK;
 }
 
+gnav_status gnav_ordering_classes(gnav_ctx* c, int32_t geom_id, int32_t* n_class) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (!n_class) return GNAV_EINVAL;
+  *n_class = c->geoms[geom_id].n_class;
+  return GNAV_OK;
+}
+
+gnav_status gnav_set_mlp(gnav_ctx* c, int32_t geom_id, gnav_mlp* mlp) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  MlpView v;
+  if (mlp && (!mlp_view(mlp, &v) || v.n_class != c->geoms[geom_id].n_class))
+    return fail(c, GNAV_EINVAL, "network class count differs from the geometry's ordering classes");
+  c->geoms[geom_id].mlp = mlp;
+  return GNAV_OK;
+}
+
 gnav_status gnav_touchable_offset(gnav_ctx* c, int32_t geom_id, int32_t* offset, int32_t* total) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
   if (offset) *offset = c->geoms[geom_id].t_base;
-  if (total) *total = (int32_t)c->t_parent.size();
+  if (total) *total = (int32_t)c->t_rec.size();
   return GNAV_OK;
 }
 
@@ -870,7 +881,7 @@ gnav_status gnav_tally_create(gnav_ctx* c, int32_t n_events, gnav_tally** out) {
   gnav_tally* t = new (std::nothrow) gnav_tally();
   if (!t) return fail(c, GNAV_ENOMEM, "tally");
   t->n_events = n_events;
-  t->n_touch = (int)c->t_parent.size();
+  t->n_touch = (int)c->t_rec.size();
   hipError_t e;
   if ((e = t->edep_t.upload(nullptr, sizeof(double) * t->n_touch)) != hipSuccess ||
       (e = t->edep_ev.upload(nullptr, sizeof(double) * (size_t)n_events)) != hipSuccess ||
@@ -899,24 +910,32 @@ gnav_status gnav_tally_free(gnav_ctx* c, gnav_tally* t) {
   return GNAV_OK;
 }
 
-gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Validate a batch and fill the launch description (may grow the
+// pending-photon buffer, which synchronises the stream).
+gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, hipStream_t stream,
+                              TransportLaunch* out) {
   if (!c || !b || !t) return GNAV_EINVAL;
   gnav_status s = check_geom(c, b->geom_id);
   if (s) return s;
-  if (b->n_primaries < 0) return fail(c, GNAV_EINVAL, "negative primary count");
+  if (b->n_primaries < 0 || b->n_primaries > 0x7fffffffL) return fail(c, GNAV_EINVAL, "primary count out of range");
   if (b->n_primaries > 0 && (!b->event_dev || !b->prim_id_dev || !b->pos_dev || !b->dir_dev || !b->energy_dev))
     return fail(c, GNAV_EINVAL, "null primary array");
-  if (t->n_touch != (int)c->t_parent.size())
+  if (t->n_touch != (int)c->t_rec.size())
     return fail(c, GNAV_ESTATE, "tally was created before the last geometry upload");
   if (b->precision != 0) return fail(c, GNAV_EUNSUPPORTED, "precision mode not available");
   if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
     return fail(c, GNAV_EINVAL, "log buffers incomplete");
   if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
   int block = b->block > 0 ? b->block : 256;
-  if (block % 64 != 0 || block > 256) return fail(c, GNAV_EINVAL, "block must be a multiple of 64, <= 256");
+  if (block != 256) return fail(c, GNAV_EINVAL, "block must be 256 (one 256-slot track pool per block)");
   long need = (b->n_primaries + block - 1) / block;
-  int grid = b->grid > 0 ? b->grid : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 8);
-  TransportLaunch L{};
+  int grid = b->grid > 0 ? b->grid : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 3);
+  TransportLaunch& L = *out;
+  L = TransportLaunch{};
   L.G = c->G;
   L.n = b->n_primaries;
   L.event = b->event_dev;
@@ -937,13 +956,105 @@ gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t
   L.esc_ev = t->esc_ev.as<double>();
   L.counters = t->counters.as<unsigned long long>();
   L.queue = c->d_queue.as<unsigned long long>();
+  // per-slot storage for the second annihilation photon of a pair conversion
+  size_t pend_bytes = (size_t)grid * block * 6 * sizeof(double);
+  if (c->d_pend.bytes < pend_bytes) {
+    HIP_TRY(c, hipStreamSynchronize(stream), "synchronize");
+    HIP_TRY(c, c->d_pend.upload(nullptr, pend_bytes), "pending-photon buffer");
+  }
+  L.pend = c->d_pend.as<double>();
+  L.count = b->count_work != 0;
+  if (b->order < 0 || b->order > 2) return fail(c, GNAV_EINVAL, "order must be 0, 1 or 2");
+  L.order = b->order;
+  if (b->order == 2) {
+    const GeomRec& gr = c->geoms[b->geom_id];
+    if (b->event_geom_dev) return fail(c, GNAV_EUNSUPPORTED, "the learned order needs a single geometry");
+    if (!gr.mlp || !mlp_view(gr.mlp, &L.mlp) || L.mlp.n_class != gr.n_class)
+      return fail(c, GNAV_ESTATE, "no network (or a class-count mismatch) for the learned order");
+  }
+  if (b->record_dev && (b->record_capacity <= 0 || !b->record_count_dev))
+    return fail(c, GNAV_EINVAL, "recorder buffers incomplete");
+  L.rec = b->record_dev;
+  L.rec_cap = b->record_dev ? b->record_capacity : 0;
+  L.rec_count = reinterpret_cast<unsigned long long*>(b->record_count_dev);
   L.log = b->log_dev;
   L.log_cap = b->log_capacity;
   L.log_n = b->log_n_dev;
   L.log_fate = b->log_fate_dev;
   L.block = block;
   L.grid = grid;
+  return GNAV_OK;
+}
+
+}  // namespace
+
+struct gnav_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream) {
+  TransportLaunch L;
+  gnav_status s = prepare_transport(c, b, t, (hipStream_t)stream, &L);
+  if (s) return s;
   HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_graph_create(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream, gnav_graph** out) {
+  if (!out) return GNAV_EINVAL;
+  *out = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  TransportLaunch L;
+  gnav_status s = prepare_transport(c, b, t, st, &L);
+  if (s) return s;
+  HIP_TRY(c, hipStreamSynchronize(st), "synchronize");
+  gnav_graph* g = new (std::nothrow) gnav_graph();
+  if (!g) return fail(c, GNAV_ENOMEM, "graph");
+  hipStream_t cap;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(c, e, "capture stream");
+  }
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = launch_zero(t->edep_t.p, t->edep_t.bytes / 8, cap);
+    hipError_t e2 = launch_zero(t->edep_ev.p, t->edep_ev.bytes / 8, cap);
+    hipError_t e3 = launch_zero(t->esc_ev.p, t->esc_ev.bytes / 8, cap);
+    hipError_t e4 = launch_zero(t->counters.p, t->counters.bytes / 8, cap);
+    hipError_t e5 = launch_transport(L, cap);
+    hipError_t ee = hipStreamEndCapture(cap, &g->graph);
+    e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : e4 != hipSuccess ? e4
+        : e5 != hipSuccess ? e5 : ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(c, e, "graph capture");
+  }
+  *out = g;
+  return GNAV_OK;
+}
+
+gnav_status gnav_graph_launch(gnav_ctx* c, gnav_graph* g, void* stream) {
+  if (!c || !g) return GNAV_EINVAL;
+  HIP_TRY(c, hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_graph_free(gnav_ctx* c, gnav_graph* g) {
+  if (!c) return GNAV_EINVAL;
+  if (g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+  }
   return GNAV_OK;
 }
 

@@ -8,6 +8,18 @@
 
 namespace gnav {
 
+// Device view of a candidate-ordering network (bf16 weights, float biases).
+struct MlpView {
+  const uint16_t* w1x;  // [128][6]
+  const uint16_t* w1m;  // [n_class][128]
+  const uint16_t* w2;   // [128][128]
+  const uint16_t* w3;   // [64][128]
+  const float* b1;
+  const float* b2;
+  const float* b3;
+  int n_class;
+};
+
 struct TransportLaunch {
   DevGeom G;
   long n;
@@ -29,13 +41,22 @@ struct TransportLaunch {
   double* esc_ev;
   unsigned long long* counters;
   unsigned long long* queue;
+  double* pend;
   gnav_logrec* log;
   long log_cap;
   int* log_n;
   int* log_fate;
   int block;
   int grid;
+  bool count;
+  int order;
+  gnav_crossing* rec;
+  long rec_cap;
+  unsigned long long* rec_count;
+  MlpView mlp;
 };
+
+bool mlp_view(const gnav_mlp* m, MlpView* out);
 
 hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const double* pos,
                          const double* dir, int* out, hipStream_t st);

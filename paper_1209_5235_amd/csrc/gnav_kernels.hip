@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_locate(DevGeom G, int W, int tbase, lon
                                                 const double* dir, int* out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  NavCount nc{};
+  NavCount<false> nc;
   V3 p{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   V3 v{0, 0, 0};
   bool hv = dir != nullptr;
@@ -35,12 +35,12 @@ __global__ void __launch_bounds__(256) k_locate(DevGeom G, int W, int tbase, lon
   out[i] = T < 0 ? -1 : T - tbase;
 }
 
-__global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int tcount, long n, const double* pos,
-                                              const double* dir, const int* touch, double* step,
-                                              int* lim_out, int* next) {
+__global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int tcount, long n,
+                                              const double* pos, const double* dir, const int* touch,
+                                              double* step, int* lim_out, int* next) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  NavCount nc{};
+  NavCount<false> nc;
   V3 p{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   V3 v{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
   int T = touch ? ((touch[i] < 0 || touch[i] >= tcount) ? -1 : touch[i] + tbase)
@@ -51,28 +51,29 @@ __global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int t
     if (next) next[i] = -1;
     return;
   }
+  TRec tr = G.t[T];
   V3 pl, vl;
-  touchable_frame(G, T, p, v, pl, vl);
+  touchable_frame(G, T, trec_kind(tr), p, v, pl, vl);
   int lim;
   double saf;
-  double s = compute_step(G, G.t_lv[T], pl, vl, lim, saf, nc);
+  double s = compute_step(G, G.lv[tr.lv], pl, vl, lim, saf, nc);
   step[i] = s;
   lim_out[i] = lim;
   if (next) {
     int nt = -1;
     if (s < kInf) {
       V3 q{p.x + s * v.x, p.y + s * v.y, p.z + s * v.z};
-      nt = relocate(G, T, q, v, lim, nc);
+      nt = relocate(G, T, tr, q, v, lim, nc);
     }
     next[i] = nt < 0 ? -1 : nt - tbase;
   }
 }
 
-__global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int tcount, long n, const double* pos,
-                                                const int* touch, double* out) {
+__global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int tcount, long n,
+                                                const double* pos, const int* touch, double* out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  NavCount nc{};
+  NavCount<false> nc;
   V3 p{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   V3 z{0, 0, 0};
   int T = touch ? ((touch[i] < 0 || touch[i] >= tcount) ? -1 : touch[i] + tbase)
@@ -81,12 +82,13 @@ __global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int
     out[i] = 0.0;
     return;
   }
+  TRec tr = G.t[T];
   V3 pl, vl;
-  touchable_frame(G, T, p, V3{0, 0, 1}, pl, vl);
+  touchable_frame(G, T, trec_kind(tr), p, V3{0, 0, 1}, pl, vl);
   int lim;
   double saf;
   // the safety comes from the start node of a step walk along any direction
-  compute_step(G, G.t_lv[T], pl, vl, lim, saf, nc);
+  compute_step(G, G.lv[tr.lv], pl, vl, lim, saf, nc);
   out[i] = saf;
 }
 
@@ -94,15 +96,19 @@ __global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int
 // Transport
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void mu_lookup(const DevGeom& G, int mat, double E, double& pe, double& co,
-                                          double& pp) {
+// Table position of energy E: node index i and weight w, linear in ln E
+// over 257 nodes (clamped at both ends).
+__device__ __forceinline__ void mu_index(const DevGeom& G, double E, int& i, double& w) {
   double x = (log(E) - G.lnE0) / G.dlnE;
-  int i;
   if (x < 0) i = 0;
   else if (x >= 255.0) i = 255;
   else i = (int)x;
-  double w = x - (double)i;
+  w = x - (double)i;
   w = dmin(dmax(w, 0.0), 1.0);
+}
+
+__device__ __forceinline__ void mu_parts(const DevGeom& G, int mat, int i, double w, double E, double& pe,
+                                         double& co, double& pp) {
   const double* t = G.xs + (size_t)mat * 3 * kNNode;
   pe = (1.0 - w) * t[i] + w * t[i + 1];
   co = (1.0 - w) * t[kNNode + i] + w * t[kNNode + i + 1];
@@ -113,15 +119,15 @@ __device__ __forceinline__ void mu_lookup(const DevGeom& G, int mat, double E, d
 // Butcher-Messel sampling of the Klein-Nishina energy fraction eps = E'/E:
 // a two-branch mixture (weights ln(1+2k) and (1-eps0^2)/2) with acceptance
 // 1 - eps sin^2(theta) / (1 + eps^2); three draws per trial.
-__device__ __forceinline__ void compton_sample(double E, Philox& rs, double& eps, double& onecost,
-                                               double& sint2) {
+__device__ __forceinline__ void compton_sample(double E, Philox& rs, uint32_t s0, uint32_t s1, double& eps,
+                                               double& onecost, double& sint2) {
   double k = E / kMe;
   double eps0 = 1.0 / (1.0 + 2.0 * k);
   double eps0sq = eps0 * eps0;
   double a1 = log(1.0 + 2.0 * k);
   double a2 = 0.5 * (1.0 - eps0sq);
   for (int trial = 0; trial < kMaxComptonTrials; trial++) {
-    double r1 = rng_next(rs), r2 = rng_next(rs), r3 = rng_next(rs);
+    double r1 = rng_next(rs, s0, s1), r2 = rng_next(rs, s0, s1), r3 = rng_next(rs, s0, s1);
     double epssq;
     if (r1 * (a1 + a2) < a1) {
       eps = exp(-a1 * r2);
@@ -137,6 +143,7 @@ __device__ __forceinline__ void compton_sample(double E, Philox& rs, double& eps
   }
 }
 
+// Turn unit vector v by polar angle (cos, sin) and azimuth phi about itself.
 __device__ __forceinline__ void rotate_dir(V3& v, double cost, double sint, double phi) {
   double cp = cos(phi), sp = sin(phi);
   double a = v.x, b = v.y, c = v.z;
@@ -167,264 +174,662 @@ struct TransportArgs {
   const double* energy;
   const int* event_geom;   // may be null
   int geom_default;
-  const int* geom_tbase;   // [geoms] first touchable (global)
+  const int* geom_tbase;   // [geoms] first touchable (global) = the world
   int n_geoms;
   int n_events;
-  uint64_t seed;
+  uint32_t seed_lo, seed_hi;
   double ecut;
-  long max_steps;
+  int max_steps;
   double* edep_t;
   double* edep_ev;
   double* esc_ev;
   unsigned long long* counters;
   unsigned long long* queue;  // [0]: next primary
+  double* pend;               // [lanes][6]: pending annihilation photon position and direction
   gnav_logrec* log;
   long log_cap;
   int* log_n;
   int* log_fate;
+  gnav_crossing* rec;         // optional crossing recorder
+  long rec_cap;
+  unsigned long long* rec_count;
+  MlpView mlp;                // candidate-ordering network (learned order)
 };
 
-__device__ __forceinline__ void atomic_add_f64(double* p, double v) {
-  unsafeAtomicAdd(p, v);
+__device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Optional occupancy target for the transport kernel (waves per SIMD), set at
+// build time; 0 leaves register allocation to the compiler.
+#ifndef GNAV_TRANSPORT_WAVES
+#define GNAV_TRANSPORT_WAVES 0
+#endif
+#if GNAV_TRANSPORT_WAVES > 0
+#define GNAV_TRANSPORT_ATTR __attribute__((amdgpu_waves_per_eu(GNAV_TRANSPORT_WAVES)))
+#else
+#define GNAV_TRANSPORT_ATTR
+#endif
+
+// ---------------------------------------------------------------------------
+// Block track pool.  Each block owns kPool track slots held in LDS as
+// structure of arrays.  One loop iteration runs four block-wide phases:
+//   refill   - empty slots take a pending annihilation photon or a queued
+//              primary (one queue atomic per wave);
+//   navigate - slots that start a track or crossed a boundary relocate;
+//   step     - slots ready to move compute mu, the safety shortcut or a
+//              ComputeStep, and advance;
+//   interact - slots whose step ended in an interaction sample it.
+// Before each phase the slots that need it are compacted into a dense work
+// list with wave ballots and a block prefix sum (optionally bucketed by a
+// small key: the mother's solid type for steps, the process for
+// interactions), so the lanes of a wave run the same code path.
+// ---------------------------------------------------------------------------
+
+constexpr int kPool = 256;
+constexpr int kWaves = kPool / 64;
+
+// slot status
+enum : int { kEmpty = 0, kNav = 1, kStep = 2, kInt = 3 };
+// process codes for kInt
+enum : int { kProcPE = 0, kProcCompton = 1, kProcPair = 2 };
+
+struct Pool {
+  double x[kPool], y[kPool], z[kPool], vx[kPool], vy[kPool], vz[kPool];
+  double E[kPool], nl[kPool], saf[kPool], mu[kPool], wmu[kPool], slast[kPool];
+  int T[kPool], lvk[kPool], tbase[kPool], event[kPool], key[kPool], draw[kPool];
+  int status[kPool];  // kEmpty / kNav / kStep / kInt
+  int aux[kPool];     // kNav: navigation mode | lim << 2 ; kInt: process
+  int zero_steps[kPool];  // zero-step count (low 8 bits) | steps << 8
+  int imu_mat[kPool];     // table node | cached material << 9 (material + 1, 0 = none)
+  int prim[kPool];
+  int sub_pend[kPool];    // photon index (0..2) | pending annihilation photons << 4
+  int nrec[kPool];
+  unsigned cnt_a[kPool];  // Compton scatters | shortcuts << 16
+  unsigned cnt_b[kPool];  // crossings | pushes << 24
+  int pred[kPool];     // learned order: predicted candidate position of the next step
+  int list[kPool];
+  int wcnt[8 * kWaves];
+  int total[8];
+  unsigned long long cnt[GNAV_NCOUNTERS];
+  int any_alive;
+};
+
+// Dense work list of the slots with `flag`, bucketed by `key` in [0, K):
+// list entries of bucket 0 first, then bucket 1, ...  Returns the count
+// (block uniform).  Must be called by every thread of the block.
+template <int K>
+__device__ __forceinline__ int compact(Pool& P, bool flag, int key) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long my_mask = 0;
+#pragma unroll
+  for (int b = 0; b < K; b++) {
+    unsigned long long m = __ballot(flag && key == b);
+    if (flag && key == b) my_mask = m;
+    if (lane == 0) P.wcnt[b * kWaves + w] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    int t = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ww++) t += P.wcnt[threadIdx.x * kWaves + ww];
+    P.total[threadIdx.x] = t;
+  }
+  __syncthreads();
+  int n = 0;
+#pragma unroll
+  for (int b = 0; b < K; b++) n += P.total[b];
+  if (flag) {
+    int base = 0;
+    for (int b = 0; b < key; b++) base += P.total[b];
+    for (int ww = 0; ww < w; ww++) base += P.wcnt[key * kWaves + ww];
+    P.list[base + __popcll(my_mask & lt)] = threadIdx.x;
+  }
+  __syncthreads();
+  return n;
 }
 
 template <bool LOG>
-__global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
-  const DevGeom& G = a.G;
-  const int lane = threadIdx.x & 63;
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+__device__ __forceinline__ void end_track(Pool& P, const TransportArgs& a, int s, int fate, int steps) {
+  P.status[s] = kEmpty;
+  int slot = fate == GNAV_FATE_ABSORBED ? GNAV_C_PE
+           : fate == GNAV_FATE_PAIR     ? GNAV_C_PAIR
+           : fate == GNAV_FATE_ESCAPED  ? GNAV_C_ESCAPED
+           : fate == GNAV_FATE_CUTOFF   ? GNAV_C_CUTOFF
+           : fate == GNAV_FATE_STUCK    ? GNAV_C_STUCK
+                                        : GNAV_C_TRUNCATED;
+  atomicAdd(&P.cnt[slot], 1ull);
+  if (steps) atomicAdd(&P.cnt[GNAV_C_STEPS], (unsigned long long)steps);
+  unsigned ca = P.cnt_a[s], cb = P.cnt_b[s];
+  if (ca & 0xFFFF) atomicAdd(&P.cnt[GNAV_C_COMPTON], (unsigned long long)(ca & 0xFFFF));
+  if (ca >> 16) atomicAdd(&P.cnt[GNAV_C_SHORTCUTS], (unsigned long long)(ca >> 16));
+  if (cb & 0xFFFFFF) atomicAdd(&P.cnt[GNAV_C_CROSSINGS], (unsigned long long)(cb & 0xFFFFFF));
+  if (cb >> 24) atomicAdd(&P.cnt[GNAV_C_PUSHES], (unsigned long long)(cb >> 24));
+  if (LOG) {
+    int sub = P.sub_pend[s] & 15;
+    a.log_n[3 * P.prim[s] + sub] = P.nrec[s];
+    a.log_fate[3 * P.prim[s] + sub] = fate;
+  }
+}
 
-  // per-lane track state
-  bool alive = false;
-  V3 x{0, 0, 0}, v{0, 0, 0};
-  double E = 0, nl = 0, safety = 0;
-  double mpe = 0, mco = 0, mpp = 0;
-  int mat_cached = -1;
-  int T = -1, tbase = 0, event = 0, zero = 0;
-  long steps = 0;
-  uint32_t key = 0;
-  Philox rs;
-  // pending annihilation photons of this lane's last primary
-  int pending = 0;
-  V3 px{0, 0, 0}, pw{0, 0, 0};
-  long prim = 0;
-  int sub = 0;
-  long nrec = 0;
-  // counters
-  unsigned c_steps = 0, c_pe = 0, c_co = 0, c_pair = 0, c_cross = 0, c_esc = 0, c_cut = 0, c_push = 0,
-           c_stuck = 0, c_trunc = 0, c_tracks = 0, c_short = 0, c_invalid = 0;
-  NavCount nc{};
+template <bool LOG>
+__device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, int T, int code, double step,
+                                        double edep, double energy) {
+  if (LOG) {
+    int n = P.nrec[s];
+    if (n < a.log_cap) {
+      int sub = P.sub_pend[s] & 15;
+      a.log[(long)(3 * P.prim[s] + sub) * a.log_cap + n] = gnav_logrec{T - P.tbase[s], code, step, edep, energy};
+    }
+    P.nrec[s] = n + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Learned order: one wave scores up to 64 queued steps with the network on
+// bf16 MFMA (v_mfma_f32_16x16x16_bf16, float accumulation), 16 queries per
+// M tile.  Per lane l: A rows m = l % 16, k = 4 (l / 16) + 0..3; B columns
+// n = l % 16, same k; D columns n = l % 16, rows 4 (l / 16) + 0..3.  Hidden
+// activations pass through a per-wave LDS tile [16][128] bf16; the logits
+// reuse it as [16][64] float.  The predicted position is the argmax.
+// ---------------------------------------------------------------------------
+
+typedef short lbf16x4 __attribute__((ext_vector_type(4)));
+typedef float lf32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t lf2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float lbf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+struct LearnScratch {
+  uint16_t h[kWaves][16][128];  // activations (bf16) / logits as float [16][64]
+  int cls[kWaves][16];
+};
+
+__device__ __forceinline__ void learned_predict(const TransportArgs& a, Pool& P, LearnScratch& S, int n) {
+  const DevGeom& G = a.G;
+  const MlpView& M = a.mlp;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  uint16_t (*h)[128] = S.h[w];
+  float (*lg)[64] = reinterpret_cast<float (*)[64]>(&S.h[w][0][0]);
+  for (int mt = 0; mt < 4; mt++) {
+    const int row0 = w * 64 + mt * 16;
+    if (row0 >= n) break;
+    // features of row r: point in the mother frame over the grid half size, direction
+    const int li = row0 + r;
+    const bool valid = li < n;
+    float f[6] = {0, 0, 0, 0, 0, 0};
+    int cls = 0;
+    if (valid) {
+      const int s = P.list[li];
+      const int lvk = P.lvk[s];
+      const LRec& L = G.lv[lvk >> 1];
+      V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
+      V3 pl, vl;
+      touchable_frame(G, P.T[s], lvk & 1, x, v, pl, vl);
+      const double pc[3] = {pl.x, pl.y, pl.z};
+#pragma unroll
+      for (int ax = 0; ax < 3; ax++) {
+        double half = 0.5 * L.n[ax] * L.vw[ax];
+        f[ax] = (float)((pc[ax] - (L.vlo[ax] + half)) / half);
+      }
+      f[3] = (float)vl.x;
+      f[4] = (float)vl.y;
+      f[5] = (float)vl.z;
+      cls = L.lclass;
+      cls = cls < 0 ? 0 : (cls >= M.n_class ? M.n_class - 1 : cls);
+    }
+    if (q == 0) S.cls[w][r] = cls;
+    lbf16x4 xa;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int k = 4 * q + j;
+      xa[j] = (short)(k < 6 ? lf2bf(f[k]) : 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // layer 1: [16 x 16] x [16 x 128] (K padded from 6), + b1 + W1m[cls], ReLU
+    for (int ct = 0; ct < 8; ct++) {
+      const int nn = 16 * ct + r;
+      lbf16x4 wb;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int k = 4 * q + j;
+        wb[j] = (short)(k < 6 ? M.w1x[nn * 6 + k] : 0);
+      }
+      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, wb, acc, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        int row = 4 * q + j;
+        float v = acc[j] + lbf2f(M.w1m[(long)S.cls[w][row] * 128 + nn]) + M.b1[nn];
+        h[row][nn] = lf2bf(v > 0.f ? v : 0.f);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // layer 2: [16 x 128] x [128 x 128], + b2, ReLU (result kept in registers, then stored)
+    lf32x4 acc2[8];
+    for (int ct = 0; ct < 8; ct++) {
+      const int nn = 16 * ct + r;
+      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int kt = 0; kt < 8; kt++) {
+        const int k0 = 16 * kt + 4 * q;
+        lbf16x4 av, bv;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          av[j] = (short)h[r][k0 + j];
+          bv[j] = (short)M.w2[nn * 128 + k0 + j];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+      acc2[ct] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int ct = 0; ct < 8; ct++) {
+      const int nn = 16 * ct + r;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        float v = acc2[ct][j] + M.b2[nn];
+        h[4 * q + j][nn] = lf2bf(v > 0.f ? v : 0.f);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // layer 3: [16 x 128] x [128 x 64], + b3 -> logits
+    lf32x4 acc3[4];
+    for (int ct = 0; ct < 4; ct++) {
+      const int nn = 16 * ct + r;
+      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int kt = 0; kt < 8; kt++) {
+        const int k0 = 16 * kt + 4 * q;
+        lbf16x4 av, bv;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          av[j] = (short)h[r][k0 + j];
+          bv[j] = (short)M.w3[nn * 128 + k0 + j];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+      acc3[ct] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int ct = 0; ct < 4; ct++) {
+      const int nn = 16 * ct + r;
+#pragma unroll
+      for (int j = 0; j < 4; j++) lg[4 * q + j][nn] = acc3[ct][j] + M.b3[nn];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (q == 0 && valid) {
+      int best = 0;
+      float bv = lg[r][0];
+      for (int c = 1; c < 64; c++) {
+        float v = lg[r][c];
+        if (v > bv) {
+          bv = v;
+          best = c;
+        }
+      }
+      P.pred[P.list[li]] = best;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <bool LOG, bool COUNT, int ORDER>
+__global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
+  const DevGeom& G = a.G;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  __shared__ Pool P;
+  double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
+
+  if (tid < GNAV_NCOUNTERS) P.cnt[tid] = 0ull;
+  P.status[tid] = kEmpty;
+  P.sub_pend[tid] = 0;
+  NavCount<COUNT> nc;
   bool queue_open = true;
+  __syncthreads();
 
   for (;;) {
-    // ---- start a track on lanes without one --------------------------------
-    bool start = false;
-    if (!alive && pending > 0) {
-      sub = 3 - pending;
-      pending--;
-      x = px;
-      v = (sub == 1) ? pw : V3{-pw.x, -pw.y, -pw.z};
-      E = kMe;
-      key = (key & ~3u) | (uint32_t)sub;
-      start = true;
-    }
-    bool need = !alive && !start;
-    if (queue_open) {
-      unsigned long long mask = __ballot(need);
-      if (mask) {
-        int cnt = __popcll(mask);
-        int leader = __ffsll((long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)cnt);
-        base = __shfl(base, leader);
-        if (base + cnt >= (unsigned long long)a.n) queue_open = false;
-        if (need) {
-          unsigned long long idx = base + __popcll(mask & lt_mask);
-          if (idx < (unsigned long long)a.n) {
-            prim = (long)idx;
-            sub = 0;
-            x = V3{a.pos[3 * prim], a.pos[3 * prim + 1], a.pos[3 * prim + 2]};
-            v = V3{a.dir[3 * prim], a.dir[3 * prim + 1], a.dir[3 * prim + 2]};
-            E = a.energy[prim];
-            event = a.event[prim];
-            key = ((uint32_t)a.prim_id[prim]) << 2;
-            int g = a.geom_default;
-            bool ok = event >= 0 && event < a.n_events;
-            if (ok && a.event_geom) g = a.event_geom[event];
-            ok = ok && g >= 0 && g < a.n_geoms && E > 0 && isfinite(E) && isfinite(x.x) &&
-                 isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
-            if (ok) {
-              tbase = a.geom_tbase[g];
-              start = true;
-            } else {
-              c_invalid++;
+    // ---- refill: thread tid owns slot tid ---------------------------------
+    {
+      const int s = tid;
+      bool empty = P.status[s] == kEmpty;
+      int sp = P.sub_pend[s];
+      int pending = sp >> 4;
+      bool start = false;
+      if (empty && pending > 0) {
+        int sub = 3 - pending;
+        P.sub_pend[s] = sub | ((pending - 1) << 4);
+        P.x[s] = my_pend[0];
+        P.y[s] = my_pend[1];
+        P.z[s] = my_pend[2];
+        double sgn = (sub == 1) ? 1.0 : -1.0;
+        P.vx[s] = sgn * my_pend[3];
+        P.vy[s] = sgn * my_pend[4];
+        P.vz[s] = sgn * my_pend[5];
+        P.E[s] = kMe;
+        P.key[s] = (P.key[s] & ~3) | sub;
+        start = true;
+      }
+      bool need = empty && !start;
+      if (queue_open) {
+        unsigned long long mask = __ballot(need);
+        if (mask) {
+          int cnt = __popcll(mask);
+          int leader = __ffsll((long long)mask) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)cnt);
+          base = __shfl(base, leader);
+          if (base + cnt >= (unsigned long long)a.n) queue_open = false;
+          if (need) {
+            unsigned long long idx = base + __popcll(mask & lt_mask);
+            if (idx < (unsigned long long)a.n) {
+              V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
+              V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
+              double E = a.energy[idx];
+              int event = a.event[idx];
+              int g = a.geom_default;
+              bool ok = event >= 0 && event < a.n_events;
+              if (ok && a.event_geom) g = a.event_geom[event];
+              ok = ok && g >= 0 && g < a.n_geoms && E > 0 && isfinite(E) && isfinite(x.x) && isfinite(x.y) &&
+                   isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
+              if (ok) {
+                P.x[s] = x.x;
+                P.y[s] = x.y;
+                P.z[s] = x.z;
+                P.vx[s] = v.x;
+                P.vy[s] = v.y;
+                P.vz[s] = v.z;
+                P.E[s] = E;
+                P.event[s] = event;
+                P.key[s] = a.prim_id[idx] << 2;
+                P.tbase[s] = a.geom_tbase[g];
+                P.prim[s] = (int)idx;
+                P.sub_pend[s] = 0;
+                start = true;
+              } else {
+                atomicAdd(&P.cnt[GNAV_C_INVALID], 1ull);
+              }
             }
           }
         }
       }
-    }
-    if (!__any(alive || start)) break;
-    if (start) {
-      // every track is located from the world of its geometry (touchable tbase)
-      c_tracks++;
-      nrec = 0;
-      rng_start(rs, a.seed, (uint32_t)event, key);
-      T = locate(G, tbase, x, true, v, nc);
-      if (T < 0) {
-        atomic_add_f64(a.esc_ev + event, E);
-        c_esc++;
-        if (LOG) {
-          a.log_n[3 * prim + sub] = 0;
-          a.log_fate[3 * prim + sub] = GNAV_FATE_ESCAPED;
-        }
-      } else {
-        nl = -log(rng_next(rs));
-        alive = true;
-        zero = 0;
-        steps = 0;
-        safety = 0.0;
-        mat_cached = -1;
+      if (start) {
+        P.status[s] = kNav;
+        P.aux[s] = kNavStart;
+        P.T[s] = P.tbase[s];
       }
     }
-    if (!alive) continue;
+    if (!__syncthreads_or(P.status[tid] != kEmpty)) break;
 
-    // ---- one transport step ------------------------------------------------
-    int fate = 0;
-    if (E < a.ecut) {
-      atomic_add_f64(a.edep_t + T, E);
-      atomic_add_f64(a.edep_ev + event, E);
-      c_cut++;
-      fate = GNAV_FATE_CUTOFF;
-    } else if (steps >= a.max_steps) {
-      c_trunc++;
-      fate = GNAV_FATE_TRUNCATED;
-    } else {
-      int mat = G.lv_mat[G.t_lv[T]];
-      if (mat != mat_cached) {
-        mu_lookup(G, mat, E, mpe, mco, mpp);
-        mat_cached = mat;
+    // ---- navigate: track starts and boundary crossings --------------------
+    {
+      int n = compact<1>(P, P.status[tid] == kNav, 0);
+      if (tid < n) {
+        const int s = P.list[tid];
+        const int mode = P.aux[s] & 3;
+        const int lim = P.aux[s] >> 2;
+        V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
+        if (mode == kNavStart) {
+          atomicAdd(&P.cnt[GNAV_C_TRACKS], 1ull);
+          P.draw[s] = 0;
+          P.nrec[s] = 0;
+          P.zero_steps[s] = 0;
+          P.cnt_a[s] = 0;
+          P.cnt_b[s] = 0;
+          P.saf[s] = 0.0;
+        }
+        int lvk = 0;
+        int nt = navigate(G, mode, P.T[s], lim, x, v, lvk, nc);
+        if (nt < 0) {
+          atomic_add_f64(a.esc_ev + P.event[s], P.E[s]);
+          end_track<LOG>(P, a, s, GNAV_FATE_ESCAPED, P.zero_steps[s] >> 8);
+        } else {
+          P.T[s] = nt;
+          P.lvk[s] = lvk;
+          P.status[s] = kStep;
+          if (mode == kNavStart) {
+            Philox rs{(uint32_t)P.event[s], (uint32_t)P.key[s], 0u};
+            P.nl[s] = -log(rng_next(rs, a.seed_lo, a.seed_hi));
+            P.draw[s] = (int)rs.draw;
+            int imu;
+            double w;
+            mu_index(G, P.E[s], imu, w);
+            P.imu_mat[s] = imu;  // no cached material
+            P.wmu[s] = w;
+          }
+        }
       }
-      double mu = mpe + mco + mpp;
-      double s_phys = mu > 0 ? nl / mu : kInf;
-      bool phys;
-      double s_geo = kInf;
-      int lim = kLimMother;
-      if (s_phys < safety - kTol) {
-        phys = true;
-        c_short++;
-      } else {
-        V3 pl, vl;
-        touchable_frame(G, T, x, v, pl, vl);
-        double saf;
-        s_geo = compute_step(G, G.t_lv[T], pl, vl, lim, saf, nc);
-        safety = saf;
-        phys = s_phys <= s_geo;
+      __syncthreads();
+    }
+
+    // ---- learned order: score the steps whose mother has a voxel grid -------
+    if constexpr (ORDER == kOrderLearned) {
+      __shared__ LearnScratch S;
+      bool elig = false;
+      if (P.status[tid] == kStep) elig = G.lv[P.lvk[tid] >> 1].lclass >= 0;
+      P.pred[tid] = -1;
+      int n = compact<1>(P, elig, 0);
+      learned_predict(a, P, S, n);
+      __syncthreads();
+    }
+
+    // ---- step: mu, safety shortcut or ComputeStep, advance ------------------
+    {
+      int key = 0;
+      if (P.status[tid] == kStep) {
+        const LRec& L = G.lv[P.lvk[tid] >> 1];
+        key = (L.info & 3) | (L.dau_cnt > 0 ? 4 : 0);
       }
-      steps++;
-      c_steps++;
-      if (phys) {
-        x = V3{x.x + s_phys * v.x, x.y + s_phys * v.y, x.z + s_phys * v.z};
-        safety -= s_phys;
-        zero = 0;
-        double u = rng_next(rs) * mu;
-        if (u < mpe) {
+      int n = compact<8>(P, P.status[tid] == kStep, key);
+      if (tid < n) {
+        const int s = P.list[tid];
+        const int T = P.T[s];
+        const int lvk = P.lvk[s];
+        const LRec& L = G.lv[lvk >> 1];
+        double E = P.E[s];
+        int zs = P.zero_steps[s];
+        int steps = zs >> 8;
+        int zero = zs & 0xFF;
+        if (E < a.ecut) {
+          atomic_add_f64(a.edep_t + T, E);
+          atomic_add_f64(a.edep_ev + P.event[s], E);
+          end_track<LOG>(P, a, s, GNAV_FATE_CUTOFF, steps);
+        } else if (steps >= a.max_steps) {
+          end_track<LOG>(P, a, s, GNAV_FATE_TRUNCATED, steps);
+        } else {
+          const int mat = L.mat;
+          int im = P.imu_mat[s];
+          const int imu = im & 511;
+          const double wmu = P.wmu[s];
+          double mu;
+          if ((im >> 9) != mat + 1) {
+            double pe, co, pp;
+            mu_parts(G, mat, imu, wmu, E, pe, co, pp);
+            mu = pe + co + pp;
+            P.mu[s] = mu;
+            P.imu_mat[s] = imu | ((mat + 1) << 9);
+          } else {
+            mu = P.mu[s];
+          }
+          double nl = P.nl[s];
+          double safety = P.saf[s];
+          V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
+          double s_phys = mu > 0 ? nl / mu : kInf;
+          bool phys;
+          double s_geo = kInf;
+          int lim = kLimMother;
+          if (s_phys < safety - kTol) {
+            phys = true;
+            P.cnt_a[s] += 1u << 16;
+          } else {
+            V3 pl, vl;
+            touchable_frame(G, T, lvk & 1, x, v, pl, vl);
+            double saf;
+            int2 nd;
+            s_geo = compute_step<COUNT, ORDER>(G, L, pl, vl, lim, saf, nc,
+                                               ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
+            safety = saf;
+            phys = s_phys <= s_geo;
+            // crossing recorder: a daughter-limited step from a node with 2+ candidates
+            if (a.rec && !phys && lim >= 0 && nd.y >= 2 && L.lclass >= 0) {
+              int label = -1;
+              for (int c = 0; c < nd.y && c < 64; c++)
+                if (G.vox_cand[nd.x + c] == lim) label = c;
+              if (label >= 0) {
+                unsigned long long ri = atomicAdd(a.rec_count, 1ull);
+                if (ri < (unsigned long long)a.rec_cap) {
+                  gnav_crossing cr;
+                  cr.cls = L.lclass;
+                  const double pc[3] = {pl.x, pl.y, pl.z};
+#pragma unroll
+                  for (int ax = 0; ax < 3; ax++) {
+                    double half = 0.5 * L.n[ax] * L.vw[ax];
+                    cr.x[ax] = (float)((pc[ax] - (L.vlo[ax] + half)) / half);
+                  }
+                  cr.v[0] = (float)vl.x;
+                  cr.v[1] = (float)vl.y;
+                  cr.v[2] = (float)vl.z;
+                  cr.label = label;
+                  a.rec[ri] = cr;
+                }
+              }
+            }
+          }
+          steps++;
+          if (phys) {
+            P.x[s] = x.x + s_phys * v.x;
+            P.y[s] = x.y + s_phys * v.y;
+            P.z[s] = x.z + s_phys * v.z;
+            P.saf[s] = safety - s_phys;
+            P.zero_steps[s] = steps << 8;
+            // process choice: the first draw after the step (u mu against the partial sums)
+            double pe, co, pp;
+            mu_parts(G, mat, imu, wmu, E, pe, co, pp);
+            Philox rs{(uint32_t)P.event[s], (uint32_t)P.key[s], (uint32_t)P.draw[s]};
+            double u = rng_next(rs, a.seed_lo, a.seed_hi) * mu;
+            P.draw[s] = (int)rs.draw;
+            P.aux[s] = u < pe ? kProcPE : (u < pe + co ? kProcCompton : kProcPair);
+            P.slast[s] = s_phys;
+            P.status[s] = kInt;
+          } else {
+            P.x[s] = x.x + s_geo * v.x;
+            P.y[s] = x.y + s_geo * v.y;
+            P.z[s] = x.z + s_geo * v.z;
+            if (mu > 0) {
+              nl = nl - s_geo * mu;
+              if (nl < 0) nl = 0;
+              P.nl[s] = nl;
+            }
+            log_rec<LOG>(P, a, s, T, lim, s_geo, 0.0, E);
+            P.cnt_b[s] += 1u;
+            P.saf[s] = 0.0;
+            zero = (s_geo < kTol) ? zero + 1 : 0;
+            P.zero_steps[s] = (steps << 8) | zero;
+            if (zero >= kZeroKill) {
+              atomic_add_f64(a.edep_t + T, E);
+              atomic_add_f64(a.edep_ev + P.event[s], E);
+              end_track<LOG>(P, a, s, GNAV_FATE_STUCK, steps);
+            } else {
+              if (zero > 0 && zero % kZeroPush == 0) {
+                P.x[s] = P.x[s] + 100.0 * kTol * v.x;
+                P.y[s] = P.y[s] + 100.0 * kTol * v.y;
+                P.z[s] = P.z[s] + 100.0 * kTol * v.z;
+                P.cnt_b[s] += 1u << 24;
+              }
+              // relocation happens in the next iteration's navigation phase
+              P.aux[s] = (lim >= 0 ? kNavEnter : kNavExit) | (lim << 2);
+              P.status[s] = kNav;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- interact: photoelectric, Compton, pair ------------------------------
+    {
+      int n = compact<3>(P, P.status[tid] == kInt, P.aux[tid]);
+      if (tid < n) {
+        const int s = P.list[tid];
+        const int proc = P.aux[s];
+        const int T = P.T[s];
+        const int event = P.event[s];
+        const double E = P.E[s];
+        const double sl = P.slast[s];
+        const int steps = P.zero_steps[s] >> 8;
+        Philox rs{(uint32_t)event, (uint32_t)P.key[s], (uint32_t)P.draw[s]};
+        if (proc == kProcPE) {
           atomic_add_f64(a.edep_t + T, E);
           atomic_add_f64(a.edep_ev + event, E);
-          c_pe++;
-          if (LOG && nrec < a.log_cap) {
-            a.log[(3 * prim + sub) * a.log_cap + nrec] = gnav_logrec{T - tbase, kLimPE, s_phys, E, 0.0};
-          }
-          nrec++;
-          fate = GNAV_FATE_ABSORBED;
-        } else if (u < mpe + mco) {
+          log_rec<LOG>(P, a, s, T, kLimPE, sl, E, 0.0);
+          end_track<LOG>(P, a, s, GNAV_FATE_ABSORBED, steps);
+        } else if (proc == kProcCompton) {
           double eps, onecost, sint2;
-          compton_sample(E, rs, eps, onecost, sint2);
-          double phi = kTwoPi * rng_next(rs);
+          compton_sample(E, rs, a.seed_lo, a.seed_hi, eps, onecost, sint2);
+          double phi = kTwoPi * rng_next(rs, a.seed_lo, a.seed_hi);
+          V3 v{P.vx[s], P.vy[s], P.vz[s]};
           rotate_dir(v, 1.0 - onecost, sqrt(sint2), phi);
+          P.vx[s] = v.x;
+          P.vy[s] = v.y;
+          P.vz[s] = v.z;
           double dep = E * (1.0 - eps);
-          E = eps * E;
-          mat_cached = -1;
+          double E2 = eps * E;
+          P.E[s] = E2;
+          int imu;
+          double w;
+          mu_index(G, E2, imu, w);
+          P.imu_mat[s] = imu;  // cached mu invalid
+          P.wmu[s] = w;
           atomic_add_f64(a.edep_t + T, dep);
           atomic_add_f64(a.edep_ev + event, dep);
-          c_co++;
-          if (LOG && nrec < a.log_cap) {
-            a.log[(3 * prim + sub) * a.log_cap + nrec] =
-                gnav_logrec{T - tbase, kLimCompton, s_phys, dep, E};
-          }
-          nrec++;
-          nl = -log(rng_next(rs));
+          P.cnt_a[s] += 1u;
+          log_rec<LOG>(P, a, s, T, kLimCompton, sl, dep, E2);
+          P.nl[s] = -log(rng_next(rs, a.seed_lo, a.seed_hi));
+          P.draw[s] = (int)rs.draw;
+          P.status[s] = kStep;
         } else {
           double dep = E - 2.0 * kMe;
           atomic_add_f64(a.edep_t + T, dep);
           atomic_add_f64(a.edep_ev + event, dep);
-          c_pair++;
-          double u1 = rng_next(rs), u2 = rng_next(rs);
+          double u1 = rng_next(rs, a.seed_lo, a.seed_hi), u2 = rng_next(rs, a.seed_lo, a.seed_hi);
           double ct = 1.0 - 2.0 * u1;
           double st = 2.0 * sqrt(u1 * (1.0 - u1));
           double ph = kTwoPi * u2;
-          pw = V3{st * cos(ph), st * sin(ph), ct};
-          px = x;
-          pending = 2;
-          if (LOG && nrec < a.log_cap) {
-            a.log[(3 * prim + sub) * a.log_cap + nrec] = gnav_logrec{T - tbase, kLimPair, s_phys, dep, 0.0};
-          }
-          nrec++;
-          fate = GNAV_FATE_PAIR;
-        }
-      } else {
-        x = V3{x.x + s_geo * v.x, x.y + s_geo * v.y, x.z + s_geo * v.z};
-        if (mu > 0) {
-          nl = nl - s_geo * mu;
-          if (nl < 0) nl = 0;
-        }
-        if (LOG && nrec < a.log_cap) {
-          a.log[(3 * prim + sub) * a.log_cap + nrec] = gnav_logrec{T - tbase, lim, s_geo, 0.0, E};
-        }
-        nrec++;
-        c_cross++;
-        safety = 0.0;
-        zero = (s_geo < kTol) ? zero + 1 : 0;
-        if (zero >= kZeroKill) {
-          atomic_add_f64(a.edep_t + T, E);
-          atomic_add_f64(a.edep_ev + event, E);
-          c_stuck++;
-          fate = GNAV_FATE_STUCK;
-        } else {
-          if (zero > 0 && zero % kZeroPush == 0) {
-            x = V3{x.x + 100.0 * kTol * v.x, x.y + 100.0 * kTol * v.y, x.z + 100.0 * kTol * v.z};
-            c_push++;
-          }
-          int nt = relocate(G, T, x, v, lim, nc);
-          if (nt < 0) {
-            atomic_add_f64(a.esc_ev + event, E);
-            c_esc++;
-            fate = GNAV_FATE_ESCAPED;
-          } else {
-            T = nt;
-          }
+          double* pd = a.pend + ((long)blockIdx.x * kPool + s) * 6;
+          pd[0] = P.x[s];
+          pd[1] = P.y[s];
+          pd[2] = P.z[s];
+          pd[3] = st * cos(ph);
+          pd[4] = st * sin(ph);
+          pd[5] = ct;
+          P.sub_pend[s] = (P.sub_pend[s] & 15) | (2 << 4);
+          log_rec<LOG>(P, a, s, T, kLimPair, sl, dep, 0.0);
+          end_track<LOG>(P, a, s, GNAV_FATE_PAIR, steps);
         }
       }
-    }
-    if (fate != 0) {
-      alive = false;
-      if (LOG) {
-        a.log_n[3 * prim + sub] = (int)(nrec > 0x7fffffff ? 0x7fffffff : nrec);
-        a.log_fate[3 * prim + sub] = fate;
-      }
+      __syncthreads();
     }
   }
 
-  // ---- flush counters: wave reduction, one atomic per counter per wave ----
-  unsigned vals[GNAV_NCOUNTERS] = {c_steps, c_pe,    c_co,    c_pair,  c_cross,    c_esc,
-                                   c_cut,   c_push,  c_stuck, c_trunc, c_tracks,   c_short,
-                                   nc.dist_in, nc.dist_out, nc.inside, nc.nodes, c_invalid};
+  // ---- flush counters -------------------------------------------------------
+  if (COUNT) {
+    unsigned vals[4] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes};
+    const int slots[4] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES};
 #pragma unroll
-  for (int c = 0; c < GNAV_NCOUNTERS; c++) {
-    unsigned long long s = vals[c];
+    for (int c = 0; c < 4; c++) {
+      unsigned long long sum = vals[c];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0 && s) atomicAdd(a.counters + c, s);
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (lane == 0 && sum) atomicAdd(&P.cnt[slots[c]], sum);
+    }
   }
+  __syncthreads();
+  if (tid < GNAV_NCOUNTERS && P.cnt[tid]) atomicAdd(a.counters + tid, P.cnt[tid]);
 }
 
 // Zero a small device array (a kernel rather than a memset node, so the
@@ -488,23 +893,44 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   a.geom_tbase = L.geom_tbase;
   a.n_geoms = L.n_geoms;
   a.n_events = L.n_events;
-  a.seed = L.seed;
+  a.seed_lo = (uint32_t)L.seed;
+  a.seed_hi = (uint32_t)(L.seed >> 32);
   a.ecut = L.ecut;
-  a.max_steps = L.max_steps;
+  a.max_steps = (int)std::min<long>(L.max_steps, 0x7fffffff);
   a.edep_t = L.edep_t;
   a.edep_ev = L.edep_ev;
   a.esc_ev = L.esc_ev;
   a.counters = L.counters;
   a.queue = L.queue;
+  a.pend = L.pend;
   a.log = L.log;
   a.log_cap = L.log_cap;
   a.log_n = L.log_n;
   a.log_fate = L.log_fate;
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, L.queue, 1);
   if (L.n <= 0) return hipGetLastError();
-  dim3 grid(L.grid), block(L.block);
-  if (L.log) hipLaunchKernelGGL(k_transport<true>, grid, block, 0, st, a);
-  else hipLaunchKernelGGL(k_transport<false>, grid, block, 0, st, a);
+  a.rec = L.rec;
+  a.rec_cap = L.rec_cap;
+  a.rec_count = L.rec_count;
+  a.mlp = L.mlp;
+  dim3 grid(L.grid), block(kPool);
+#define GNAV_LAUNCH(LOGV, CNTV, ORDV) \
+  hipLaunchKernelGGL((k_transport<LOGV, CNTV, ORDV>), grid, block, 0, st, a)
+#define GNAV_LAUNCH_ORDER(LOGV, CNTV)                                   \
+  do {                                                                  \
+    if (L.order == kOrderBound) GNAV_LAUNCH(LOGV, CNTV, kOrderBound);   \
+    else if (L.order == kOrderLearned) GNAV_LAUNCH(LOGV, CNTV, kOrderLearned); \
+    else GNAV_LAUNCH(LOGV, CNTV, kOrderPlain);                          \
+  } while (0)
+  if (L.log) {
+    if (L.count) GNAV_LAUNCH_ORDER(true, true);
+    else GNAV_LAUNCH_ORDER(true, false);
+  } else {
+    if (L.count) GNAV_LAUNCH_ORDER(false, true);
+    else GNAV_LAUNCH_ORDER(false, false);
+  }
+#undef GNAV_LAUNCH_ORDER
+#undef GNAV_LAUNCH
   return hipGetLastError();
 }
 

@@ -1,0 +1,402 @@
+// gnav_mlp.hip -- training kernels of the candidate-ordering MLP (bf16 MFMA,
+// float32 accumulation) and their C ABI.
+//
+// The network scores the candidates of a voxel node during ComputeStep:
+// inputs are the point and direction in the mother frame (6 values) and the
+// mother volume (a class id, realised as a row gather of the first layer's
+// weights); two hidden layers of 128 ReLU units; 64 logits, one per candidate
+// position.  Training data are crossings recorded by the transport itself.
+//
+// Matrix products use v_mfma_f32_16x16x16_bf16: each wave computes one 16x16
+// output tile, K in steps of 16.  Operand layout per lane l (wave64):
+//   A (16 x 16, rows m, columns k): row m = l % 16, k = 4 (l / 16) + 0..3
+//   B (16 x 16, rows k, columns n): column n = l % 16, k = 4 (l / 16) + 0..3
+//   D (16 x 16 float):              column n = l % 16, rows 4 (l / 16) + 0..3
+// Element-wise work (bias, ReLU, masks, casts, softmax) runs on the VALU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gnav.h"
+#include "gnav_internal.h"
+
+namespace gnav {
+
+constexpr int kNIn = 6, kNH = 128, kNOut = 64;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// C[m][n] = sum_k A(m, k) B(k, n); A(m, k) = A[m * sam + k * sak], B(k, n) =
+// B[k * sbk + n * sbn] (bf16 bits), C float with row stride ldc.  M, N, K are
+// multiples of 16.  One wave per 16x16 tile; grid covers all tiles.
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A,
+                                                   long sam, long sak, const uint16_t* __restrict__ B,
+                                                   long sbk, long sbn, float* __restrict__ C, long ldc) {
+  const int lane = threadIdx.x & 63;
+  const long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int tn = N / 16;
+  const long tiles = (long)(M / 16) * tn;
+  if (tile >= tiles) return;
+  const int m0 = (int)(tile / tn) * 16, n0 = (int)(tile % tn) * 16;
+  const int r = lane & 15, q = lane >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      int k = k0 + 4 * q + j;
+      a[j] = (short)A[(long)(m0 + r) * sam + (long)k * sak];
+      b[j] = (short)B[(long)k * sbk + (long)(n0 + r) * sbn];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; j++) C[(long)(m0 + 4 * q + j) * ldc + (n0 + r)] = acc[j];
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = f2bf(src[i]);
+}
+
+// Layer 1: A1 = bf16(x) W1x^T + W1m[cls] + b1 (float), H1b = bf16(ReLU(A1)).
+__global__ void k_layer1(int B, const float* __restrict__ x, const int* __restrict__ cls, int n_class,
+                         const uint16_t* __restrict__ w1x, const uint16_t* __restrict__ w1m,
+                         const float* __restrict__ b1, uint16_t* __restrict__ xb, float* __restrict__ a1,
+                         uint16_t* __restrict__ h1b) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)B * kNH) return;
+  int b = (int)(i / kNH), h = (int)(i % kNH);
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < kNIn; k++) acc += bf2f(f2bf(x[b * kNIn + k])) * bf2f(w1x[h * kNIn + k]);
+  int c = cls[b];
+  c = c < 0 ? 0 : (c >= n_class ? n_class - 1 : c);
+  float v = acc + bf2f(w1m[(long)c * kNH + h]) + b1[h];
+  a1[i] = v;
+  h1b[i] = f2bf(v > 0.f ? v : 0.f);
+  if (h < kNIn) xb[b * 16 + h] = f2bf(x[b * kNIn + h]);
+}
+
+// In place: A += bias; H = bf16(ReLU(A)).
+__global__ void k_bias_relu(long n, int N, float* __restrict__ a, const float* __restrict__ bias,
+                            uint16_t* __restrict__ hb) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float v = a[i] + bias[i % N];
+    a[i] = v;
+    hb[i] = f2bf(v > 0.f ? v : 0.f);
+  }
+}
+
+// Softmax cross-entropy over 64 logits per sample (one wave per sample):
+// dZ = (softmax(z) - onehot(label)) / B, loss += (lse - z_label) / B.
+__global__ void k_softmax_ce(int B, float* __restrict__ z, const float* __restrict__ b3,
+                             const int* __restrict__ label, float* __restrict__ dz, uint16_t* __restrict__ dzb,
+                             float* __restrict__ loss) {
+  const int lane = threadIdx.x & 63;
+  const long b = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= B) return;
+  float v = z[b * kNOut + lane] + b3[lane];
+  z[b * kNOut + lane] = v;
+  float mx = v;
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  float e = expf(v - mx);
+  float s = e;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  int lab = label[b];
+  float g = (e / s - (lane == lab ? 1.f : 0.f)) / (float)B;
+  dz[b * kNOut + lane] = g;
+  dzb[b * kNOut + lane] = f2bf(g);
+  if (lane == lab && loss) atomicAdd(loss, (logf(s) - (v - mx)) / (float)B);
+}
+
+// In place: A += bias (no activation; the logits).
+__global__ void k_bias_relu_noact(long n, int N, float* __restrict__ a, const float* __restrict__ bias) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    a[i] = a[i] + bias[i % N];
+}
+
+// dA = dH * 1[A > 0]; dAb = bf16(dA).
+__global__ void k_relu_grad(long n, float* __restrict__ dh, const float* __restrict__ a,
+                            uint16_t* __restrict__ dab) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float g = a[i] > 0.f ? dh[i] : 0.f;
+    dh[i] = g;
+    dab[i] = f2bf(g);
+  }
+}
+
+// Column sums of a [B x N] float matrix (bias gradients): one thread per column.
+__global__ void k_colsum(int B, int N, const float* __restrict__ d, float* __restrict__ out) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; b++) s += d[(long)b * N + n];
+  out[n] = s;
+}
+
+// First-layer gradients: dW1x[h][k] = sum_b bf16(dA1)[b][h] bf16(x)[b][k];
+// dW1m[cls[b]][h] += dA1[b][h] (float).  One thread per (h, k) or per (b, h).
+__global__ void k_w1_grads(int B, int n_class, const float* __restrict__ da1, const uint16_t* __restrict__ da1b,
+                           const uint16_t* __restrict__ xb, const int* __restrict__ cls,
+                           float* __restrict__ dw1x, float* __restrict__ dw1m) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kNH * kNIn) {
+    int h = (int)(i / kNIn), k = (int)(i % kNIn);
+    float s = 0.f;
+    for (int b = 0; b < B; b++) s += bf2f(da1b[(long)b * kNH + h]) * bf2f(xb[b * 16 + k]);
+    dw1x[i] = s;
+  }
+  long j = i;
+  if (j < (long)B * kNH) {
+    int b = (int)(j / kNH), h = (int)(j % kNH);
+    int c = cls[b];
+    c = c < 0 ? 0 : (c >= n_class ? n_class - 1 : c);
+    atomicAdd(&dw1m[(long)c * kNH + h], da1[j]);
+  }
+}
+
+// Adam on the float master copy; refreshes the bf16 copy.
+__global__ void k_adam(long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ pb, float lr, float c1, float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float mh = mi / c1, vh = vi / c2;
+    float w = p[i] - lr * mh / (sqrtf(vh) + eps);
+    p[i] = w;
+    pb[i] = f2bf(w);
+  }
+}
+
+}  // namespace gnav
+
+using namespace gnav;
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct gnav_mlp {
+  int n_class = 0, max_batch = 0;
+  long n_params = 0;
+  long o_w1x, o_w1m, o_b1, o_w2, o_b2, o_w3, o_b3;
+  long step = 0;
+  // parameters: float master, bf16 copy, gradients, Adam moments
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t* pb = nullptr;
+  // activations for max_batch samples
+  float *a1 = nullptr, *a2 = nullptr, *z = nullptr, *dz = nullptr, *dh = nullptr, *loss = nullptr;
+  uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *dzb = nullptr, *da2b = nullptr, *da1b = nullptr;
+  std::vector<void*> allocs;
+  ~gnav_mlp() {
+    for (void* q : allocs) (void)hipFree(q);
+  }
+  template <class T>
+  hipError_t alloc(T** ptr, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
+    if (e == hipSuccess) {
+      allocs.push_back(q);
+      *ptr = (T*)q;
+      e = hipMemset(q, 0, std::max<size_t>(count * sizeof(T), 16));
+    }
+    return e;
+  }
+};
+
+namespace gnav {
+bool mlp_view(const gnav_mlp* q, MlpView* v) {
+  if (!q || !v) return false;
+  v->w1x = q->pb + q->o_w1x;
+  v->w1m = q->pb + q->o_w1m;
+  v->w2 = q->pb + q->o_w2;
+  v->w3 = q->pb + q->o_w3;
+  v->b1 = q->p + q->o_b1;
+  v->b2 = q->p + q->o_b2;
+  v->b3 = q->p + q->o_b3;
+  v->n_class = q->n_class;
+  return true;
+}
+}  // namespace gnav
+
+namespace {
+
+unsigned blocks_for(long n, int bs = 256) { return (unsigned)std::min<long>((n + bs - 1) / bs, 65535L * 8); }
+
+hipError_t gemm(int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
+                float* C, long ldc, hipStream_t st) {
+  long tiles = (long)(M / 16) * (N / 16);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, M, N, K, A, sam, sak, B,
+                     sbk, sbn, C, ldc);
+  return hipGetLastError();
+}
+
+// Forward and backward for a batch; gradients land in mlp->g.
+hipError_t run_grad(gnav_mlp* q, int Bn, const float* x, const int* cls, const int* label, hipStream_t st) {
+  hipError_t e;
+  const uint16_t* w1x = q->pb + q->o_w1x;
+  const uint16_t* w1m = q->pb + q->o_w1m;
+  const uint16_t* w2 = q->pb + q->o_w2;
+  const uint16_t* w3 = q->pb + q->o_w3;
+  if ((e = launch_zero(q->g, (size_t)((q->n_params + 1) / 2), st)) != hipSuccess) return e;
+  if ((e = launch_zero(q->loss, 1, st)) != hipSuccess) return e;
+  // forward
+  hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, Bn, x, cls, q->n_class, w1x,
+                     w1m, q->p + q->o_b1, q->xb, q->a1, q->h1b);
+  if ((e = gemm(Bn, kNH, kNH, q->h1b, kNH, 1, w2, 1, kNH, q->a2, kNH, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bias_relu, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, kNH, q->a2,
+                     q->p + q->o_b2, q->h2b);
+  if ((e = gemm(Bn, kNOut, kNH, q->h2b, kNH, 1, w3, 1, kNH, q->z, kNOut, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_softmax_ce, dim3((unsigned)((Bn + 3) / 4)), dim3(256), 0, st, Bn, q->z, q->p + q->o_b3,
+                     label, q->dz, q->dzb, q->loss);
+  // backward
+  float* g = q->g;
+  // dW3 = dZb^T H2b : [64 x B] [B x 128]
+  if ((e = gemm(kNOut, kNH, Bn, q->dzb, 1, kNOut, q->h2b, kNH, 1, g + q->o_w3, kNH, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNOut), 0, st, Bn, kNOut, q->dz, g + q->o_b3);
+  // dH2 = dZb W3 : [B x 64] [64 x 128]
+  if ((e = gemm(Bn, kNH, kNOut, q->dzb, kNOut, 1, w3, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relu_grad, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, q->dh, q->a2,
+                     q->da2b);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNH), 0, st, Bn, kNH, q->dh, g + q->o_b2);
+  // dW2 = dA2b^T H1b : [128 x B] [B x 128]
+  if ((e = gemm(kNH, kNH, Bn, q->da2b, 1, kNH, q->h1b, kNH, 1, g + q->o_w2, kNH, st)) != hipSuccess) return e;
+  // dH1 = dA2b W2 : [B x 128] [128 x 128]
+  if ((e = gemm(Bn, kNH, kNH, q->da2b, kNH, 1, w2, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relu_grad, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, q->dh, q->a1,
+                     q->da1b);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNH), 0, st, Bn, kNH, q->dh, g + q->o_b1);
+  hipLaunchKernelGGL(k_w1_grads, dim3(blocks_for(std::max<long>((long)Bn * kNH, kNH * kNIn))), dim3(256), 0, st,
+                     Bn, q->n_class, q->dh, q->da1b, q->xb, cls, g + q->o_w1x, g + q->o_w1m);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+gnav_status gnav_mlp_create(gnav_ctx* ctx, int32_t n_class, int32_t max_batch, const float* params,
+                            gnav_mlp** out) {
+  if (!ctx || !out || !params || n_class <= 0 || n_class > 4096 || max_batch <= 0 || max_batch % 16 != 0 ||
+      max_batch > (1 << 22))
+    return GNAV_EINVAL;
+  *out = nullptr;
+  gnav_mlp* q = new (std::nothrow) gnav_mlp();
+  if (!q) return GNAV_ENOMEM;
+  q->n_class = n_class;
+  q->max_batch = max_batch;
+  long o = 0;
+  q->o_w1x = o; o += (long)kNH * kNIn;
+  q->o_w1m = o; o += (long)n_class * kNH;
+  q->o_b1 = o; o += kNH;
+  q->o_w2 = o; o += (long)kNH * kNH;
+  q->o_b2 = o; o += kNH;
+  q->o_w3 = o; o += (long)kNOut * kNH;
+  q->o_b3 = o; o += kNOut;
+  q->n_params = o;
+  long Bn = max_batch;
+  hipError_t e;
+  if ((e = q->alloc(&q->p, o)) != hipSuccess || (e = q->alloc(&q->g, o + 2)) != hipSuccess ||
+      (e = q->alloc(&q->m, o)) != hipSuccess || (e = q->alloc(&q->v, o)) != hipSuccess ||
+      (e = q->alloc(&q->pb, o)) != hipSuccess || (e = q->alloc(&q->a1, Bn * kNH)) != hipSuccess ||
+      (e = q->alloc(&q->a2, Bn * kNH)) != hipSuccess || (e = q->alloc(&q->z, Bn * kNOut)) != hipSuccess ||
+      (e = q->alloc(&q->dz, Bn * kNOut)) != hipSuccess || (e = q->alloc(&q->dh, Bn * kNH)) != hipSuccess ||
+      (e = q->alloc(&q->loss, 2)) != hipSuccess || (e = q->alloc(&q->xb, Bn * 16)) != hipSuccess ||
+      (e = q->alloc(&q->h1b, Bn * kNH)) != hipSuccess || (e = q->alloc(&q->h2b, Bn * kNH)) != hipSuccess ||
+      (e = q->alloc(&q->dzb, Bn * kNOut)) != hipSuccess || (e = q->alloc(&q->da2b, Bn * kNH)) != hipSuccess ||
+      (e = q->alloc(&q->da1b, Bn * kNH)) != hipSuccess) {
+    delete q;
+    return e == hipErrorOutOfMemory ? GNAV_ENOMEM : GNAV_EHIP;
+  }
+  if (hipMemcpy(q->p, params, o * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    delete q;
+    return GNAV_EHIP;
+  }
+  hipLaunchKernelGGL(k_cast_bf16, dim3(blocks_for(o)), dim3(256), 0, 0, q->p, q->pb, o);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    delete q;
+    return GNAV_EHIP;
+  }
+  *out = q;
+  return GNAV_OK;
+}
+
+int64_t gnav_mlp_n_params(const gnav_mlp* q) { return q ? q->n_params : -1; }
+
+gnav_status gnav_mlp_grad(gnav_ctx* ctx, gnav_mlp* q, int64_t batch, const float* x_dev, const int32_t* cls_dev,
+                          const int32_t* label_dev, float* grad_dev, float* loss_dev, void* stream) {
+  if (!ctx || !q || !x_dev || !cls_dev || !label_dev) return GNAV_EINVAL;
+  if (batch <= 0 || batch > q->max_batch || batch % 16 != 0) return GNAV_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (run_grad(q, (int)batch, x_dev, cls_dev, label_dev, st) != hipSuccess) return GNAV_EHIP;
+  if (grad_dev && hipMemcpyAsync(grad_dev, q->g, q->n_params * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+                      hipSuccess)
+    return GNAV_EHIP;
+  if (loss_dev && hipMemcpyAsync(loss_dev, q->loss, sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return GNAV_EHIP;
+  return GNAV_OK;
+}
+
+gnav_status gnav_mlp_adam(gnav_ctx* ctx, gnav_mlp* q, float lr, void* stream) {
+  if (!ctx || !q || !(lr > 0)) return GNAV_EINVAL;
+  q->step++;
+  float c1 = (float)(1.0 - std::pow(0.9, (double)q->step));
+  float c2 = (float)(1.0 - std::pow(0.999, (double)q->step));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(q->n_params)), dim3(256), 0, (hipStream_t)stream, q->n_params, q->p,
+                     q->g, q->m, q->v, q->pb, lr, c1, c2);
+  return hipGetLastError() == hipSuccess ? GNAV_OK : GNAV_EHIP;
+}
+
+gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* q, int64_t batch, const float* x_dev,
+                             const int32_t* cls_dev, float* logits_dev, void* stream) {
+  if (!ctx || !q || !x_dev || !cls_dev || !logits_dev) return GNAV_EINVAL;
+  if (batch <= 0 || batch > q->max_batch || batch % 16 != 0) return GNAV_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int Bn = (int)batch;
+  hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, Bn, x_dev, cls_dev, q->n_class,
+                     q->pb + q->o_w1x, q->pb + q->o_w1m, q->p + q->o_b1, q->xb, q->a1, q->h1b);
+  if (gemm(Bn, kNH, kNH, q->h1b, kNH, 1, q->pb + q->o_w2, 1, kNH, q->a2, kNH, st) != hipSuccess) return GNAV_EHIP;
+  hipLaunchKernelGGL(k_bias_relu, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, kNH, q->a2,
+                     q->p + q->o_b2, q->h2b);
+  if (gemm(Bn, kNOut, kNH, q->h2b, kNH, 1, q->pb + q->o_w3, 1, kNH, logits_dev, kNOut, st) != hipSuccess)
+    return GNAV_EHIP;
+  hipLaunchKernelGGL(k_bias_relu_noact, dim3(blocks_for((long)Bn * kNOut)), dim3(256), 0, st, (long)Bn * kNOut,
+                     kNOut, logits_dev, q->p + q->o_b3);
+  return hipGetLastError() == hipSuccess ? GNAV_OK : GNAV_EHIP;
+}
+
+gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* q, float* params_host) {
+  if (!ctx || !q || !params_host) return GNAV_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return GNAV_EHIP;
+  if (hipMemcpy(params_host, q->p, q->n_params * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return GNAV_EHIP;
+  return GNAV_OK;
+}
+
+gnav_status gnav_mlp_free(gnav_ctx* ctx, gnav_mlp* q) {
+  if (!ctx) return GNAV_EINVAL;
+  (void)hipDeviceSynchronize();
+  delete q;
+  return GNAV_OK;
+}
+
+}  // extern "C"

@@ -52,7 +52,9 @@ class gnav_batch(C.Structure):
         ("pos_dev", C.c_void_p), ("dir_dev", C.c_void_p), ("energy_dev", C.c_void_p),
         ("event_geom_dev", C.c_void_p), ("geom_id", C.c_int32), ("seed", C.c_uint64),
         ("e_cut", C.c_double), ("max_steps_per_track", C.c_int64), ("precision", C.c_int32),
-        ("block", C.c_int32), ("grid", C.c_int32), ("log_dev", C.c_void_p),
+        ("block", C.c_int32), ("grid", C.c_int32), ("count_work", C.c_int32),
+        ("order", C.c_int32), ("record_dev", C.c_void_p), ("record_capacity", C.c_int64),
+        ("record_count_dev", C.c_void_p), ("log_dev", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_n_dev", C.c_void_p), ("log_fate_dev", C.c_void_p),
     ]
 
@@ -78,6 +80,18 @@ def _load():
         "gnav_tally_free": ([P, P], C.c_int32),
         "gnav_transport_batch": ([P, C.POINTER(gnav_batch), P, P], C.c_int32),
         "gnav_read_tallies": ([P, P, P, P, P, P, P], C.c_int32),
+        "gnav_graph_create": ([P, C.POINTER(gnav_batch), P, P, C.POINTER(P)], C.c_int32),
+        "gnav_graph_launch": ([P, P, P], C.c_int32),
+        "gnav_graph_free": ([P, P], C.c_int32),
+        "gnav_mlp_create": ([P, C.c_int32, C.c_int32, P, C.POINTER(P)], C.c_int32),
+        "gnav_mlp_n_params": ([P], C.c_int64),
+        "gnav_mlp_grad": ([P, P, C.c_int64, P, P, P, P, P, P], C.c_int32),
+        "gnav_mlp_adam": ([P, P, C.c_float, P], C.c_int32),
+        "gnav_mlp_forward": ([P, P, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_mlp_get_params": ([P, P, P], C.c_int32),
+        "gnav_mlp_free": ([P, P], C.c_int32),
+        "gnav_ordering_classes": ([P, C.c_int32, _i32p], C.c_int32),
+        "gnav_set_mlp": ([P, C.c_int32, P], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -103,6 +117,20 @@ gnav_tally_reset = lib.gnav_tally_reset
 gnav_tally_free = lib.gnav_tally_free
 gnav_transport_batch = lib.gnav_transport_batch
 gnav_read_tallies = lib.gnav_read_tallies
+gnav_graph_create = lib.gnav_graph_create
+gnav_graph_launch = lib.gnav_graph_launch
+gnav_graph_free = lib.gnav_graph_free
+gnav_mlp_create = lib.gnav_mlp_create
+gnav_mlp_n_params = lib.gnav_mlp_n_params
+gnav_mlp_grad = lib.gnav_mlp_grad
+gnav_mlp_adam = lib.gnav_mlp_adam
+gnav_mlp_forward = lib.gnav_mlp_forward
+gnav_mlp_get_params = lib.gnav_mlp_get_params
+gnav_mlp_free = lib.gnav_mlp_free
+gnav_ordering_classes = lib.gnav_ordering_classes
+gnav_set_mlp = lib.gnav_set_mlp
+CROSSING_DTYPE = np.dtype([("cls", np.int32), ("x", np.float32, 3), ("v", np.float32, 3),
+                           ("label", np.int32)])
 
 
 class GnavError(RuntimeError):
@@ -140,9 +168,9 @@ class Context:
         self._keep = []
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and gnav_destroy is not None:
             gnav_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -230,9 +258,17 @@ class Context:
         self._check(gnav_tally_create(self.h, int(n_events), C.byref(t)), "gnav_tally_create")
         return Tally(self, t, n_events)
 
-    def transport_batch(self, geom_id, prim, tally, seed=0, e_cut=1e-3, max_steps=0, precision=0,
-                        block=0, grid=0, log=None, event_geom=None, stream=None):
-        """prim: dict of device tensors event, prim_id, pos, dir, energy."""
+    def ordering_classes(self, geom_id):
+        n = C.c_int32()
+        self._check(gnav_ordering_classes(self.h, geom_id, C.byref(n)), "gnav_ordering_classes")
+        return n.value
+
+    def set_mlp(self, geom_id, net):
+        self._check(gnav_set_mlp(self.h, geom_id, net.h if net is not None else None),
+                    "gnav_set_mlp")
+
+    def _batch(self, geom_id, prim, seed=0, e_cut=1e-3, max_steps=0, precision=0, block=0, grid=0,
+               log=None, event_geom=None, count_work=False, order=0, record=None):
         b = gnav_batch()
         b.n_primaries = prim["energy"].shape[0]
         b.event_dev = prim["event"].data_ptr()
@@ -248,13 +284,104 @@ class Context:
         b.precision = precision
         b.block = block
         b.grid = grid
+        b.count_work = int(bool(count_work))
+        b.order = order
+        if record is not None:
+            b.record_dev = record["rec"].data_ptr()
+            b.record_capacity = record["cap"]
+            b.record_count_dev = record["count"].data_ptr()
         if log is not None:
             b.log_dev = log["rec"].data_ptr()
             b.log_capacity = log["cap"]
             b.log_n_dev = log["n"].data_ptr()
             b.log_fate_dev = log["fate"].data_ptr()
+        return b
+
+    def transport_batch(self, geom_id, prim, tally, stream=None, **kw):
+        """prim: dict of device tensors event, prim_id, pos, dir, energy."""
+        b = self._batch(geom_id, prim, **kw)
         self._check(gnav_transport_batch(self.h, C.byref(b), tally.h, _stream(stream)),
                     "gnav_transport_batch")
+
+    def graph_create(self, geom_id, prim, tally, stream=None, **kw):
+        b = self._batch(geom_id, prim, **kw)
+        g = C.c_void_p()
+        self._check(gnav_graph_create(self.h, C.byref(b), tally.h, _stream(stream), C.byref(g)),
+                    "gnav_graph_create")
+        return g
+
+    def graph_launch(self, g, stream=None):
+        self._check(gnav_graph_launch(self.h, g, _stream(stream)), "gnav_graph_launch")
+
+    def graph_free(self, g):
+        self._check(gnav_graph_free(self.h, g), "gnav_graph_free")
+
+
+class MLP:
+    """Candidate-ordering network on the device (parameters float32, products bf16 MFMA)."""
+
+    PARAMS = ["w1x", "w1m", "b1", "w2", "b2", "w3", "b3"]
+
+    def __init__(self, ctx, n_class, params, max_batch=4096):
+        self.ctx = ctx
+        self.n_class = n_class
+        flat = np.concatenate([np.ascontiguousarray(params[k], np.float32).reshape(-1)
+                               for k in self.PARAMS])
+        h = C.c_void_p()
+        ctx._check(gnav_mlp_create(ctx.h, int(n_class), int(max_batch),
+                                   flat.ctypes.data_as(C.c_void_p), C.byref(h)), "gnav_mlp_create")
+        self.h = h
+        self.n_params = int(gnav_mlp_n_params(h))
+        self.shapes = {k: np.asarray(params[k]).shape for k in self.PARAMS}
+
+    def grad(self, x, cls, label, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self.ctx._check(gnav_mlp_grad(self.ctx.h, self.h, x.shape[0], _ptr(x), _ptr(cls), _ptr(label),
+                                      _ptr(g), _ptr(loss), _stream(stream)), "gnav_mlp_grad")
+        return g, loss
+
+    def step(self, x, cls, label, lr=1e-3, stream=None, want_loss=False):
+        loss = None
+        if want_loss:
+            import torch
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self.ctx._check(gnav_mlp_grad(self.ctx.h, self.h, x.shape[0], _ptr(x), _ptr(cls), _ptr(label),
+                                      None, _ptr(loss), _stream(stream)), "gnav_mlp_grad")
+        self.ctx._check(gnav_mlp_adam(self.ctx.h, self.h, float(lr), _stream(stream)), "gnav_mlp_adam")
+        return loss
+
+    def forward(self, x, cls, stream=None):
+        import torch
+        out = torch.empty((x.shape[0], 64), dtype=torch.float32, device=x.device)
+        self.ctx._check(gnav_mlp_forward(self.ctx.h, self.h, x.shape[0], _ptr(x), _ptr(cls), _ptr(out),
+                                         _stream(stream)), "gnav_mlp_forward")
+        return out
+
+    def params(self):
+        flat = np.zeros(self.n_params, np.float32)
+        self.ctx._check(gnav_mlp_get_params(self.ctx.h, self.h, flat.ctypes.data_as(C.c_void_p)),
+                        "gnav_mlp_get_params")
+        out, o = {}, 0
+        for k in self.PARAMS:
+            n = int(np.prod(self.shapes[k]))
+            out[k] = flat[o:o + n].reshape(self.shapes[k])
+            o += n
+        return out
+
+    def unflatten(self, flat):
+        out, o = {}, 0
+        for k in self.PARAMS:
+            n = int(np.prod(self.shapes[k]))
+            out[k] = np.asarray(flat[o:o + n]).reshape(self.shapes[k])
+            o += n
+        return out
+
+    def free(self):
+        if self.h:
+            gnav_mlp_free(self.ctx.h, self.h)
+            self.h = None
 
 
 class Tally:
@@ -303,6 +430,18 @@ def make_log(n_primaries, cap, device="cuda"):
     return dict(rec=torch.zeros((3 * n_primaries, cap, 4), dtype=torch.float64, device=device),
                 cap=cap, n=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device),
                 fate=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device))
+
+
+def make_recorder(capacity, device="cuda"):
+    """Device buffers for the crossing recorder (32-byte records)."""
+    import torch
+    return dict(rec=torch.zeros((capacity, 8), dtype=torch.int32, device=device), cap=capacity,
+                count=torch.zeros(1, dtype=torch.int64, device=device))
+
+
+def recorder_to_numpy(rec):
+    n = min(int(rec["count"].cpu()[0]), rec["cap"])
+    return rec["rec"][:n].cpu().numpy().view(CROSSING_DTYPE).reshape(n)
 
 
 def log_to_numpy(log):

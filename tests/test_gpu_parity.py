@@ -237,7 +237,7 @@ def test_transport_launch_shape_independent(ctx, torch_dev, oracle_lib):
     desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
     print_case("launch_shape")
     _, prim, _ = W.calorimeter(n=3000)
-    a = run_transport(ctx, torch, gid, prim, 200, block=64, grid=3)
+    a = run_transport(ctx, torch, gid, prim, 200, grid=3)
     b = run_transport(ctx, torch, gid, prim, 200, block=256, grid=97)
     assert np.array_equal(a["log_n"], b["log_n"])
     for f in ("touchable", "code", "step", "edep", "energy"):
