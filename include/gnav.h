@@ -76,7 +76,8 @@ typedef int32_t gnav_status;
 #define GNAV_C_INSIDE 14        /* point-in-solid tests (locate / relocate) */
 #define GNAV_C_VOXEL_NODES 15   /* voxel nodes visited by the step walk */
 #define GNAV_C_INVALID 16       /* primaries skipped: bad event/geometry id, non-finite state, E <= 0 */
-#define GNAV_NCOUNTERS 17
+#define GNAV_C_DIST_IN_F32 17   /* daughter entry distances evaluated in FP32 (FP32 precisions) */
+#define GNAV_NCOUNTERS 18
 
 /* Limiter codes of a step. */
 #define GNAV_LIM_MOTHER (-1)    /* left the current volume (>= 0: entered that daughter slot) */
@@ -173,6 +174,31 @@ gnav_status gnav_compute_step(gnav_ctx* ctx, int32_t geom_id, int64_t n, const d
                               double* step_dev, int32_t* limiter_dev,
                               int32_t* next_touchable_dev, void* stream);
 
+/* Distance arithmetic of ComputeStep (Sec. 5 names FP64 throughput as a
+ * limit of the GPU port).  In both FP32 forms positions, optical depths,
+ * point-in-volume decisions, the voxel walk and tallies stay FP64 and the
+ * daughter candidates' solid arithmetic runs in FP32 on coordinates local to
+ * each candidate.
+ *   GNAV_PREC_FP64: every distance in FP64.
+ *   GNAV_PREC_FP32_SCREENED: FP32 entry distances rank the candidates; the
+ *     first is evaluated in FP64, the others in FP64 unless a rigorous FP32
+ *     lower bound shows they cannot reach the best distance.  Steps,
+ *     limiters and therefore whole transports equal the FP64 results.
+ *   GNAV_PREC_FP32: the step is the FP32 distance (mother and daughters);
+ *     results deviate from FP64 by FP32 rounding. */
+#define GNAV_PREC_FP64 0
+#define GNAV_PREC_FP32_SCREENED 1
+#define GNAV_PREC_FP32 2
+
+/* ComputeStep at a chosen precision.  Arguments as gnav_compute_step, plus
+ * safety_dev [n] (may be NULL): the voxel-limited safety at each point (a
+ * lower bound on the distance to any boundary in the FP64 and screened
+ * forms, the FP32 value in the GNAV_PREC_FP32 form). */
+gnav_status gnav_compute_step_prec(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                                   const double* dir_dev, const int32_t* touchable_dev, int32_t precision,
+                                   double* step_dev, int32_t* limiter_dev, int32_t* next_touchable_dev,
+                                   double* safety_dev, void* stream);
+
 /* ComputeSafety: a lower bound >= 0 on the isotropic distance from each point
  * to any boundary of its touchable (mother or daughter), limited to the
  * point's voxel node.  touchable_dev NULL: locate first. */
@@ -211,7 +237,7 @@ typedef struct {
   uint64_t seed;              /* Philox key of the transport stream */
   double e_cut;               /* MeV: photons below it deposit locally and stop */
   int64_t max_steps_per_track;/* <= 0: 1e6 */
-  int32_t precision;          /* 0: FP64 distances */
+  int32_t precision;          /* GNAV_PREC_*; FP32 forms need order 0 and no recorder */
   int32_t block;              /* threads per block (multiple of 64, <= 256), 0 = default */
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
   int32_t count_work;         /* 1: also count navigation work (GNAV_C_DIST_IN..VOXEL_NODES) */
@@ -224,6 +250,12 @@ typedef struct {
   int64_t log_capacity;       /*   its two annihilation photons), log_capacity records each */
   int32_t* log_n_dev;         /*   [3 n] records written per slot (may exceed the capacity) */
   int32_t* log_fate_dev;      /*   [3 n] GNAV_FATE_* per slot (0 = slot unused) */
+  int32_t chunk;              /* primaries a block claims from the device queue at once; 0: each
+                                 wave claims exactly what its idle lanes need (one atomic) */
+  int32_t sort_period;        /* every sort_period-th round the step phase groups tracks by their
+                                 current logical volume instead of solid family; 0: never */
+  int32_t tuned;              /* 1: take grid, chunk and sort_period from gnav_autotune's cache
+                                 for this geometry, precision and order when present */
 } gnav_batch;
 
 /* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase
@@ -233,6 +265,26 @@ typedef struct {
  * depend on launch shape or scheduling. */
 gnav_status gnav_transport_batch(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally,
                                  void* stream);
+
+/* Launch settings of gnav_transport_batch chosen by gnav_autotune. */
+typedef struct {
+  int32_t grid;
+  int32_t chunk;
+  int32_t sort_period;
+  float ms;                   /* median kernel time of the setting, milliseconds */
+} gnav_tuning;
+
+/* Autotuner (the scheduling knobs of Sec. 5: how tracks are grouped and
+ * refilled).  Times the transport of `batch` (trials runs per setting after
+ * one warm-up, median, hipEvents on `stream`) over a coordinate search of
+ * grid (1, 2, 3, 4, 6 blocks per compute unit), chunk (0, 256, 1024, 4096)
+ * and sort_period (0, 1, 4, 16), keeps the fastest in the context for this
+ * geometry, precision, order and batch size (power-of-two class), and
+ * returns it in `out` (may be NULL).  Batches with tuned = 1 then use it.
+ * `tally` is scratch (left zeroed); batch must not carry a log or recorder.
+ * Synchronous; trials in 1..100. */
+gnav_status gnav_autotune(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally, int32_t trials,
+                          void* stream, gnav_tuning* out);
 
 /* Copy tallies to host memory (Alg. 2, phase 6) after the stream passes the
  * earlier calls; synchronises `stream`.  Outputs may be NULL:

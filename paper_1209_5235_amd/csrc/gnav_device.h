@@ -81,6 +81,28 @@ struct PRec {
   int pad[6];
 };
 
+// FP32 twin of a placement for the FP32-distance variant: the translation
+// stays FP64 (the offset from the placement origin is formed in FP64 and
+// then rounded, so local coordinates keep FP32's relative precision), the
+// rotation, bounding box and the placed solid's parameters are float (160
+// bytes, everything one candidate test reads).
+struct PRecF {
+  double t[3];
+  float r[9];          // mother -> local rotation (R^T, row major)
+  int kind;            // 0: no rotation
+  float lo[3], hi[3];  // bounding box in the mother frame, rounded outward
+  int info;            // solid info of the placed LV
+  float par[kSolidPar];
+  float bscale;        // largest |lo|, |hi| (rounding margin of the box test)
+  float sscale;        // largest solid parameter magnitude (margin of the safety)
+  float sgrow;         // 1 + largest cone slope |B| (margin growth with distance)
+  int pad[2];
+};
+
+static_assert(sizeof(LRec) == 256, "LRec layout");
+static_assert(sizeof(PRec) == 176, "PRec layout");
+static_assert(sizeof(PRecF) == 160, "PRecF layout");
+
 // All device tables, by value in kernel arguments.  Indices are global over
 // every resident geometry.
 struct DevGeom {
@@ -91,6 +113,8 @@ struct DevGeom {
   const int2* vox_node;     // {candidate offset, count}
   const uint16_t* vox_cand; // daughter slots, ascending within a node
   const double* xs;         // [mat][3][257] attenuation, 1/mm
+  const PRecF* pvf;         // [PV] FP32 twins of the placements
+  const float* lv_parf;     // [LV][12] FP32 twins of the LV solid parameters
   double lnE0, dlnE;
 };
 
@@ -101,9 +125,12 @@ struct DevGeom {
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
 
-struct V3 {
-  double x, y, z;
+template <typename R>
+struct Vec3 {
+  R x, y, z;
 };
+using V3 = Vec3<double>;
+using V3f = Vec3<float>;
 
 __device__ __forceinline__ V3 xf_point(const double* __restrict__ m, int kind, V3 p) {
   double d0 = p.x - m[9], d1 = p.y - m[10], d2 = p.z - m[11];
@@ -119,11 +146,25 @@ __device__ __forceinline__ V3 xf_dir(const double* __restrict__ m, int kind, V3 
 }
 
 // ---------------------------------------------------------------------------
+// Solid functions, templated on the arithmetic type R.  The FP64 path
+// instantiates them with double; the FP32-distance path (Sec. 5 names FP64
+// throughput as a limit of the port) with float on coordinates local to the
+// solid's centre.  Every constant is written as R(...) so the float
+// instantiation carries no hidden double arithmetic.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R tmax(R a, R b) { return a > b ? a : b; }
+template <typename R>
+__device__ __forceinline__ R tmin(R a, R b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------------------
 // Box (half lengths h)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double box_d(const double* h, V3 p) {
-  return dmax(dmax(fabs(p.x) - h[0], fabs(p.y) - h[1]), fabs(p.z) - h[2]);
+template <typename R>
+__device__ __forceinline__ R box_d(const R* h, Vec3<R> p) {
+  return tmax(tmax(fabs(p.x) - h[0], fabs(p.y) - h[1]), fabs(p.z) - h[2]);
 }
 
 __device__ __forceinline__ int box_inside(const double* h, V3 p, bool has_v, V3 v) {
@@ -139,37 +180,41 @@ __device__ __forceinline__ int box_inside(const double* h, V3 p, bool has_v, V3 
 }
 
 // Slab entry: the ray enters when it is inside all three slabs.
-__device__ __forceinline__ double box_dist_in(const double* h, V3 p, V3 v) {
-  if (fabs(p.x) - h[0] >= -kHalfTol && p.x * v.x >= 0) return kInf;
-  if (fabs(p.y) - h[1] >= -kHalfTol && p.y * v.y >= 0) return kInf;
-  if (fabs(p.z) - h[2] >= -kHalfTol && p.z * v.z >= 0) return kInf;
-  double te = -kInf, tx = kInf;
-  const double pc[3] = {p.x, p.y, p.z};
-  const double vc[3] = {v.x, v.y, v.z};
+template <typename R>
+__device__ __forceinline__ R box_dist_in(const R* h, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  if (fabs(p.x) - h[0] >= -ht && p.x * v.x >= zero) return inf;
+  if (fabs(p.y) - h[1] >= -ht && p.y * v.y >= zero) return inf;
+  if (fabs(p.z) - h[2] >= -ht && p.z * v.z >= zero) return inf;
+  R te = -inf, tx = inf;
+  const R pc[3] = {p.x, p.y, p.z};
+  const R vc[3] = {v.x, v.y, v.z};
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    if (vc[i] == 0.0) continue;
-    double t1 = (-h[i] - pc[i]) / vc[i];
-    double t2 = (h[i] - pc[i]) / vc[i];
-    te = dmax(te, dmin(t1, t2));
-    tx = dmin(tx, dmax(t1, t2));
+    if (vc[i] == zero) continue;
+    R t1 = (-h[i] - pc[i]) / vc[i];
+    R t2 = (h[i] - pc[i]) / vc[i];
+    te = tmax(te, tmin(t1, t2));
+    tx = tmin(tx, tmax(t1, t2));
   }
-  if (te >= tx - kHalfTol) return kInf;
-  return te < kHalfTol ? 0.0 : te;
+  if (te >= tx - ht) return inf;
+  return te < ht ? zero : te;
 }
 
-__device__ __forceinline__ double box_dist_out(const double* h, V3 p, V3 v) {
-  double t = kInf;
-  const double pc[3] = {p.x, p.y, p.z};
-  const double vc[3] = {v.x, v.y, v.z};
+template <typename R>
+__device__ __forceinline__ R box_dist_out(const R* h, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), zero = R(0);
+  R t = R(kInf);
+  const R pc[3] = {p.x, p.y, p.z};
+  const R vc[3] = {v.x, v.y, v.z};
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    double sd;
-    if (vc[i] > 0) sd = h[i] - pc[i];
-    else if (vc[i] < 0) sd = h[i] + pc[i];
+    R sd;
+    if (vc[i] > zero) sd = h[i] - pc[i];
+    else if (vc[i] < zero) sd = h[i] + pc[i];
     else continue;
-    if (sd <= kHalfTol) return 0.0;
-    t = dmin(t, sd / fabs(vc[i]));
+    if (sd <= ht) return zero;
+    t = tmin(t, sd / fabs(vc[i]));
   }
   return t;
 }
@@ -178,45 +223,50 @@ __device__ __forceinline__ double box_dist_out(const double* h, V3 p, V3 v) {
 // Orb (radius R)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double orb_d(double R, V3 p) {
-  return sqrt(p.x * p.x + p.y * p.y + p.z * p.z) - R;
+template <typename R>
+__device__ __forceinline__ R orb_d(R rad, Vec3<R> p) {
+  return sqrt(p.x * p.x + p.y * p.y + p.z * p.z) - rad;
 }
 
-__device__ __forceinline__ int orb_inside(double R, V3 p, bool has_v, V3 v) {
-  double d = orb_d(R, p);
+__device__ __forceinline__ int orb_inside(double rad, V3 p, bool has_v, V3 v) {
+  double d = orb_d(rad, p);
   if (d < -kHalfTol) return kIn;
   if (d > kHalfTol) return kOut;
   if (!has_v) return kIn;
   return (p.x * v.x + p.y * v.y + p.z * v.z) < 0 ? kIn : kOut;
 }
 
-__device__ __forceinline__ double orb_dist_in(double R, V3 p, V3 v) {
-  double rr = p.x * p.x + p.y * p.y + p.z * p.z;
-  double sd = sqrt(rr) - R;
-  double b = p.x * v.x + p.y * v.y + p.z * v.z;
-  if (sd < -kHalfTol) return 0.0;
-  if (b >= 0) return kInf;
-  double c = rr - R * R;
-  double disc = b * b - c;
-  if (disc <= 0) return kInf;
-  double sq = sqrt(disc);
-  double te = c / (sq - b);
-  double tx = sq - b;
-  if (te >= tx - kHalfTol) return kInf;
-  return te < kHalfTol ? 0.0 : te;
+template <typename R>
+__device__ __forceinline__ R orb_dist_in(R rad, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  R rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  R sd = sqrt(rr) - rad;
+  R b = p.x * v.x + p.y * v.y + p.z * v.z;
+  if (sd < -ht) return zero;
+  if (b >= zero) return inf;
+  R c = rr - rad * rad;
+  R disc = b * b - c;
+  if (disc <= zero) return inf;
+  R sq = sqrt(disc);
+  R te = c / (sq - b);
+  R tx = sq - b;
+  if (te >= tx - ht) return inf;
+  return te < ht ? zero : te;
 }
 
-__device__ __forceinline__ double orb_dist_out(double R, V3 p, V3 v) {
-  double rr = p.x * p.x + p.y * p.y + p.z * p.z;
-  double sd = sqrt(rr) - R;
-  double b = p.x * v.x + p.y * v.y + p.z * v.z;
-  if (sd >= -kHalfTol && b >= 0) return 0.0;
-  double c = rr - R * R;
-  double disc = b * b - c;
-  if (disc < 0) disc = 0;
-  double sq = sqrt(disc);
-  double t = (b > 0) ? -c / (b + sq) : sq - b;
-  return t > 0 ? t : 0.0;
+template <typename R>
+__device__ __forceinline__ R orb_dist_out(R rad, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), zero = R(0);
+  R rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  R sd = sqrt(rr) - rad;
+  R b = p.x * v.x + p.y * v.y + p.z * v.z;
+  if (sd >= -ht && b >= zero) return zero;
+  R c = rr - rad * rad;
+  R disc = b * b - c;
+  if (disc < zero) disc = zero;
+  R sq = sqrt(disc);
+  R t = (b > zero) ? -c / (b + sq) : sq - b;
+  return t > zero ? t : zero;
 }
 
 // ---------------------------------------------------------------------------
@@ -224,32 +274,36 @@ __device__ __forceinline__ double orb_dist_out(double R, V3 p, V3 v) {
 // z (optional), slab |z| <= dz, phi wedge (optional, at most pi wide).
 // ---------------------------------------------------------------------------
 
+template <typename R>
 struct RadComps {
-  double ro, ri, z, pa, pb;
+  R ro, ri, z, pa, pb;
 };
 
-__device__ __forceinline__ RadComps rad_comps(const double* q, int info, V3 p) {
-  RadComps k;
-  double rho = sqrt(p.x * p.x + p.y * p.y);
+template <typename R>
+__device__ __forceinline__ RadComps<R> rad_comps(const R* q, int info, Vec3<R> p) {
+  const R inf = R(kInf);
+  RadComps<R> k;
+  R rho = sqrt(p.x * p.x + p.y * p.y);
   k.ro = (rho - (q[R_AO] + q[R_BO] * p.z)) * q[R_CO];
-  k.ri = (info & kInfoInner) ? ((q[R_AI] + q[R_BI] * p.z) - rho) * q[R_CI] : -kInf;
+  k.ri = (info & kInfoInner) ? ((q[R_AI] + q[R_BI] * p.z) - rho) * q[R_CI] : -inf;
   k.z = fabs(p.z) - q[R_DZ];
   if (info & kInfoPhi) {
     k.pa = p.x * q[R_NS0] + p.y * q[R_NS1];
     k.pb = p.x * q[R_NE0] + p.y * q[R_NE1];
   } else {
-    k.pa = -kInf;
-    k.pb = -kInf;
+    k.pa = -inf;
+    k.pb = -inf;
   }
   return k;
 }
 
-__device__ __forceinline__ double rad_dmax(const RadComps& k) {
-  return dmax(dmax(dmax(k.ro, k.ri), dmax(k.z, k.pa)), k.pb);
+template <typename R>
+__device__ __forceinline__ R rad_dmax(const RadComps<R>& k) {
+  return tmax(tmax(tmax(k.ro, k.ri), tmax(k.z, k.pa)), k.pb);
 }
 
 __device__ __forceinline__ int rad_inside(const double* q, int info, V3 p, bool has_v, V3 v) {
-  RadComps k = rad_comps(q, info, p);
+  RadComps<double> k = rad_comps(q, info, p);
   double d = rad_dmax(k);
   if (d < -kHalfTol) return kIn;
   if (d > kHalfTol) return kOut;
@@ -269,130 +323,137 @@ __device__ __forceinline__ int rad_inside(const double* q, int info, V3 p, bool 
 // Roots of f(t) = rho(t)^2 - (A + B z(t))^2 = a t^2 + 2 b t + c on the real
 // sheet (A + B z >= 0); `want` selects the slope sign: +1 leaving rho <= R(z),
 // -1 entering it.  Returns the smallest such root that is >= lo.
-__device__ __forceinline__ double radial_root(double A, double B, V3 p, V3 v, int want, double lo) {
-  double R0 = A + B * p.z;
-  double Rv = B * v.z;
-  double a = v.x * v.x + v.y * v.y - Rv * Rv;
-  double b = p.x * v.x + p.y * v.y - R0 * Rv;
-  double c = p.x * p.x + p.y * p.y - R0 * R0;
-  double t0, t1;
+template <typename R>
+__device__ __forceinline__ R radial_root(R A, R B, Vec3<R> p, Vec3<R> v, int want, R lo) {
+  const R inf = R(kInf), zero = R(0);
+  R R0 = A + B * p.z;
+  R Rv = B * v.z;
+  R a = v.x * v.x + v.y * v.y - Rv * Rv;
+  R b = p.x * v.x + p.y * v.y - R0 * Rv;
+  R c = p.x * p.x + p.y * p.y - R0 * R0;
+  R t0, t1;
   int n;
-  if (a == 0.0) {
-    if (b == 0.0) return kInf;
-    t0 = -c / (2.0 * b);
-    t1 = kInf;
+  if (a == zero) {
+    if (b == zero) return inf;
+    t0 = -c / (R(2) * b);
+    t1 = inf;
     n = 1;
   } else {
-    double disc = b * b - a * c;
-    if (disc < 0.0) return kInf;
-    double sq = sqrt(disc);
-    double qq = (b >= 0.0) ? -(b + sq) : (sq - b);
-    double r1 = qq / a;
-    double r2 = (qq != 0.0) ? c / qq : r1;
-    t0 = dmin(r1, r2);
-    t1 = dmax(r1, r2);
+    R disc = b * b - a * c;
+    if (disc < zero) return inf;
+    R sq = sqrt(disc);
+    R qq = (b >= zero) ? -(b + sq) : (sq - b);
+    R r1 = qq / a;
+    R r2 = (qq != zero) ? c / qq : r1;
+    t0 = tmin(r1, r2);
+    t1 = tmax(r1, r2);
     n = 2;
   }
-  double best = kInf;
+  R best = inf;
   {
-    double s = a * t0 + b;
-    bool ok = want > 0 ? (s > 0) : (s < 0);
-    if (ok && R0 + Rv * t0 >= 0 && t0 >= lo) best = t0;
+    R s = a * t0 + b;
+    bool ok = want > 0 ? (s > zero) : (s < zero);
+    if (ok && R0 + Rv * t0 >= zero && t0 >= lo) best = t0;
   }
-  if (n == 2 && best == kInf) {
-    double s = a * t1 + b;
-    bool ok = want > 0 ? (s > 0) : (s < 0);
-    if (ok && R0 + Rv * t1 >= 0 && t1 >= lo) best = t1;
+  if (n == 2 && best == inf) {
+    R s = a * t1 + b;
+    bool ok = want > 0 ? (s > zero) : (s < zero);
+    if (ok && R0 + Rv * t1 >= zero && t1 >= lo) best = t1;
   }
   return best;
 }
 
-__device__ __forceinline__ bool rad_ok_except(const double* q, int info, V3 p, V3 v, double t,
-                                              int skip) {
-  V3 r{p.x + t * v.x, p.y + t * v.y, p.z + t * v.z};
-  RadComps k = rad_comps(q, info, r);
-  if (skip != 0 && k.ro > kHalfTol) return false;
-  if (skip != 1 && k.ri > kHalfTol) return false;
-  if (skip != 2 && k.z > kHalfTol) return false;
-  if (skip != 3 && k.pa > kHalfTol) return false;
-  if (skip != 4 && k.pb > kHalfTol) return false;
+template <typename R>
+__device__ __forceinline__ bool rad_ok_except(const R* q, int info, Vec3<R> p, Vec3<R> v, R t, int skip) {
+  const R ht = R(kHalfTol);
+  Vec3<R> r{p.x + t * v.x, p.y + t * v.y, p.z + t * v.z};
+  RadComps<R> k = rad_comps(q, info, r);
+  if (skip != 0 && k.ro > ht) return false;
+  if (skip != 1 && k.ri > ht) return false;
+  if (skip != 2 && k.z > ht) return false;
+  if (skip != 3 && k.pa > ht) return false;
+  if (skip != 4 && k.pb > ht) return false;
   return true;
 }
 
 // Entry distance, surface by surface: a crossing through one face counts if
 // every other component holds at the crossing point.
-__device__ __forceinline__ double rad_dist_in(const double* q, int info, V3 p, V3 v) {
-  RadComps k = rad_comps(q, info, p);
-  if (rad_dmax(k) < -kHalfTol) return 0.0;
-  double rho = sqrt(p.x * p.x + p.y * p.y);
-  double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
-  double best = kInf;
-  if (k.z >= -kHalfTol) {
-    if (p.z * v.z >= 0) return kInf;
-    double t = k.z / fabs(v.z);
-    if (t < 0) t = 0;
-    if (rad_ok_except(q, info, p, v, t, 2)) best = dmin(best, t);
+template <typename R>
+__device__ __forceinline__ R rad_dist_in(const R* q, int info, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  RadComps<R> k = rad_comps(q, info, p);
+  if (rad_dmax(k) < -ht) return zero;
+  R rho = sqrt(p.x * p.x + p.y * p.y);
+  R rv = rho > zero ? (p.x * v.x + p.y * v.y) / rho : zero;
+  R best = inf;
+  if (k.z >= -ht) {
+    if (p.z * v.z >= zero) return inf;
+    R t = k.z / fabs(v.z);
+    if (t < zero) t = zero;
+    if (rad_ok_except(q, info, p, v, t, 2)) best = tmin(best, t);
   }
-  if (k.ro >= -kHalfTol) {
-    if (rv - q[R_BO] * v.z >= 0) return kInf;
-    double t = radial_root(q[R_AO], q[R_BO], p, v, -1, -kInf);
-    if (t == kInf) return kInf;
-    if (t < 0) t = 0;
-    if (rad_ok_except(q, info, p, v, t, 0)) best = dmin(best, t);
+  if (k.ro >= -ht) {
+    if (rv - q[R_BO] * v.z >= zero) return inf;
+    R t = radial_root(q[R_AO], q[R_BO], p, v, -1, -inf);
+    if (t == inf) return inf;
+    if (t < zero) t = zero;
+    if (rad_ok_except(q, info, p, v, t, 0)) best = tmin(best, t);
   }
   if (info & kInfoInner) {
-    double t = -1.0;
-    if (fabs(k.ri) <= kHalfTol) {
-      double vn = -rv + q[R_BI] * v.z;
-      if (vn < 0) t = 0.0;
-      else if (vn > 0) t = radial_root(q[R_AI], q[R_BI], p, v, +1, 0.0);
+    R t = R(-1);
+    if (fabs(k.ri) <= ht) {
+      R vn = -rv + q[R_BI] * v.z;
+      if (vn < zero) t = zero;
+      else if (vn > zero) t = radial_root(q[R_AI], q[R_BI], p, v, +1, zero);
     } else {
-      t = radial_root(q[R_AI], q[R_BI], p, v, +1, 0.0);
+      t = radial_root(q[R_AI], q[R_BI], p, v, +1, zero);
     }
-    if (t >= 0 && t < kInf && rad_ok_except(q, info, p, v, t, 1)) best = dmin(best, t);
+    if (t >= zero && t < inf && rad_ok_except(q, info, p, v, t, 1)) best = tmin(best, t);
   }
   if (info & kInfoPhi) {
-    if (k.pa >= -kHalfTol) {
-      double dv = v.x * q[R_NS0] + v.y * q[R_NS1];
-      if (dv >= 0) return kInf;
-      double t = k.pa / (-dv);
-      if (t < 0) t = 0;
-      if (rad_ok_except(q, info, p, v, t, 3)) best = dmin(best, t);
+    if (k.pa >= -ht) {
+      R dv = v.x * q[R_NS0] + v.y * q[R_NS1];
+      if (dv >= zero) return inf;
+      R t = k.pa / (-dv);
+      if (t < zero) t = zero;
+      if (rad_ok_except(q, info, p, v, t, 3)) best = tmin(best, t);
     }
-    if (k.pb >= -kHalfTol) {
-      double dv = v.x * q[R_NE0] + v.y * q[R_NE1];
-      if (dv >= 0) return kInf;
-      double t = k.pb / (-dv);
-      if (t < 0) t = 0;
-      if (rad_ok_except(q, info, p, v, t, 4)) best = dmin(best, t);
+    if (k.pb >= -ht) {
+      R dv = v.x * q[R_NE0] + v.y * q[R_NE1];
+      if (dv >= zero) return inf;
+      R t = k.pb / (-dv);
+      if (t < zero) t = zero;
+      if (rad_ok_except(q, info, p, v, t, 4)) best = tmin(best, t);
     }
   }
-  return best < kHalfTol ? 0.0 : best;
+  return best < ht ? zero : best;
 }
 
-__device__ __forceinline__ double rad_dist_out(const double* q, int info, V3 p, V3 v) {
-  RadComps k = rad_comps(q, info, p);
-  double rho = sqrt(p.x * p.x + p.y * p.y);
-  double rv = rho > 0 ? (p.x * v.x + p.y * v.y) / rho : 0.0;
-  double t = kInf;
-  if (v.z != 0) {
-    double sd = v.z > 0 ? q[R_DZ] - p.z : q[R_DZ] + p.z;
-    if (sd <= kHalfTol) return 0.0;
-    t = dmin(t, sd / fabs(v.z));
+template <typename R>
+__device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<R> v) {
+  const R ht = R(kHalfTol), zero = R(0);
+  RadComps<R> k = rad_comps(q, info, p);
+  R rho = sqrt(p.x * p.x + p.y * p.y);
+  R rv = rho > zero ? (p.x * v.x + p.y * v.y) / rho : zero;
+  R t = R(kInf);
+  if (v.z != zero) {
+    R sd = v.z > zero ? q[R_DZ] - p.z : q[R_DZ] + p.z;
+    if (sd <= ht) return zero;
+    t = tmin(t, sd / fabs(v.z));
   }
-  if (k.ro >= -kHalfTol && rv - q[R_BO] * v.z >= 0) return 0.0;
-  t = dmin(t, radial_root(q[R_AO], q[R_BO], p, v, +1, 0.0));
+  if (k.ro >= -ht && rv - q[R_BO] * v.z >= zero) return zero;
+  t = tmin(t, radial_root(q[R_AO], q[R_BO], p, v, +1, zero));
   if (info & kInfoInner) {
-    if (k.ri >= -kHalfTol && -rv + q[R_BI] * v.z >= 0) return 0.0;
-    t = dmin(t, radial_root(q[R_AI], q[R_BI], p, v, -1, 0.0));
+    if (k.ri >= -ht && -rv + q[R_BI] * v.z >= zero) return zero;
+    t = tmin(t, radial_root(q[R_AI], q[R_BI], p, v, -1, zero));
   }
   if (info & kInfoPhi) {
-    double dv = v.x * q[R_NS0] + v.y * q[R_NS1];
-    if (k.pa >= -kHalfTol && dv >= 0) return 0.0;
-    if (dv > 0) t = dmin(t, dmax(-k.pa / dv, 0.0));
+    R dv = v.x * q[R_NS0] + v.y * q[R_NS1];
+    if (k.pa >= -ht && dv >= zero) return zero;
+    if (dv > zero) t = tmin(t, tmax(-k.pa / dv, zero));
     dv = v.x * q[R_NE0] + v.y * q[R_NE1];
-    if (k.pb >= -kHalfTol && dv >= 0) return 0.0;
-    if (dv > 0) t = dmin(t, dmax(-k.pb / dv, 0.0));
+    if (k.pb >= -ht && dv >= zero) return zero;
+    if (dv > zero) t = tmin(t, tmax(-k.pb / dv, zero));
   }
   return t;
 }
@@ -409,7 +470,8 @@ __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, boo
   }
 }
 
-__device__ __forceinline__ double solid_d(int info, const double* q, V3 p) {
+template <typename R>
+__device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
   switch (info & 15) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
@@ -417,7 +479,8 @@ __device__ __forceinline__ double solid_d(int info, const double* q, V3 p) {
   }
 }
 
-__device__ __forceinline__ double solid_dist_in(int info, const double* q, V3 p, V3 v) {
+template <typename R>
+__device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3<R> v) {
   switch (info & 15) {
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
@@ -425,7 +488,8 @@ __device__ __forceinline__ double solid_dist_in(int info, const double* q, V3 p,
   }
 }
 
-__device__ __forceinline__ double solid_dist_out(int info, const double* q, V3 p, V3 v) {
+template <typename R>
+__device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec3<R> v) {
   switch (info & 15) {
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
@@ -447,8 +511,9 @@ __device__ __forceinline__ int vox_axis_index(double p, double lo, double inv_w,
 // Work counters for the roofline accounting; compiled out when not wanted.
 template <bool ON>
 struct NavCount {
-  unsigned dist_in = 0, dist_out = 0, inside = 0, nodes = 0;
+  unsigned dist_in = 0, dist_out = 0, inside = 0, nodes = 0, dist_in32 = 0;
   __device__ __forceinline__ void in() { if (ON) dist_in++; }
+  __device__ __forceinline__ void in32() { if (ON) dist_in32++; }
   __device__ __forceinline__ void out() { if (ON) dist_out++; }
   __device__ __forceinline__ void ins() { if (ON) inside++; }
   __device__ __forceinline__ void node() { if (ON) nodes++; }
@@ -786,6 +851,232 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
   }
   safety = saf;
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// FP32-distance navigation (Sec. 5 names FP64 throughput among the limits
+// of the GPU port).  Positions, optical depths, point-in-volume decisions,
+// the voxel walk and the tallies stay FP64; what moves to FP32 is the
+// solid arithmetic of the daughter candidates, on coordinates local to each
+// candidate.  Two forms:
+//  * screened: FP32 entry distances rank a node's candidates; the first in
+//    that order is evaluated in FP64, and every other candidate is
+//    evaluated in FP64 unless a rigorous FP32 lower bound on its FP64
+//    distance exceeds the best distance so far.  Skipped candidates can
+//    neither beat nor tie the result, so limiter, step and every later
+//    decision equal the FP64 path's.
+//  * pure: the step is the FP32 distance itself (mother and daughters).
+// ---------------------------------------------------------------------------
+
+enum : int { kPrecFP64 = 0, kPrecScreened = 1, kPrecPure = 2 };
+
+// Candidate frame in FP32: offset from the placement origin in FP64, then
+// rounded and rotated in FP32.
+__device__ __forceinline__ void xf_local_f(const PRecF& P, V3 pl, V3 vl, V3f& pd, V3f& vd) {
+  float d0 = (float)(pl.x - P.t[0]), d1 = (float)(pl.y - P.t[1]), d2 = (float)(pl.z - P.t[2]);
+  float v0 = (float)vl.x, v1 = (float)vl.y, v2 = (float)vl.z;
+  if (P.kind == 0) {
+    pd = V3f{d0, d1, d2};
+    vd = V3f{v0, v1, v2};
+    return;
+  }
+  const float* r = P.r;
+  pd = V3f{r[0] * d0 + r[1] * d1 + r[2] * d2, r[3] * d0 + r[4] * d1 + r[5] * d2,
+           r[6] * d0 + r[7] * d1 + r[8] * d2};
+  vd = V3f{r[0] * v0 + r[1] * v1 + r[2] * v2, r[3] * v0 + r[4] * v1 + r[5] * v2,
+           r[6] * v0 + r[7] * v1 + r[8] * v2};
+}
+
+// Isotropic safety of a candidate from its FP32 local point, lowered by a
+// margin that covers the rounding of the local point (about 2^-24 per
+// coordinate and 2^-22 after the rotation), of the parameters (2^-24) and
+// of the solid function (a few 2^-24 of the magnitudes involved), with a
+// factor 16 to spare: 2^-18 of (|p|_1 * (1 + |B|) + parameter scale).
+__device__ __forceinline__ float safety_lo_f(const PRecF& P, V3f pd) {
+  float d = solid_d<float>(P.info, P.par, pd);
+  float m = 0x1p-18f * ((fabsf(pd.x) + fabsf(pd.y) + fabsf(pd.z)) * P.sgrow + P.sscale);
+  d -= m;
+  return d > 0.f ? d : 0.f;
+}
+
+// Rigorous lower bound on the FP64 entry distance of a candidate from the
+// mother-frame ray (pl, vl): the larger of its lowered safety and the ray's
+// entry into its bounding box grown by mu = 2^-20 (|p|_inf + box scale),
+// which exceeds the rounding of the FP32 point and of each slab numerator
+// sixteen-fold, so the computed entry is never later than the true one and
+// a ray that meets the true box is never declared a miss.  +inf on a miss.
+__device__ __forceinline__ double lower_bound_f(const PRecF& P, V3 pl, V3 vl, V3f pd) {
+  const float pc[3] = {(float)pl.x, (float)pl.y, (float)pl.z};
+  const float vc[3] = {(float)vl.x, (float)vl.y, (float)vl.z};
+  float pm = fmaxf(fmaxf(fabsf(pc[0]), fabsf(pc[1])), fabsf(pc[2]));
+  float mu = 0x1p-20f * (pm + P.bscale);
+  float te = 0.f, tx = __builtin_inff();
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    float n1 = P.lo[a] - pc[a], n2 = P.hi[a] - pc[a];
+    if (vc[a] == 0.f) {
+      // parallel to the slab: a miss only if outside the grown slab (a ray
+      // with a direction component below float range would enter it only
+      // after a distance far beyond any mother's exit distance)
+      if (n1 - mu > 0.f || n2 + mu < 0.f) return kInf;
+      continue;
+    }
+    float t1, t2;
+    if (vc[a] > 0.f) {
+      t1 = (n1 - mu) / vc[a];
+      t2 = (n2 + mu) / vc[a];
+    } else {
+      t1 = (n2 + mu) / vc[a];
+      t2 = (n1 - mu) / vc[a];
+    }
+    te = fmaxf(te, t1);
+    tx = fminf(tx, t2);
+  }
+  if (te > tx) return kInf;
+  return dmax((double)te, (double)safety_lo_f(P, pd));
+}
+
+// ComputeStep with FP32 candidate arithmetic (see above).  `lv` indexes the
+// FP32 parameter twins of the mother (pure form only).  The walk, the node
+// faces of the safety and the tie rule are those of compute_step.
+template <bool C, bool PURE>
+__device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec& L, int lv, V3 pl, V3 vl,
+                                                   int& lim, double& safety, NavCount<C>& nc) {
+  const int info = L.info;
+  double s, saf;
+  if (PURE) {
+    const float* q = G.lv_parf + (size_t)lv * kSolidPar;
+    V3f pf{(float)pl.x, (float)pl.y, (float)pl.z}, vf{(float)vl.x, (float)vl.y, (float)vl.z};
+    s = (double)solid_dist_out<float>(info, q, pf, vf);
+    float md = solid_d<float>(info, q, pf);
+    saf = md < 0.f ? (double)(-md) : 0.0;
+  } else {
+    s = solid_dist_out(info, L.par, pl, vl);
+    double md = solid_d(info, L.par, pl);
+    saf = md < 0 ? -md : 0.0;
+  }
+  nc.out();
+  lim = kLimMother;
+  const int cnt = L.dau_cnt;
+  if (cnt == 0) {
+    safety = saf;
+    return s;
+  }
+  const int base = L.dau_base;
+  const bool vox = L.vox != 0;
+  const double pc[3] = {pl.x, pl.y, pl.z};
+  const double vc[3] = {vl.x, vl.y, vl.z};
+  int idx[3] = {0, 0, 0};
+  if (vox) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) idx[a] = vox_axis_index(pc[a], L.vlo[a], L.vinv[a], L.n[a]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      double lo = L.vlo[a] + idx[a] * L.vw[a];
+      double hi = L.vlo[a] + (idx[a] + 1) * L.vw[a];
+      if (idx[a] > 0) saf = dmin(saf, dmax(pc[a] - lo, 0.0));
+      if (idx[a] < L.n[a] - 1) saf = dmin(saf, dmax(hi - pc[a], 0.0));
+    }
+  }
+  bool first = true;
+  for (;;) {
+    int2 nd = int2{0, cnt};
+    if (vox) {
+      nd = G.vox_node[L.node_base + (idx[0] * L.n[1] + idx[1]) * L.n[2] + idx[2]];
+      nc.node();
+    }
+    auto slot = [&](int c) { return vox ? (int)G.vox_cand[nd.x + c] : c; };
+    if (PURE) {
+      for (int c = 0; c < nd.y; c++) {
+        const int k = slot(c);
+        const PRecF& P = G.pvf[base + k];
+        V3f pd, vd;
+        xf_local_f(P, pl, vl, pd, vd);
+        double t = (double)solid_dist_in<float>(P.info, P.par, pd, vd);
+        nc.in32();
+        if (first) {
+          float d = solid_d<float>(P.info, P.par, pd);
+          saf = dmin(saf, d > 0.f ? (double)d : 0.0);
+        }
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+    } else {
+      // rank by the FP32 entry distance; the node's safety from lowered FP32 safeties
+      int lead = -1;
+      float tl = __builtin_inff();
+      for (int c = 0; c < nd.y; c++) {
+        const PRecF& P = G.pvf[base + slot(c)];
+        V3f pd, vd;
+        xf_local_f(P, pl, vl, pd, vd);
+        float t = solid_dist_in<float>(P.info, P.par, pd, vd);
+        nc.in32();
+        if (first) saf = dmin(saf, (double)safety_lo_f(P, pd));
+        if (t < tl) {
+          tl = t;
+          lead = c;
+        }
+      }
+      if (lead >= 0) {
+        const int k = slot(lead);
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        nc.in();
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+      for (int c = 0; c < nd.y; c++) {
+        if (c == lead) continue;
+        const int k = slot(c);
+        const PRecF& P = G.pvf[base + k];
+        V3f pd, vd;
+        xf_local_f(P, pl, vl, pd, vd);
+        double lb = lower_bound_f(P, pl, vl, pd);
+        if (lb * (1.0 - 1e-6) - kTol > s) continue;
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        nc.in();
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+    }
+    first = false;
+    if (!vox) break;
+    double tx = kInf;
+    int ax = -1;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (vc[a] == 0.0) continue;
+      double plane = L.vlo[a] + (idx[a] + (vc[a] > 0 ? 1 : 0)) * L.vw[a];
+      double ta = (plane - pc[a]) / vc[a];
+      if (ta < tx) {
+        tx = ta;
+        ax = a;
+      }
+    }
+    if (ax < 0 || s < tx) break;
+    idx[ax] += vc[ax] > 0 ? 1 : -1;
+    if (idx[ax] < 0 || idx[ax] >= L.n[ax]) break;
+  }
+  safety = saf;
+  return s;
+}
+
+// Precision dispatch of ComputeStep.
+template <bool C, int ORDER, int PREC>
+__device__ __forceinline__ double compute_step_p(const DevGeom& G, const LRec& L, int lv, V3 pl, V3 vl,
+                                                 int& lim, double& safety, NavCount<C>& nc, int pred,
+                                                 int2* start_node) {
+  if constexpr (PREC == kPrecFP64) {
+    return compute_step<C, ORDER>(G, L, pl, vl, lim, safety, nc, pred, start_node);
+  } else {
+    if (start_node) *start_node = int2{0, 0};
+    return compute_step_f32<C, PREC == kPrecPure>(G, L, lv, pl, vl, lim, safety, nc);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -9,9 +9,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <string>
@@ -424,6 +426,8 @@ struct gnav_ctx {
   std::vector<double> t_xf;
   std::vector<LRec> lv_rec;
   std::vector<PRec> pv_rec;
+  std::vector<PRecF> pvf;
+  std::vector<float> lv_parf;
   std::vector<int2> vox_node;
   std::vector<uint16_t> vox_cand;
   std::vector<double> xs;
@@ -432,9 +436,11 @@ struct gnav_ctx {
   int n_mats_total = 0;
   double lnE0 = 0, dlnE = 0;
   // device copies
-  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
+  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_lv_parf, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
   DevBuf d_queue, d_pend;
   DevGeom G{};
+  // autotuned launch settings by (geometry, precision, order, log2 of the batch size)
+  std::map<std::array<int, 4>, gnav_tuning> tuning;
 };
 
 struct gnav_tally {
@@ -469,6 +475,8 @@ hipError_t upload_all(gnav_ctx* c) {
   UP(d_t_xf, t_xf)
   UP(d_lv_rec, lv_rec)
   UP(d_pv_rec, pv_rec)
+  UP(d_pvf, pvf)
+  UP(d_lv_parf, lv_parf)
   UP(d_vox_node, vox_node)
   UP(d_vox_cand, vox_cand)
   UP(d_xs, xs)
@@ -479,12 +487,27 @@ hipError_t upload_all(gnav_ctx* c) {
   G.t_xf = c->d_t_xf.as<double>();
   G.lv = c->d_lv_rec.as<LRec>();
   G.pv = c->d_pv_rec.as<PRec>();
+  G.pvf = c->d_pvf.as<PRecF>();
+  G.lv_parf = c->d_lv_parf.as<float>();
   G.vox_node = c->d_vox_node.as<int2>();
   G.vox_cand = c->d_vox_cand.as<uint16_t>();
   G.xs = c->d_xs.as<double>();
   G.lnE0 = c->lnE0;
   G.dlnE = c->dlnE;
   return hipSuccess;
+}
+
+// Nearest float not above / not below x.
+float round_down_f(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -std::numeric_limits<float>::infinity());
+  return f;
+}
+
+float round_up_f(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+  return f;
 }
 
 bool is_identity(const double* R) {
@@ -735,6 +758,38 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
     }
     c->lv_rec.push_back(lr);
   }
+  // FP32 twins: mother parameters per LV, and per placement everything a
+  // candidate test reads (bounding box rounded outward)
+  for (int l = gr.lv_base; l < (int)c->lv_rec.size(); l++)
+    for (int k = 0; k < kSolidPar; k++) c->lv_parf.push_back((float)c->lv_rec[l].par[k]);
+  for (int p = gr.pv_base; p < (int)c->pv_rec.size(); p++) {
+    const PRec& pr = c->pv_rec[p];
+    const LRec& dl = c->lv_rec[pr.lv];
+    PRecF pf;
+    std::memset(&pf, 0, sizeof(pf));
+    for (int a = 0; a < 3; a++) pf.t[a] = pr.m[9 + a];
+    for (int k = 0; k < 9; k++) pf.r[k] = (float)pr.m[k];
+    pf.kind = pr.kind;
+    float bs = 0.f;
+    for (int a = 0; a < 3; a++) {
+      pf.lo[a] = round_down_f(pr.box_lo[a]);
+      pf.hi[a] = round_up_f(pr.box_hi[a]);
+      bs = std::max(bs, std::max(std::fabs(pf.lo[a]), std::fabs(pf.hi[a])));
+    }
+    pf.bscale = bs;
+    pf.info = dl.info;
+    float ss = 0.f;
+    for (int k = 0; k < kSolidPar; k++) {
+      pf.par[k] = (float)dl.par[k];
+      ss = std::max(ss, std::fabs(pf.par[k]));
+    }
+    pf.sscale = ss;
+    int ty = dl.info & 15;
+    pf.sgrow = (ty == kTubs || ty == kCons)
+                   ? 1.f + (float)std::max(std::fabs(dl.par[R_BO]), std::fabs(dl.par[R_BI]))
+                   : 1.f;
+    c->pvf.push_back(pf);
+  }
   // touchables: breadth first from the world
   gr.h_parent.assign(nt, -1);
   gr.h_pv.assign(nt, -1);
@@ -853,12 +908,20 @@ gnav_status gnav_locate(gnav_ctx* c, int32_t geom_id, int64_t n, const double* p
 gnav_status gnav_compute_step(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
                               const int32_t* touch, double* step, int32_t* lim, int32_t* next,
                               void* stream) {
+  return gnav_compute_step_prec(c, geom_id, n, pos, dir, touch, GNAV_PREC_FP64, step, lim, next, nullptr,
+                                stream);
+}
+
+gnav_status gnav_compute_step_prec(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos,
+                                   const double* dir, const int32_t* touch, int32_t precision, double* step,
+                                   int32_t* lim, int32_t* next, double* safety, void* stream) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
   if (n < 0 || (n > 0 && (!pos || !dir || !step || !lim))) return fail(c, GNAV_EINVAL, "bad step arguments");
+  if (precision < GNAV_PREC_FP64 || precision > GNAV_PREC_FP32) return fail(c, GNAV_EINVAL, "bad precision");
   int tb = c->geoms[geom_id].t_base;
-  HIP_TRY(c, launch_step(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, dir, touch, step, lim, next,
-                         (hipStream_t)stream),
+  HIP_TRY(c, launch_step(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, dir, touch, step, lim, next, safety,
+                         precision, (hipStream_t)stream),
           "step launch");
   return GNAV_OK;
 }
@@ -916,6 +979,12 @@ namespace {
 
 // Validate a batch and fill the launch description (may grow the
 // pending-photon buffer, which synchronises the stream).
+std::array<int, 4> tuning_key(const gnav_batch* b) {
+  int lg = 0;
+  while (lg < 62 && (1LL << (lg + 1)) <= b->n_primaries) lg++;
+  return {b->geom_id, b->precision, b->order, lg};
+}
+
 gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, hipStream_t stream,
                               TransportLaunch* out) {
   if (!c || !b || !t) return GNAV_EINVAL;
@@ -926,14 +995,26 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
     return fail(c, GNAV_EINVAL, "null primary array");
   if (t->n_touch != (int)c->t_rec.size())
     return fail(c, GNAV_ESTATE, "tally was created before the last geometry upload");
-  if (b->precision != 0) return fail(c, GNAV_EUNSUPPORTED, "precision mode not available");
+  if (b->precision < GNAV_PREC_FP64 || b->precision > GNAV_PREC_FP32)
+    return fail(c, GNAV_EINVAL, "precision must be GNAV_PREC_FP64, _FP32_SCREENED or _FP32");
+  if (b->precision != GNAV_PREC_FP64 && (b->order != 0 || b->record_dev))
+    return fail(c, GNAV_EINVAL, "candidate orders and the crossing recorder need FP64 distances");
   if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
     return fail(c, GNAV_EINVAL, "log buffers incomplete");
   if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
+  int grid_req = b->grid, chunk_req = b->chunk, sort_req = b->sort_period;
+  if (b->tuned) {
+    auto it = c->tuning.find(tuning_key(b));
+    if (it != c->tuning.end()) {
+      grid_req = it->second.grid;
+      chunk_req = it->second.chunk;
+      sort_req = it->second.sort_period;
+    }
+  }
   int block = b->block > 0 ? b->block : 256;
   if (block != 256) return fail(c, GNAV_EINVAL, "block must be 256 (one 256-slot track pool per block)");
   long need = (b->n_primaries + block - 1) / block;
-  int grid = b->grid > 0 ? b->grid : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 3);
+  int grid = grid_req > 0 ? grid_req : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 3);
   TransportLaunch& L = *out;
   L = TransportLaunch{};
   L.G = c->G;
@@ -966,6 +1047,12 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.count = b->count_work != 0;
   if (b->order < 0 || b->order > 2) return fail(c, GNAV_EINVAL, "order must be 0, 1 or 2");
   L.order = b->order;
+  L.prec = b->precision;
+  if (chunk_req < 0 || chunk_req > (1 << 24)) return fail(c, GNAV_EINVAL, "chunk out of range");
+  if (sort_req < 0) return fail(c, GNAV_EINVAL, "negative sort period");
+  L.chunk = chunk_req;
+  L.sort_period = sort_req;
+  L.G_n_lv = std::max(1, (int)c->lv_rec.size());
   if (b->order == 2) {
     const GeomRec& gr = c->geoms[b->geom_id];
     if (b->event_geom_dev) return fail(c, GNAV_EUNSUPPORTED, "the learned order needs a single geometry");
@@ -1000,6 +1087,95 @@ gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t
   gnav_status s = prepare_transport(c, b, t, (hipStream_t)stream, &L);
   if (s) return s;
   HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");
+  return GNAV_OK;
+}
+
+namespace {
+
+// Median kernel time (ms) of `trials` runs of one launch setting, each on a
+// freshly zeroed tally.
+gnav_status time_setting(gnav_ctx* c, const gnav_batch& b, gnav_tally* t, hipStream_t st, int trials,
+                         float* ms_out) {
+  TransportLaunch L;
+  gnav_status s = prepare_transport(c, &b, t, st, &L);
+  if (s) return s;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0), "event");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(c, e, "event");
+  }
+  std::vector<float> ms;
+  for (int r = 0; r <= trials && e == hipSuccess; r++) {  // r = 0 warms up
+    if ((s = gnav_tally_reset(c, t, st))) break;
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+    if ((e = launch_transport(L, st)) != hipSuccess) break;
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float v = 0;
+    if ((e = hipEventElapsedTime(&v, e0, e1)) != hipSuccess) break;
+    if (r > 0) ms.push_back(v);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(c, e, "autotune run");
+  std::sort(ms.begin(), ms.end());
+  *ms_out = ms[ms.size() / 2];
+  return GNAV_OK;
+}
+
+}  // namespace
+
+gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, int32_t trials, void* stream,
+                          gnav_tuning* out) {
+  if (!c || !batch || !t) return GNAV_EINVAL;
+  if (trials < 1 || trials > 100) return fail(c, GNAV_EINVAL, "trials must be 1..100");
+  if (batch->log_dev || batch->record_dev)
+    return fail(c, GNAV_EINVAL, "tune without the per-track log or the recorder");
+  hipStream_t st = (hipStream_t)stream;
+  gnav_batch b = *batch;
+  b.tuned = 0;
+  long need = std::max<long>(1, (b.n_primaries + 255) / 256);
+  // coordinate descent: grid, then chunk, then sort period
+  gnav_tuning best{(int)std::min<long>(need, (long)c->n_cu * 3), 0, 0, 0.f};
+  b.grid = best.grid;
+  b.chunk = 0;
+  b.sort_period = 0;
+  gnav_status s = time_setting(c, b, t, st, trials, &best.ms);
+  if (s) return s;
+  auto consider = [&](gnav_batch cand) -> gnav_status {
+    float ms = 0;
+    gnav_status r = time_setting(c, cand, t, st, trials, &ms);
+    if (r) return r;
+    if (ms < best.ms) best = gnav_tuning{cand.grid, cand.chunk, cand.sort_period, ms};
+    return GNAV_OK;
+  };
+  for (int f : {1, 2, 4, 6}) {
+    int g = (int)std::min<long>(need, (long)c->n_cu * f);
+    if (g == best.grid) continue;
+    gnav_batch cand = b;
+    cand.grid = g;
+    if ((s = consider(cand))) return s;
+  }
+  for (int ch : {256, 1024, 4096}) {
+    gnav_batch cand = b;
+    cand.grid = best.grid;
+    cand.chunk = ch;
+    if ((s = consider(cand))) return s;
+  }
+  for (int sp : {1, 4, 16}) {
+    gnav_batch cand = b;
+    cand.grid = best.grid;
+    cand.chunk = best.chunk;
+    cand.sort_period = sp;
+    if ((s = consider(cand))) return s;
+  }
+  if ((s = gnav_tally_reset(c, t, st))) return s;
+  HIP_TRY(c, hipStreamSynchronize(st), "synchronize");
+  c->tuning[tuning_key(&b)] = best;
+  if (out) *out = best;
   return GNAV_OK;
 }
 

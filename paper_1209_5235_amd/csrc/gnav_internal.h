@@ -50,6 +50,10 @@ struct TransportLaunch {
   int grid;
   bool count;
   int order;
+  int prec;  // kPrecFP64 / kPrecScreened / kPrecPure (FP32 forms use the plain order)
+  int chunk;        // queue claim size per block (0: per wave, exactly what it needs)
+  int sort_period;  // rounds between volume-bucketed step phases (0: never)
+  int G_n_lv;       // resident logical volumes
   gnav_crossing* rec;
   long rec_cap;
   unsigned long long* rec_count;
@@ -61,7 +65,8 @@ bool mlp_view(const gnav_mlp* m, MlpView* out);
 hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const double* pos,
                          const double* dir, int* out, hipStream_t st);
 hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                       const double* dir, const int* touch, double* step, int* lim, int* next, hipStream_t st);
+                       const double* dir, const int* touch, double* step, int* lim, int* next, double* saf,
+                       int prec, hipStream_t st);
 hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
                          const int* touch, double* out, hipStream_t st);
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);

@@ -35,9 +35,10 @@ __global__ void __launch_bounds__(256) k_locate(DevGeom G, int W, int tbase, lon
   out[i] = T < 0 ? -1 : T - tbase;
 }
 
+template <int PREC>
 __global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int tcount, long n,
                                               const double* pos, const double* dir, const int* touch,
-                                              double* step, int* lim_out, int* next) {
+                                              double* step, int* lim_out, int* next, double* saf_out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   NavCount<false> nc;
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int t
     step[i] = kInf;
     lim_out[i] = kLimMother;
     if (next) next[i] = -1;
+    if (saf_out) saf_out[i] = 0.0;
     return;
   }
   TRec tr = G.t[T];
@@ -56,9 +58,11 @@ __global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int t
   touchable_frame(G, T, trec_kind(tr), p, v, pl, vl);
   int lim;
   double saf;
-  double s = compute_step(G, G.lv[tr.lv], pl, vl, lim, saf, nc);
+  double s = compute_step_p<false, kOrderPlain, PREC>(G, G.lv[tr.lv], tr.lv, pl, vl, lim, saf, nc, -1,
+                                                      nullptr);
   step[i] = s;
   lim_out[i] = lim;
+  if (saf_out) saf_out[i] = saf;
   if (next) {
     int nt = -1;
     if (s < kInf) {
@@ -194,6 +198,9 @@ struct TransportArgs {
   long rec_cap;
   unsigned long long* rec_count;
   MlpView mlp;                // candidate-ordering network (learned order)
+  int chunk;                  // 0: each wave claims what it needs; > 0: the block claims chunks
+  int sort_period;            // every sort_period-th round buckets the step phase by volume (0: never)
+  int n_lv;                   // resident logical volumes (sort keys)
 };
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
@@ -247,9 +254,11 @@ struct Pool {
   unsigned cnt_b[kPool];  // crossings | pushes << 24
   int pred[kPool];     // learned order: predicted candidate position of the next step
   int list[kPool];
-  int wcnt[8 * kWaves];
-  int total[8];
+  int wcnt[16 * kWaves];
+  int total[16];
   unsigned long long cnt[GNAV_NCOUNTERS];
+  long qr[4];          // block-claimed primaries not yet started: [qr0, qr1) then [qr2, qr3)
+  int qopen;           // the device queue may still hold primaries
   int any_alive;
 };
 
@@ -477,7 +486,7 @@ __device__ __forceinline__ void learned_predict(const TransportArgs& a, Pool& P,
   }
 }
 
-template <bool LOG, bool COUNT, int ORDER>
+template <bool LOG, bool COUNT, int ORDER, int PREC>
 __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
   const DevGeom& G = a.G;
   const int tid = threadIdx.x;
@@ -487,13 +496,15 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
 
   if (tid < GNAV_NCOUNTERS) P.cnt[tid] = 0ull;
+  if (tid < 4) P.qr[tid] = 0;
+  if (tid == 0) P.qopen = 1;
   P.status[tid] = kEmpty;
   P.sub_pend[tid] = 0;
   NavCount<COUNT> nc;
   bool queue_open = true;
   __syncthreads();
 
-  for (;;) {
+  for (int round = 0;; round++) {
     // ---- refill: thread tid owns slot tid ---------------------------------
     {
       const int s = tid;
@@ -516,8 +527,10 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         start = true;
       }
       bool need = empty && !start;
-      if (queue_open) {
-        unsigned long long mask = __ballot(need);
+      long idx = -1;
+      if (a.chunk <= 0) {
+        // each wave claims exactly the primaries its idle lanes need
+        unsigned long long mask = queue_open ? __ballot(need) : 0ull;
         if (mask) {
           int cnt = __popcll(mask);
           int leader = __ffsll((long long)mask) - 1;
@@ -526,36 +539,91 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           base = __shfl(base, leader);
           if (base + cnt >= (unsigned long long)a.n) queue_open = false;
           if (need) {
-            unsigned long long idx = base + __popcll(mask & lt_mask);
-            if (idx < (unsigned long long)a.n) {
-              V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
-              V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
-              double E = a.energy[idx];
-              int event = a.event[idx];
-              int g = a.geom_default;
-              bool ok = event >= 0 && event < a.n_events;
-              if (ok && a.event_geom) g = a.event_geom[event];
-              ok = ok && g >= 0 && g < a.n_geoms && E > 0 && isfinite(E) && isfinite(x.x) && isfinite(x.y) &&
-                   isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
-              if (ok) {
-                P.x[s] = x.x;
-                P.y[s] = x.y;
-                P.z[s] = x.z;
-                P.vx[s] = v.x;
-                P.vy[s] = v.y;
-                P.vz[s] = v.z;
-                P.E[s] = E;
-                P.event[s] = event;
-                P.key[s] = a.prim_id[idx] << 2;
-                P.tbase[s] = a.geom_tbase[g];
-                P.prim[s] = (int)idx;
-                P.sub_pend[s] = 0;
-                start = true;
+            unsigned long long q = base + __popcll(mask & lt_mask);
+            if (q < (unsigned long long)a.n) idx = (long)q;
+          }
+        }
+      } else {
+        // the block claims `chunk` primaries at a time and hands them out in
+        // slot order; at most two claimed ranges are open at once
+        const int w = tid >> 6;
+        unsigned long long mask = __ballot(need);
+        if (lane == 0) P.wcnt[w] = __popcll(mask);
+        __syncthreads();
+        int before = 0, n_need = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ww++) {
+          int c = P.wcnt[ww];
+          if (ww < w) before += c;
+          n_need += c;
+        }
+        if (tid == 0 && P.qopen) {
+          long have = (P.qr[1] - P.qr[0]) + (P.qr[3] - P.qr[2]);
+          if (have < n_need) {
+            long want = max((long)a.chunk, (long)n_need - have);
+            long base = (long)atomicAdd(a.queue, (unsigned long long)want);
+            long end = min(base + want, a.n);
+            if (base + want >= a.n) P.qopen = 0;
+            if (base < end) {
+              if (P.qr[1] == P.qr[0]) {
+                P.qr[0] = P.qr[2];
+                P.qr[1] = P.qr[3];
+              }
+              if (P.qr[1] == P.qr[0]) {
+                P.qr[0] = base;
+                P.qr[1] = end;
+                P.qr[2] = P.qr[3] = 0;
               } else {
-                atomicAdd(&P.cnt[GNAV_C_INVALID], 1ull);
+                P.qr[2] = base;
+                P.qr[3] = end;
               }
             }
           }
+        }
+        __syncthreads();
+        const long r0 = P.qr[0], r1 = P.qr[1], r2 = P.qr[2], r3 = P.qr[3];
+        if (need) {
+          long rank = before + __popcll(mask & lt_mask);
+          if (rank < r1 - r0) idx = r0 + rank;
+          else if (rank - (r1 - r0) < r3 - r2) idx = r2 + rank - (r1 - r0);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          long take = n_need;
+          long t1 = min(take, r1 - r0);
+          P.qr[0] = r0 + t1;
+          take -= t1;
+          long t2 = min(take, r3 - r2);
+          P.qr[2] = r2 + t2;
+          if (P.qr[2] == P.qr[3]) P.qr[2] = P.qr[3] = 0;
+        }
+      }
+      if (idx >= 0) {
+        V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
+        V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
+        double E = a.energy[idx];
+        int event = a.event[idx];
+        int g = a.geom_default;
+        bool ok = event >= 0 && event < a.n_events;
+        if (ok && a.event_geom) g = a.event_geom[event];
+        ok = ok && g >= 0 && g < a.n_geoms && E > 0 && isfinite(E) && isfinite(x.x) && isfinite(x.y) &&
+             isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
+        if (ok) {
+          P.x[s] = x.x;
+          P.y[s] = x.y;
+          P.z[s] = x.z;
+          P.vx[s] = v.x;
+          P.vy[s] = v.y;
+          P.vz[s] = v.z;
+          P.E[s] = E;
+          P.event[s] = event;
+          P.key[s] = a.prim_id[idx] << 2;
+          P.tbase[s] = a.geom_tbase[g];
+          P.prim[s] = (int)idx;
+          P.sub_pend[s] = 0;
+          start = true;
+        } else {
+          atomicAdd(&P.cnt[GNAV_C_INVALID], 1ull);
         }
       }
       if (start) {
@@ -564,7 +632,14 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         P.T[s] = P.tbase[s];
       }
     }
-    if (!__syncthreads_or(P.status[tid] != kEmpty)) break;
+    // done when no slot holds a track and no claimed or unclaimed primary is
+    // left (a refill that met only invalid primaries does not end the block)
+    {
+      bool more = P.status[tid] != kEmpty;
+      if (a.chunk <= 0) more = more || queue_open;
+      else if (tid == 0) more = more || P.qopen || P.qr[1] > P.qr[0] || P.qr[3] > P.qr[2];
+      if (!__syncthreads_or(more)) break;
+    }
 
     // ---- navigate: track starts and boundary crossings --------------------
     {
@@ -620,12 +695,21 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
 
     // ---- step: mu, safety shortcut or ComputeStep, advance ------------------
     {
+      // bucket the step work by solid family and daughters, or, every
+      // sort_period-th round, by the current logical volume (16 ranges of LV id)
+      const bool by_volume = a.sort_period > 0 && round % a.sort_period == 0;
       int key = 0;
       if (P.status[tid] == kStep) {
-        const LRec& L = G.lv[P.lvk[tid] >> 1];
-        key = (L.info & 3) | (L.dau_cnt > 0 ? 4 : 0);
+        const int lv = P.lvk[tid] >> 1;
+        if (by_volume) {
+          key = (int)(((long)lv * 16) / a.n_lv);
+        } else {
+          const LRec& L = G.lv[lv];
+          key = (L.info & 3) | (L.dau_cnt > 0 ? 4 : 0);
+        }
       }
-      int n = compact<8>(P, P.status[tid] == kStep, key);
+      int n = by_volume ? compact<16>(P, P.status[tid] == kStep, key)
+                        : compact<8>(P, P.status[tid] == kStep, key);
       if (tid < n) {
         const int s = P.list[tid];
         const int T = P.T[s];
@@ -671,8 +755,8 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             touchable_frame(G, T, lvk & 1, x, v, pl, vl);
             double saf;
             int2 nd;
-            s_geo = compute_step<COUNT, ORDER>(G, L, pl, vl, lim, saf, nc,
-                                               ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
+            s_geo = compute_step_p<COUNT, ORDER, PREC>(G, L, lvk >> 1, pl, vl, lim, saf, nc,
+                                                       ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
             safety = saf;
             phys = s_phys <= s_geo;
             // crossing recorder: a daughter-limited step from a node with 2+ candidates
@@ -818,10 +902,11 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
 
   // ---- flush counters -------------------------------------------------------
   if (COUNT) {
-    unsigned vals[4] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes};
-    const int slots[4] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES};
+    unsigned vals[5] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes, nc.dist_in32};
+    const int slots[5] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
+                          GNAV_C_DIST_IN_F32};
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < 5; c++) {
       unsigned long long sum = vals[c];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
@@ -857,10 +942,19 @@ hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const doubl
 }
 
 hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                       const double* dir, const int* touch, double* step, int* lim, int* next, hipStream_t st) {
+                       const double* dir, const int* touch, double* step, int* lim, int* next, double* saf,
+                       int prec, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_step, dim3(grid_for(n, 256)), dim3(256), 0, st, G, W, tbase, tcount, n, pos, dir, touch,
-                     step, lim, next);
+  dim3 grid(grid_for(n, 256)), block(256);
+  if (prec == kPrecScreened)
+    hipLaunchKernelGGL(k_step<kPrecScreened>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch,
+                       step, lim, next, saf);
+  else if (prec == kPrecPure)
+    hipLaunchKernelGGL(k_step<kPrecPure>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch, step,
+                       lim, next, saf);
+  else
+    hipLaunchKernelGGL(k_step<kPrecFP64>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch, step,
+                       lim, next, saf);
   return hipGetLastError();
 }
 
@@ -913,14 +1007,19 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   a.rec_cap = L.rec_cap;
   a.rec_count = L.rec_count;
   a.mlp = L.mlp;
+  a.chunk = L.chunk;
+  a.sort_period = L.sort_period;
+  a.n_lv = L.G_n_lv;
   dim3 grid(L.grid), block(kPool);
-#define GNAV_LAUNCH(LOGV, CNTV, ORDV) \
-  hipLaunchKernelGGL((k_transport<LOGV, CNTV, ORDV>), grid, block, 0, st, a)
-#define GNAV_LAUNCH_ORDER(LOGV, CNTV)                                   \
-  do {                                                                  \
-    if (L.order == kOrderBound) GNAV_LAUNCH(LOGV, CNTV, kOrderBound);   \
-    else if (L.order == kOrderLearned) GNAV_LAUNCH(LOGV, CNTV, kOrderLearned); \
-    else GNAV_LAUNCH(LOGV, CNTV, kOrderPlain);                          \
+#define GNAV_LAUNCH(LOGV, CNTV, ORDV, PRECV) \
+  hipLaunchKernelGGL((k_transport<LOGV, CNTV, ORDV, PRECV>), grid, block, 0, st, a)
+#define GNAV_LAUNCH_ORDER(LOGV, CNTV)                                                    \
+  do {                                                                                   \
+    if (L.prec == kPrecScreened) GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecScreened);    \
+    else if (L.prec == kPrecPure) GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecPure);       \
+    else if (L.order == kOrderBound) GNAV_LAUNCH(LOGV, CNTV, kOrderBound, kPrecFP64);    \
+    else if (L.order == kOrderLearned) GNAV_LAUNCH(LOGV, CNTV, kOrderLearned, kPrecFP64); \
+    else GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecFP64);                                \
   } while (0)
   if (L.log) {
     if (L.count) GNAV_LAUNCH_ORDER(true, true);

@@ -24,7 +24,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGEOM", -5: "EST
           -6: "EUNSUPPORTED"}
 COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
             "truncated", "tracks", "shortcuts", "dist_in", "dist_out", "inside", "voxel_nodes",
-            "invalid"]
+            "invalid", "dist_in_f32"]
+# distance arithmetic of ComputeStep (GNAV_PREC_*)
+PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
 NCOUNTERS = len(COUNTERS)
 LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
                       ("edep", np.float64), ("energy", np.float64)])
@@ -56,7 +58,13 @@ class gnav_batch(C.Structure):
         ("order", C.c_int32), ("record_dev", C.c_void_p), ("record_capacity", C.c_int64),
         ("record_count_dev", C.c_void_p), ("log_dev", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_n_dev", C.c_void_p), ("log_fate_dev", C.c_void_p),
+        ("chunk", C.c_int32), ("sort_period", C.c_int32), ("tuned", C.c_int32),
     ]
+
+
+class gnav_tuning(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("chunk", C.c_int32), ("sort_period", C.c_int32),
+                ("ms", C.c_float)]
 
 
 def _load():
@@ -74,12 +82,16 @@ def _load():
         "gnav_touchable_offset": ([P, C.c_int32, _i32p, _i32p], C.c_int32),
         "gnav_locate": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
         "gnav_compute_step": ([P, C.c_int32, C.c_int64, P, P, P, P, P, P, P], C.c_int32),
+        "gnav_compute_step_prec": ([P, C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P, P, P, P],
+                                   C.c_int32),
         "gnav_compute_safety": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
         "gnav_tally_create": ([P, C.c_int32, C.POINTER(P)], C.c_int32),
         "gnav_tally_reset": ([P, P, P], C.c_int32),
         "gnav_tally_free": ([P, P], C.c_int32),
         "gnav_transport_batch": ([P, C.POINTER(gnav_batch), P, P], C.c_int32),
         "gnav_read_tallies": ([P, P, P, P, P, P, P], C.c_int32),
+        "gnav_autotune": ([P, C.POINTER(gnav_batch), P, C.c_int32, P, C.POINTER(gnav_tuning)],
+                          C.c_int32),
         "gnav_graph_create": ([P, C.POINTER(gnav_batch), P, P, C.POINTER(P)], C.c_int32),
         "gnav_graph_launch": ([P, P, P], C.c_int32),
         "gnav_graph_free": ([P, P], C.c_int32),
@@ -111,12 +123,14 @@ gnav_touchables = lib.gnav_touchables
 gnav_touchable_offset = lib.gnav_touchable_offset
 gnav_locate = lib.gnav_locate
 gnav_compute_step = lib.gnav_compute_step
+gnav_compute_step_prec = lib.gnav_compute_step_prec
 gnav_compute_safety = lib.gnav_compute_safety
 gnav_tally_create = lib.gnav_tally_create
 gnav_tally_reset = lib.gnav_tally_reset
 gnav_tally_free = lib.gnav_tally_free
 gnav_transport_batch = lib.gnav_transport_batch
 gnav_read_tallies = lib.gnav_read_tallies
+gnav_autotune = lib.gnav_autotune
 gnav_graph_create = lib.gnav_graph_create
 gnav_graph_launch = lib.gnav_graph_launch
 gnav_graph_free = lib.gnav_graph_free
@@ -234,15 +248,27 @@ class Context:
                     "gnav_locate")
         return out
 
-    def compute_step(self, geom_id, pos, dirs, touch=None, with_next=True, stream=None):
+    def compute_step(self, geom_id, pos, dirs, touch=None, with_next=True, stream=None, precision=0,
+                     with_safety=False):
+        """gnav_compute_step (FP64) or gnav_compute_step_prec; returns (step, limiter, next)
+        plus the safety when with_safety."""
         import torch
         n = pos.shape[0]
         step = torch.empty(n, dtype=torch.float64, device=pos.device)
         lim = torch.empty(n, dtype=torch.int32, device=pos.device)
         nxt = torch.empty(n, dtype=torch.int32, device=pos.device) if with_next else None
-        self._check(gnav_compute_step(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
-                                      _ptr(step), _ptr(lim), _ptr(nxt), _stream(stream)),
-                    "gnav_compute_step")
+        saf = torch.empty(n, dtype=torch.float64, device=pos.device) if with_safety else None
+        if precision == PREC_FP64 and not with_safety:
+            self._check(gnav_compute_step(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
+                                          _ptr(step), _ptr(lim), _ptr(nxt), _stream(stream)),
+                        "gnav_compute_step")
+        else:
+            self._check(gnav_compute_step_prec(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
+                                               int(precision), _ptr(step), _ptr(lim), _ptr(nxt),
+                                               _ptr(saf), _stream(stream)),
+                        "gnav_compute_step_prec")
+        if with_safety:
+            return step, lim, nxt, saf
         return step, lim, nxt
 
     def compute_safety(self, geom_id, pos, touch=None, stream=None):
@@ -268,7 +294,8 @@ class Context:
                     "gnav_set_mlp")
 
     def _batch(self, geom_id, prim, seed=0, e_cut=1e-3, max_steps=0, precision=0, block=0, grid=0,
-               log=None, event_geom=None, count_work=False, order=0, record=None):
+               log=None, event_geom=None, count_work=False, order=0, record=None, chunk=0,
+               sort_period=0, tuned=False):
         b = gnav_batch()
         b.n_primaries = prim["energy"].shape[0]
         b.event_dev = prim["event"].data_ptr()
@@ -286,6 +313,9 @@ class Context:
         b.grid = grid
         b.count_work = int(bool(count_work))
         b.order = order
+        b.chunk = chunk
+        b.sort_period = sort_period
+        b.tuned = int(bool(tuned))
         if record is not None:
             b.record_dev = record["rec"].data_ptr()
             b.record_capacity = record["cap"]
@@ -302,6 +332,15 @@ class Context:
         b = self._batch(geom_id, prim, **kw)
         self._check(gnav_transport_batch(self.h, C.byref(b), tally.h, _stream(stream)),
                     "gnav_transport_batch")
+
+    def autotune(self, geom_id, prim, tally, trials=3, stream=None, **kw):
+        """gnav_autotune: fastest {grid, chunk, sort_period} for this batch (cached in the
+        context for batches passed with tuned=True)."""
+        b = self._batch(geom_id, prim, **kw)
+        out = gnav_tuning()
+        self._check(gnav_autotune(self.h, C.byref(b), tally.h, int(trials), _stream(stream),
+                                  C.byref(out)), "gnav_autotune")
+        return dict(grid=out.grid, chunk=out.chunk, sort_period=out.sort_period, ms=out.ms)
 
     def graph_create(self, geom_id, prim, tally, stream=None, **kw):
         b = self._batch(geom_id, prim, **kw)

@@ -1,0 +1,120 @@
+"""Shared pieces of the GPU tests: geometries, query samplers, fixtures and the
+per-track log comparison against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+RTOL = 1e-9
+ATOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_1209_5235_amd import gnav
+    c = gnav.Context(0)
+    yield c
+    c.close()
+
+
+GEOMS = {
+    "tiny": lambda: W.geometry.tiny(),
+    "tiny_rot": lambda: W.geometry.tiny(rotated=True),
+    "zoo": lambda: W.geometry.solids_zoo(),
+    "calorimeter": lambda: W.geometry.calorimeter(),
+    "barrel": lambda: W.geometry.barrel(),
+    "barrel_v103": lambda: W.geometry.barrel_variant(103),
+}
+
+_cache = {}
+
+
+def geom(ctx, name, oracle_lib):
+    key = (id(ctx), name)
+    if key not in _cache:
+        desc = GEOMS[name]()
+        gid, nt = ctx.upload_geometry(desc)
+        _cache[key] = (desc, gid, nt, oracle_lib.Geometry(desc))
+    return _cache[key]
+
+
+def sample_points(desc, rng, n):
+    """Points spread over the world plus points on daughter faces and near centres."""
+    s = desc.lv_solid[desc.world_lv]
+    par = desc.solid_par[s]
+    half = par[:3] if desc.solid_type[s] == 0 else np.array([1600, 1600, 3000.0])
+    pts = rng.uniform(-1.02, 1.02, size=(n, 3)) * half
+    m = n // 3
+    if desc.n_pv:
+        pv = rng.integers(0, desc.n_pv, m)
+        pts[:m] = desc.pv_trans[pv] + rng.normal(0, 30, size=(m, 3))
+    return pts
+
+
+def print_case(*a):
+    print("CASE", *a, flush=True)
+    sys.stdout.flush()
+
+
+def surface_points(desc, og, rng, n):
+    """Points exactly on the boundary of random steps (end points of oracle steps)."""
+    pts = sample_points(desc, rng, n)
+    dirs = W.primaries.isotropic(rng, n)
+    T = og.locate(pts, dirs)
+    ok = T >= 0
+    pts, dirs, T = pts[ok], dirs[ok], T[ok]
+    step, lim, nxt = og.compute_step(pts, dirs, T)
+    end = pts + step[:, None] * dirs
+    return end, dirs, nxt
+
+
+def compare_logs(rec, n, fate, ref, cap):
+    """Number of track slots whose logs disagree, and the first disagreement."""
+    bad = []
+    nslots = len(n)
+    for s in range(nslots):
+        if n[s] != ref["log_n"][s] or fate[s] != ref["log_fate"][s]:
+            bad.append((s, "count/fate", int(n[s]), int(ref["log_n"][s]), int(fate[s]),
+                        int(ref["log_fate"][s])))
+            continue
+        k = min(int(n[s]), cap)
+        a, b = rec[s, :k], ref["log"][s, :k]
+        if not (np.array_equal(a["touchable"], b["touchable"]) and np.array_equal(a["code"], b["code"])):
+            i = int(np.nonzero((a["touchable"] != b["touchable"]) | (a["code"] != b["code"]))[0][0])
+            bad.append((s, "volume", i))
+            continue
+        for f in ("step", "edep", "energy"):
+            if not np.allclose(a[f], b[f], rtol=RTOL, atol=ATOL):
+                bad.append((s, f))
+                break
+    return bad
+
+
+def run_transport(ctx, torch, gid, prim, cap, seed=0, **kw):
+    from paper_1209_5235_amd import gnav
+    tally = ctx.tally_create(prim.n_events)
+    dev = gnav.primaries_to_device(prim, "cuda")
+    log = gnav.make_log(prim.n, cap, "cuda") if cap else None
+    ctx.transport_batch(gid, dev, tally, seed=seed, log=log, **kw)
+    torch.cuda.synchronize()
+    got = tally.read()
+    tally.free()
+    off, _ = ctx.touchable_offset(gid)
+    nt = ctx.geoms[gid][1]
+    got["edep_touchable"] = got["edep_touchable"][off:off + nt]
+    if cap:
+        got["log"], got["log_n"], got["log_fate"] = gnav.log_to_numpy(log)
+    return got
+
+
+EXACT = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
+         "truncated", "tracks"]

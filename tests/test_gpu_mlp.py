@@ -73,6 +73,15 @@ def test_mlp_gradients_match_numpy(dev):
 
 
 def test_mlp_training_matches_numpy_adam(dev):
+    """Adam on the GPU follows the numpy oracle.
+
+    Adam divides each update by the root of its running squared gradient, so
+    components whose gradient is near zero move by about the learning rate
+    whatever the sign of the rounding noise: parameters of two runs that differ
+    only in accumulation order drift apart over many steps.  The parameters are
+    therefore compared element-wise after a few steps, and the long run by its
+    loss curve.
+    """
     torch, gnav, ctx = dev
     print_case("mlp_adam")
     n_class = 3
@@ -86,14 +95,19 @@ def test_mlp_training_matches_numpy_adam(dev):
     m = {k: np.zeros_like(v) for k, v in p.items()}
     v = {k: np.zeros_like(val) for k, val in p.items()}
     pn = dict(p)
-    losses = []
+    losses, ref_losses = [], []
     for t in range(1, 101):
         loss = net.step(xt, ct, lt, lr=3e-3, want_loss=True)
         losses.append(float(loss.cpu()[0]))
-        g, _ = mlp.backward_bf16(pn, x, cls, label)
+        g, ref_loss = mlp.backward_bf16(pn, x, cls, label)
+        ref_losses.append(ref_loss)
         pn = mlp.adam_step(pn, g, m, v, t, lr=3e-3)
-    got = net.params()
-    for k in mlp.PARAMS:
-        assert rel(got[k], pn[k]) < 2e-2, (k, rel(got[k], pn[k]))
+        if t == 3:
+            got = net.params()
+            for k in mlp.PARAMS:
+                assert rel(got[k], pn[k]) < 1e-2, (k, rel(got[k], pn[k]))
     assert losses[-1] < 0.5 * losses[0]
+    assert ref_losses[-1] < 0.5 * ref_losses[0]
+    for a, b in zip(losses, ref_losses):
+        assert abs(a - b) <= 0.1 * b + 1e-3, (a, b)
     net.free()
