@@ -53,15 +53,163 @@ def algorithmic_flops(c):
             + FLOPS["compton"] * c["compton"] + FLOPS["pe"] * c["pe"] + FLOPS["pair"] * c["pair"])
 
 
-def cpu_baseline(n_sample, seed=0):
+def _oracle_slice(args):
+    """Oracle transport of primaries [lo, hi) of the calorimeter workload (worker)."""
+    n_sample, lo, hi = args
     import oracle
     import workloads as W
-    geoms, prim, _ = W.calorimeter(n=n_sample, seed=seed)
+    geoms, prim, _ = W.calorimeter(n=n_sample, seed=0)
     og = oracle.Geometry(geoms[0])
+    sub = prim.subset(np.arange(lo, hi))
     t0 = time.perf_counter()
-    r = og.transport(prim, seed=0)
-    dt = time.perf_counter() - t0
-    return r["counters"]["steps"] / dt, dt, r["counters"]["steps"]
+    r = og.transport(sub, seed=0, n_events=prim.n_events)
+    return r["counters"]["steps"], time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample, workers):
+    """Oracle steps/s on host cores: one thread over the sample, then `workers`
+    processes over equal slices of it (each a plain single-threaded oracle)."""
+    steps1, dt1 = _oracle_slice((n_sample, 0, n_sample))
+    out = {"single": (steps1 / dt1, dt1, steps1)}
+    if workers > 1:
+        import multiprocessing as mp
+        cuts = np.linspace(0, n_sample, workers + 1).astype(int)
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_slice, [(n_sample, int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])])
+        dt = time.perf_counter() - t0
+        steps = sum(r[0] for r in res)
+        out["all"] = (steps / dt, dt, steps)
+    return out
+
+
+def kernel_source_hash():
+    """Hash of the transport kernel sources (ties stored counter readings to a build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gnav_kernels.hip", "gnav_device.h", "gnav_internal.h"):
+        with open(os.path.join(ROOT, "paper_1209_5235_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None when it was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "k_transport_calorimeter_1e6_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_batches(ctx, gid, prim_d, tally, stream, reps, **kw):
+    """Median kernel time (ms, HIP events on the launch stream) of `reps` batches
+    after one warm-up, and the counters of an extra counting batch."""
+    import torch
+    tally.reset(stream)
+    ctx.transport_batch(gid, prim_d, tally, stream=stream, **kw)
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tally.reset(stream)
+        a.record(stream)
+        ctx.transport_batch(gid, prim_d, tally, stream=stream, **kw)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    res = tally.read(stream)
+    tally.reset(stream)
+    ctx.transport_batch(gid, prim_d, tally, stream=stream, count_work=True, **kw)
+    work = tally.read(stream)["counters"]
+    return float(np.median(ms)), res, work
+
+
+def barrel_variants(ctx, gnav, n, reps, train_photons):
+    """Barrel workload: FP64 plain walk against the bound and learned candidate
+    orders (identical results) and the two FP32-distance forms."""
+    import torch
+    import workloads as W
+    from paper_1209_5235_amd import learned
+    geoms, prim, _ = W.barrel(n=n, seed=0)
+    gid, _ = ctx.upload_geometry(geoms[0])
+    stream = torch.cuda.current_stream()
+    prim_d = gnav.primaries_to_device(prim, "cuda")
+    tally = ctx.tally_create(prim.n_events)
+    out = {"workload": f"barrel: 64 tubs layers x 128 segments, 2x16 cons rings, 32 orbs; {n:.0e} "
+                       "photons from the axis, log-uniform 0.05-20 MeV, seed 0"}
+    base_ms, base, base_w = time_batches(ctx, gid, prim_d, tally, stream, reps)
+    steps = base["counters"]["steps"]
+
+    def entry(ms, res, work):
+        e = {"ms": ms, "steps_per_s": res["counters"]["steps"] / ms * 1e3, "speedup": base_ms / ms,
+             "dist_in_fp64": work["dist_in"], "dist_in_fp32": work["dist_in_f32"]}
+        same = all(res["counters"][k] == base["counters"][k]
+                   for k in ("steps", "pe", "compton", "pair", "crossings", "escaped", "tracks"))
+        d = np.abs(res["edep_event"] - base["edep_event"]) / np.maximum(base["edep_event"], 1e-300)
+        e["same_counters"] = bool(same)
+        e["max_rel_event_deposit_diff"] = float(d[base["edep_event"] > 0].max())
+        return e
+
+    out["fp64"] = {"ms": base_ms, "steps_per_s": steps / base_ms * 1e3, "steps": steps,
+                   "dist_in_fp64": base_w["dist_in"]}
+    out["fp64_bound_order"] = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, order=1))
+    out["fp32_screened"] = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, precision=1))
+    pure = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, precision=2))
+    # pure FP32: deposit histogram chi-square per degree of freedom against FP64
+    tally.reset(stream)
+    ctx.transport_batch(gid, prim_d, tally, stream=stream, precision=2)
+    pr = tally.read(stream)
+    bins = np.logspace(-3, np.log10(25.0), 41)
+    ha = np.histogram(base["edep_event"], bins)[0].astype(float)
+    hb = np.histogram(pr["edep_event"], bins)[0].astype(float)
+    m = (ha + hb) > 0
+    pure["chi2_per_ndf_event_deposits"] = float(np.sum((ha[m] - hb[m]) ** 2 / (ha[m] + hb[m])) /
+                                               max(int(m.sum()) - 1, 1))
+    pure["pushes"] = pr["counters"]["pushes"]
+    pure["stuck"] = pr["counters"]["stuck"]
+    out["fp32_pure"] = pure
+    # per-query FP32 error against FP64 (the FP64 query path equals the oracle per query)
+    rng = np.random.Generator(np.random.Philox(key=77))
+    q = 100_000
+    pts = np.column_stack([rng.uniform(-1500, 1500, q), rng.uniform(-1500, 1500, q),
+                           rng.uniform(-2900, 2900, q)])
+    dirs = W.primaries.isotropic(rng, q)
+    pt, dt = torch.from_numpy(pts).cuda(), torch.from_numpy(dirs).cuda()
+    s64, l64, _ = ctx.compute_step(gid, pt, dt, with_next=False)
+    s32, l32, _ = ctx.compute_step(gid, pt, dt, with_next=False, precision=2)
+    s64, l64, s32, l32 = (x.cpu().numpy() for x in (s64, l64, s32, l32))
+    fin = np.isfinite(s64) & np.isfinite(s32)
+    err = np.abs(s32[fin] - s64[fin])
+    out["fp32_pure"]["per_query"] = {
+        "queries": q, "limiter_agreement": float(np.mean(l32 == l64)),
+        "abs_err_median_mm": float(np.median(err)), "abs_err_p99_mm": float(np.quantile(err, 0.99)),
+        "rel_err_p99": float(np.quantile(err / np.maximum(s64[fin], 1.0), 0.99))}
+    # learned order: record crossings (other seeds), train on the GPU, time
+    if train_photons > 0:
+        t0 = time.perf_counter()
+        _, tprim, _ = W.barrel(n=train_photons, seed=1)
+        rec = learned.record_crossings(ctx, gid, gnav.primaries_to_device(tprim, "cuda"),
+                                       tprim.n_events, capacity=8_000_000, seed=1)
+        x, cls, label = learned.records_to_tensors(rec)
+        t1 = time.perf_counter()
+        net, losses = learned.train(ctx, ctx.ordering_classes(gid), x, cls, label, epochs=2, batch=4096)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.set_mlp(gid, net)
+        e = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, order=2))
+        e["training"] = {"crossings": int(x.shape[0]), "epochs": 2, "batch": 4096,
+                         "record_s": t1 - t0, "train_s": t2 - t1,
+                         "accuracy_top1": learned.accuracy(net, x[:200_000], cls[:200_000],
+                                                           label[:200_000])}
+        out["fp64_learned_order"] = e
+        ctx.set_mlp(gid, None)
+        net.free()
+    tally.free()
+    return out
 
 
 def main():
@@ -72,9 +220,17 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000, help="photons per batch")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=400_000,
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="primaries of the same workload for the oracle timing (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes for the all-cores figure (0: min(16, cpus))")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--barrel-n", type=int, default=10_000_000,
+                    help="photons of the barrel variant comparison (0: skip)")
+    ap.add_argument("--train-photons", type=int, default=1_000_000,
+                    help="photons whose crossings train the learned order (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -83,6 +239,13 @@ def main():
               "(events are independent, see the sharding notes in the design document)",
               file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline runs first, in processes forked before any GPU use
+    cpu = None
+    if not args.no_cpu and args.cpu_sample > 0:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(args.cpu_sample, workers)
+        print(f"cpu baseline done: {cpu}", file=sys.stderr, flush=True)
 
     import torch
     import workloads as W
@@ -96,18 +259,22 @@ def main():
     prim_d = gnav.primaries_to_device(prim, dev)
     tally = ctx.tally_create(prim.n_events)
     stream = torch.cuda.current_stream()
-
-    def one_batch():
-        tally.reset(stream)
-        ctx.transport_batch(gid, prim_d, tally, seed=0, block=args.block, grid=args.grid,
-                            stream=stream)
+    kw = dict(seed=0, block=args.block, grid=args.grid)
+    if args.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
-        one_batch()
+        tally.reset(stream)
+        ctx.transport_batch(gid, prim_d, tally, stream=stream, **kw)
     torch.cuda.synchronize()
-    # counters of one batch (identical every batch: counter-keyed random numbers)
+    # counters of one batch (identical every batch: counter-keyed random numbers);
+    # the work counters (candidate evaluations etc.) come from a counting launch
     tally.reset(stream)
-    ctx.transport_batch(gid, prim_d, tally, seed=0, block=args.block, grid=args.grid, stream=stream)
+    ctx.transport_batch(gid, prim_d, tally, stream=stream, count_work=True, **kw)
     c = tally.read(stream)["counters"]
     steps_per_batch = c["steps"]
 
@@ -119,11 +286,11 @@ def main():
     for i in range(args.steps):
         tally.reset(stream)
         starts[i].record(stream)
-        ctx.transport_batch(gid, prim_d, tally, seed=0, block=args.block, grid=args.grid,
-                            stream=stream)
+        ctx.transport_batch(gid, prim_d, tally, stream=stream, **kw)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    print(f"timed region done: {args.steps} batches in {wall:.3f} s", file=sys.stderr, flush=True)
     kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     avg_kern_s = float(np.mean(kern_ms)) / 1e3
     ms_per_step = wall * 1e3 / args.steps
@@ -131,6 +298,7 @@ def main():
 
     flops = algorithmic_flops(c)
     achieved_tf = flops / avg_kern_s / 1e12
+    traffic = stored_traffic()
     out = {
         "metric": "gamma navigation steps/s on 1 GPU",
         "value": value,
@@ -159,21 +327,31 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP64_TFLOPS,
-            "traffic": None,
-            "kernel": "k_transport<false>",
+            "traffic": traffic,
+            "kernel": "k_transport<false, false, 0, 0>",
             "kernel_ms": avg_kern_s * 1e3,
             "flops_per_launch": flops,
+            "kernel_source_hash": kernel_source_hash(),
         },
         "counters": c,
     }
-    if not args.no_cpu and args.cpu_sample > 0:
-        rate, dt, nsteps = cpu_baseline(args.cpu_sample)
+    if cpu is not None:
+        rate, dt, nsteps = cpu["single"]
         out["cpu_baseline"] = {
             "value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"first {args.cpu_sample} primaries of the same calorimeter workload "
-                      f"({nsteps} steps in {dt:.1f} s, single thread, brute-force navigation)",
+                      f"({nsteps} steps in {dt:.1f} s, one thread, brute-force navigation)",
         }
+        if "all" in cpu:
+            rate, dt, nsteps = cpu["all"]
+            out["cpu_baseline_all_cores"] = {
+                "value": rate, "unit": "steps/s", "cores": workers, "kind": "oracle",
+                "sample": f"the same {args.cpu_sample} primaries in {workers} single-threaded "
+                          f"oracle processes ({nsteps} steps in {dt:.1f} s wall)"}
     tally.free()
+    if args.barrel_n > 0:
+        out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
+        print("barrel variants done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -153,6 +153,18 @@ __device__ __forceinline__ V3 xf_dir(const double* __restrict__ m, int kind, V3 
 // instantiation carries no hidden double arithmetic.
 // ---------------------------------------------------------------------------
 
+// Half width of the surface band.  FP64 uses the navigation tolerance; the
+// FP32 instantiation (used for steps only by the pure FP32 form) needs a
+// band wider than FP32 rounding of coordinates of a few metres (2.4e-4 mm
+// per unit in the last place at 3 m), so it uses 1e-3 mm.
+constexpr float kHalfTolF = 1e-3f;
+template <typename R>
+__device__ __forceinline__ constexpr R half_tol();
+template <>
+__device__ __forceinline__ constexpr double half_tol<double>() { return kHalfTol; }
+template <>
+__device__ __forceinline__ constexpr float half_tol<float>() { return kHalfTolF; }
+
 template <typename R>
 __device__ __forceinline__ R tmax(R a, R b) { return a > b ? a : b; }
 template <typename R>
@@ -182,7 +194,7 @@ __device__ __forceinline__ int box_inside(const double* h, V3 p, bool has_v, V3 
 // Slab entry: the ray enters when it is inside all three slabs.
 template <typename R>
 __device__ __forceinline__ R box_dist_in(const R* h, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  const R ht = half_tol<R>(), inf = R(kInf), zero = R(0);
   if (fabs(p.x) - h[0] >= -ht && p.x * v.x >= zero) return inf;
   if (fabs(p.y) - h[1] >= -ht && p.y * v.y >= zero) return inf;
   if (fabs(p.z) - h[2] >= -ht && p.z * v.z >= zero) return inf;
@@ -203,7 +215,7 @@ __device__ __forceinline__ R box_dist_in(const R* h, Vec3<R> p, Vec3<R> v) {
 
 template <typename R>
 __device__ __forceinline__ R box_dist_out(const R* h, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), zero = R(0);
+  const R ht = half_tol<R>(), zero = R(0);
   R t = R(kInf);
   const R pc[3] = {p.x, p.y, p.z};
   const R vc[3] = {v.x, v.y, v.z};
@@ -238,7 +250,7 @@ __device__ __forceinline__ int orb_inside(double rad, V3 p, bool has_v, V3 v) {
 
 template <typename R>
 __device__ __forceinline__ R orb_dist_in(R rad, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  const R ht = half_tol<R>(), inf = R(kInf), zero = R(0);
   R rr = p.x * p.x + p.y * p.y + p.z * p.z;
   R sd = sqrt(rr) - rad;
   R b = p.x * v.x + p.y * v.y + p.z * v.z;
@@ -256,7 +268,7 @@ __device__ __forceinline__ R orb_dist_in(R rad, Vec3<R> p, Vec3<R> v) {
 
 template <typename R>
 __device__ __forceinline__ R orb_dist_out(R rad, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), zero = R(0);
+  const R ht = half_tol<R>(), zero = R(0);
   R rr = p.x * p.x + p.y * p.y + p.z * p.z;
   R sd = sqrt(rr) - rad;
   R b = p.x * v.x + p.y * v.y + p.z * v.z;
@@ -365,7 +377,7 @@ __device__ __forceinline__ R radial_root(R A, R B, Vec3<R> p, Vec3<R> v, int wan
 
 template <typename R>
 __device__ __forceinline__ bool rad_ok_except(const R* q, int info, Vec3<R> p, Vec3<R> v, R t, int skip) {
-  const R ht = R(kHalfTol);
+  const R ht = half_tol<R>();
   Vec3<R> r{p.x + t * v.x, p.y + t * v.y, p.z + t * v.z};
   RadComps<R> k = rad_comps(q, info, r);
   if (skip != 0 && k.ro > ht) return false;
@@ -380,7 +392,7 @@ __device__ __forceinline__ bool rad_ok_except(const R* q, int info, Vec3<R> p, V
 // every other component holds at the crossing point.
 template <typename R>
 __device__ __forceinline__ R rad_dist_in(const R* q, int info, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), inf = R(kInf), zero = R(0);
+  const R ht = half_tol<R>(), inf = R(kInf), zero = R(0);
   RadComps<R> k = rad_comps(q, info, p);
   if (rad_dmax(k) < -ht) return zero;
   R rho = sqrt(p.x * p.x + p.y * p.y);
@@ -431,7 +443,7 @@ __device__ __forceinline__ R rad_dist_in(const R* q, int info, Vec3<R> p, Vec3<R
 
 template <typename R>
 __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<R> v) {
-  const R ht = R(kHalfTol), zero = R(0);
+  const R ht = half_tol<R>(), zero = R(0);
   RadComps<R> k = rad_comps(q, info, p);
   R rho = sqrt(p.x * p.x + p.y * p.y);
   R rv = rho > zero ? (p.x * v.x + p.y * v.y) / rho : zero;

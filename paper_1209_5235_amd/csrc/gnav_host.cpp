@@ -300,15 +300,31 @@ bool extent_is_tight(int type, const double* R) {
 }
 
 // ---------------------------------------------------------------------------
-// Voxel grid choice: per axis a slice count from a small candidate set; the
-// score is the mean number of candidates per node (separable per daughter:
-// sum of slice spans products / nodes) plus a small per-slice walk cost.
+// Voxel grids (the smart voxels of Sec. 3.2's navigation, uniform per
+// mother).  Grid choice: per axis a slice count from a small candidate set;
+// the score is the mean number of candidates per node plus a small
+// per-slice walk cost.  The first search counts bounding-box overlaps
+// (separable per daughter: sum of slice span products / nodes); mothers whose
+// daughters' boxes overlap heavily (concentric shells) get a second search
+// with shape-aware counts.  Node lists always hold exactly the daughters
+// whose solid may meet the node (conservative shape test), not every
+// daughter whose bounding box does.
 // ---------------------------------------------------------------------------
 
 struct VoxBuild {
   double lo[3], w[3], inv_w[3];
   int n[3];
   std::vector<std::vector<uint16_t>> nodes;
+};
+
+// A placed daughter as the voxel builder sees it: padded extent in the
+// mother frame plus the solid itself, for shape-aware node lists.
+struct DauShape {
+  Box3 box;
+  int info;
+  double q[kSolidPar];
+  double R[9];  // daughter -> mother rotation: x_mother = R x_local + t
+  double t[3];
 };
 
 int span_lo(double x, double lo, double w, int n) {
@@ -318,26 +334,125 @@ int span_lo(double x, double lo, double w, int n) {
   return (int)f;
 }
 
-VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
+// Conservative test: may the daughter's solid meet box b (mother frame)?
+// The box goes to the daughter frame as the extent of its 8 transformed
+// corners, grown by pad; boxes are tested slab-wise, orbs by the box's
+// nearest point, tube and cone sections by the range of the distance to the
+// axis over the box against the radii over the box's z range (phi sections
+// are not used to reject).  A false "meets" only costs a candidate; a false
+// "misses" never happens.
+bool shape_meets_box(const DauShape& d, const Box3& b, double pad) {
+  for (int a = 0; a < 3; a++)
+    if (b.hi[a] < d.box.lo[a] || b.lo[a] > d.box.hi[a]) return false;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int c = 0; c < 8; c++) {
+    double p[3] = {((c & 1) ? b.hi[0] : b.lo[0]) - d.t[0], ((c & 2) ? b.hi[1] : b.lo[1]) - d.t[1],
+                   ((c & 4) ? b.hi[2] : b.lo[2]) - d.t[2]};
+    for (int i = 0; i < 3; i++) {
+      double x = d.R[i] * p[0] + d.R[3 + i] * p[1] + d.R[6 + i] * p[2];  // R^T p
+      lo[i] = std::min(lo[i], x);
+      hi[i] = std::max(hi[i], x);
+    }
+  }
+  for (int i = 0; i < 3; i++) {
+    lo[i] -= pad;
+    hi[i] += pad;
+  }
+  const double* q = d.q;
+  switch (d.info & 15) {
+    case kBox:
+      for (int i = 0; i < 3; i++)
+        if (hi[i] < -q[i] || lo[i] > q[i]) return false;
+      return true;
+    case kOrb: {
+      double s2 = 0;
+      for (int i = 0; i < 3; i++) {
+        double e = lo[i] > 0 ? lo[i] : (hi[i] < 0 ? -hi[i] : 0.0);
+        s2 += e * e;
+      }
+      return s2 <= q[0] * q[0];
+    }
+    default: {
+      double dz = q[R_DZ];
+      double z0 = std::max(lo[2], -dz), z1 = std::min(hi[2], dz);
+      if (z0 > z1) return false;
+      double ex = lo[0] > 0 ? lo[0] : (hi[0] < 0 ? -hi[0] : 0.0);
+      double ey = lo[1] > 0 ? lo[1] : (hi[1] < 0 ? -hi[1] : 0.0);
+      double rho_min = std::sqrt(ex * ex + ey * ey);
+      double fx = std::max(std::fabs(lo[0]), std::fabs(hi[0]));
+      double fy = std::max(std::fabs(lo[1]), std::fabs(hi[1]));
+      double rho_max = std::sqrt(fx * fx + fy * fy);
+      double r_out = q[R_AO] + q[R_BO] * (q[R_BO] > 0 ? z1 : z0);
+      if (rho_min > r_out) return false;
+      if (d.info & kInfoInner) {
+        double r_in = q[R_AI] + q[R_BI] * (q[R_BI] > 0 ? z0 : z1);
+        if (rho_max < r_in) return false;
+      }
+      return true;
+    }
+  }
+}
+
+// Node box of grid (lo, w) at index (i, j, k), grown by pad.
+Box3 node_box(const double* lo, const double* w, int i, int j, int k, double pad) {
+  Box3 b;
+  const int ix[3] = {i, j, k};
+  for (int a = 0; a < 3; a++) {
+    b.lo[a] = lo[a] + ix[a] * w[a] - pad;
+    b.hi[a] = lo[a] + (ix[a] + 1) * w[a] + pad;
+  }
+  return b;
+}
+
+// Mean candidates per node of grid n over box g with shape-aware lists:
+// every node when there are at most 512, else a fixed pseudo-random sample.
+double shape_cost(const Box3& g, const int* n, const std::vector<DauShape>& dau, double pad) {
+  double w[3];
+  for (int a = 0; a < 3; a++) w[a] = (g.hi[a] - g.lo[a]) / n[a];
+  const long total = (long)n[0] * n[1] * n[2];
+  const long samples = std::min<long>(total, 512);
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+  double sum = 0;
+  for (long s = 0; s < samples; s++) {
+    long id = s;
+    if (samples < total) {
+      h ^= h << 13;
+      h ^= h >> 7;
+      h ^= h << 17;
+      id = (long)(h % (uint64_t)total);
+    }
+    int i = (int)(id / ((long)n[1] * n[2])), j = (int)((id / n[2]) % n[1]), k = (int)(id % n[2]);
+    Box3 b = node_box(g.lo, w, i, j, k, pad);
+    for (const DauShape& d : dau) sum += shape_meets_box(d, b, pad) ? 1.0 : 0.0;
+  }
+  return sum / samples;
+}
+
+VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau) {
   const int cnt = (int)dau.size();
   Box3 g = mother;
-  for (const Box3& d : dau) {
+  for (const DauShape& d : dau) {
     for (int a = 0; a < 3; a++) {
-      g.lo[a] = std::min(g.lo[a], d.lo[a]);
-      g.hi[a] = std::max(g.hi[a], d.hi[a]);
+      g.lo[a] = std::min(g.lo[a], d.box.lo[a]);
+      g.hi[a] = std::max(g.hi[a], d.box.hi[a]);
     }
   }
   // pad the grid box slightly so points on its faces map inside
+  double scale = 1.0;
   for (int a = 0; a < 3; a++) {
     double s = 1e-9 * std::max(1.0, std::max(std::fabs(g.lo[a]), std::fabs(g.hi[a])));
     g.lo[a] -= s;
     g.hi[a] += s;
+    scale = std::max(scale, std::max(std::fabs(g.lo[a]), std::fabs(g.hi[a])));
   }
+  // node boxes are grown by pad before the shape test (well above the
+  // surface tolerance, so surface points find their daughters)
+  const double pad = 1e-6 + 1e-12 * scale;
   const int max_nodes = std::max(64, std::min(1 << 18, 8 * cnt));
   std::vector<int> opts[3];
   for (int a = 0; a < 3; a++) {
     std::vector<double> w;
-    for (const Box3& d : dau) w.push_back(d.hi[a] - d.lo[a]);
+    for (const DauShape& d : dau) w.push_back(d.box.hi[a] - d.box.lo[a]);
     std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
     double med = std::max(w[w.size() / 2], 1e-6);
     double L = g.hi[a] - g.lo[a];
@@ -350,20 +465,20 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
     o.erase(std::unique(o.begin(), o.end()), o.end());
     opts[a] = o;
   }
-  // spans[a][option][daughter]
+  // bounding-box cost: spans[a][option][daughter]
   std::vector<std::vector<std::vector<int>>> spans(3);
   for (int a = 0; a < 3; a++) {
     for (int n : opts[a]) {
       double w = (g.hi[a] - g.lo[a]) / n;
       std::vector<int> s(cnt);
       for (int d = 0; d < cnt; d++) {
-        s[d] = span_lo(dau[d].hi[a], g.lo[a], w, n) - span_lo(dau[d].lo[a], g.lo[a], w, n) + 1;
+        s[d] = span_lo(dau[d].box.hi[a], g.lo[a], w, n) - span_lo(dau[d].box.lo[a], g.lo[a], w, n) + 1;
       }
       spans[a].push_back(std::move(s));
     }
   }
-  double best = INFINITY;
-  int bi[3] = {0, 0, 0};
+  double best = INFINITY, best_cand = 0;
+  int bn[3] = {1, 1, 1};
   for (size_t i = 0; i < opts[0].size(); i++)
     for (size_t j = 0; j < opts[1].size(); j++)
       for (size_t k = 0; k < opts[2].size(); k++) {
@@ -375,17 +490,40 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
         double score = tot / nodes + 0.02 * (opts[0][i] + opts[1][j] + opts[2][k]);
         if (score < best - 1e-12) {
           best = score;
-          bi[0] = (int)i;
-          bi[1] = (int)j;
-          bi[2] = (int)k;
+          best_cand = tot / nodes;
+          bn[0] = opts[0][i];
+          bn[1] = opts[1][j];
+          bn[2] = opts[2][k];
         }
       }
+  // Daughters whose bounding boxes overlap heavily (nested shells, sections
+  // around an axis) leave many candidates per node: then search again with
+  // shape-aware counts over power-of-two grids, allowing finer grids.
+  if (best_cand > 4.0) {
+    double cur = shape_cost(g, bn, dau, pad) + 0.02 * (bn[0] + bn[1] + bn[2]);
+    const long max_fine = std::max<long>(max_nodes, std::min<long>(1 << 16, 64L * cnt));
+    const int ladder[] = {1, 2, 4, 8, 16, 32, 64, 128};
+    for (int nx : ladder)
+      for (int ny : ladder)
+        for (int nz : ladder) {
+          if ((long)nx * ny * nz > max_fine) continue;
+          const int n3[3] = {nx, ny, nz};
+          double score = 0.02 * (nx + ny + nz);
+          if (score >= cur) continue;
+          score += shape_cost(g, n3, dau, pad);
+          if (score < cur - 1e-12) {
+            cur = score;
+            bn[0] = nx;
+            bn[1] = ny;
+            bn[2] = nz;
+          }
+        }
+  }
   VoxBuild vb;
   for (int a = 0; a < 3; a++) {
-    int n = opts[a][bi[a]];
-    vb.n[a] = n;
+    vb.n[a] = bn[a];
     vb.lo[a] = g.lo[a];
-    vb.w[a] = (g.hi[a] - g.lo[a]) / n;
+    vb.w[a] = (g.hi[a] - g.lo[a]) / bn[a];
     vb.inv_w[a] = 1.0 / vb.w[a];
   }
   const int nx = vb.n[0], ny = vb.n[1], nz = vb.n[2];
@@ -393,12 +531,14 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<Box3>& dau) {
   for (int d = 0; d < cnt; d++) {
     int l[3], h[3];
     for (int a = 0; a < 3; a++) {
-      l[a] = span_lo(dau[d].lo[a], g.lo[a], vb.w[a], vb.n[a]);
-      h[a] = span_lo(dau[d].hi[a], g.lo[a], vb.w[a], vb.n[a]);
+      l[a] = span_lo(dau[d].box.lo[a], g.lo[a], vb.w[a], vb.n[a]);
+      h[a] = span_lo(dau[d].box.hi[a], g.lo[a], vb.w[a], vb.n[a]);
     }
     for (int i = l[0]; i <= h[0]; i++)
       for (int j = l[1]; j <= h[1]; j++)
-        for (int k = l[2]; k <= h[2]; k++) vb.nodes[((size_t)i * ny + j) * nz + k].push_back((uint16_t)d);
+        for (int k = l[2]; k <= h[2]; k++)
+          if (shape_meets_box(dau[d], node_box(vb.lo, vb.w, i, j, k, pad), pad))
+            vb.nodes[((size_t)i * ny + j) * nz + k].push_back((uint16_t)d);
   }
   return vb;
 }
@@ -719,18 +859,23 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
     lr.lclass = -1;
     bool want = d->lv_voxelize ? d->lv_voxelize[l] != 0 : true;
     if (want && d->lv_dau_cnt[l] >= 3) {
-      std::vector<Box3> db;
+      std::vector<DauShape> db;
       for (int k = 0; k < d->lv_dau_cnt[l]; k++) {
         int p = d->lv_dau_off[l] + k;
         int ds = d->lv_solid[d->pv_lv[p]];
-        Box3 b = place_solid(d->solid_type[ds], d->solid_par + 8 * ds, ext[ds], d->pv_rot + 9 * p,
+        DauShape sh;
+        sh.box = place_solid(d->solid_type[ds], d->solid_par + 8 * ds, ext[ds], d->pv_rot + 9 * p,
                              d->pv_trans + 3 * p);
         for (int a = 0; a < 3; a++) {
-          double pad = 1e-7 + 1e-12 * std::max(std::fabs(b.lo[a]), std::fabs(b.hi[a]));
-          b.lo[a] -= pad;
-          b.hi[a] += pad;
+          double pad = 1e-7 + 1e-12 * std::max(std::fabs(sh.box.lo[a]), std::fabs(sh.box.hi[a]));
+          sh.box.lo[a] -= pad;
+          sh.box.hi[a] += pad;
         }
-        db.push_back(b);
+        sh.info = info[ds];
+        for (int i = 0; i < kSolidPar; i++) sh.q[i] = q[(size_t)ds * kSolidStride + i];
+        for (int i = 0; i < 9; i++) sh.R[i] = d->pv_rot[9 * p + i];
+        for (int i = 0; i < 3; i++) sh.t[i] = d->pv_trans[3 * p + i];
+        db.push_back(sh);
       }
       VoxBuild vb = build_voxels(ext[d->lv_solid[l]], db);
       lr.vox = 1;

@@ -812,7 +812,11 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             log_rec<LOG>(P, a, s, T, lim, s_geo, 0.0, E);
             P.cnt_b[s] += 1u;
             P.saf[s] = 0.0;
-            zero = (s_geo < kTol) ? zero + 1 : 0;
+            // zero-length steps and the push that ends a run of them, on the
+            // length scale of the surface band of the distance arithmetic
+            constexpr double kZeroLen = PREC == kPrecPure ? 2.0 * kHalfTolF : kTol;
+            constexpr double kPushLen = PREC == kPrecPure ? 10.0 * kZeroLen : 100.0 * kTol;
+            zero = (s_geo < kZeroLen) ? zero + 1 : 0;
             P.zero_steps[s] = (steps << 8) | zero;
             if (zero >= kZeroKill) {
               atomic_add_f64(a.edep_t + T, E);
@@ -820,9 +824,9 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
               end_track<LOG>(P, a, s, GNAV_FATE_STUCK, steps);
             } else {
               if (zero > 0 && zero % kZeroPush == 0) {
-                P.x[s] = P.x[s] + 100.0 * kTol * v.x;
-                P.y[s] = P.y[s] + 100.0 * kTol * v.y;
-                P.z[s] = P.z[s] + 100.0 * kTol * v.z;
+                P.x[s] = P.x[s] + kPushLen * v.x;
+                P.y[s] = P.y[s] + kPushLen * v.y;
+                P.z[s] = P.z[s] + kPushLen * v.z;
                 P.cnt_b[s] += 1u << 24;
               }
               // relocation happens in the next iteration's navigation phase
