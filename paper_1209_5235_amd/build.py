@@ -34,20 +34,23 @@ def hipcc():
     return h
 
 
-def build(verbose=False, defines=(), out=None):
-    """Compile the sources; `defines` adds -D flags, `out` overrides the library path."""
-    objs = []
-    tmpdir = os.path.join(HERE, "_build")
+def build(verbose=False, defines=(), out=None, objdir=None):
+    """Compile the sources (in parallel); `defines` adds -D flags, `out` overrides the
+    library path and `objdir` the object directory."""
+    tmpdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(tmpdir, src + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc()] + lang + HIPFLAGS + [f"-D{d}" for d in defines] + ["-I", INCLUDE, "-I", CSRC, "-c",
-                                             os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), "-x", "hip"] + HIPFLAGS + [f"-D{d}" for d in defines] + \
+              ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     target = out or LIB
     tmp = target + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
