@@ -233,6 +233,7 @@ __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtom
 
 constexpr int kPool = 256;
 constexpr int kWaves = kPool / 64;
+constexpr int kStack = 64;  // block stack of annihilation photons (entries)
 
 // slot status
 enum : int { kEmpty = 0, kNav = 1, kStep = 2, kInt = 3 };
@@ -253,6 +254,11 @@ struct Pool {
   unsigned cnt_a[kPool];  // Compton scatters | shortcuts << 16
   unsigned cnt_b[kPool];  // crossings | pushes << 24
   int pred[kPool];     // learned order: predicted candidate position of the next step
+  double dep[kPool];   // deposits of the slot's current track, added to its event at the end
+  // annihilation photons waiting for any free slot of the block (a stack)
+  double sx[kStack], sy[kStack], sz[kStack], svx[kStack], svy[kStack], svz[kStack];
+  int sev[kStack], skey[kStack], stb[kStack], sprim[kStack];
+  int sn;              // valid stack entries
   int list[kPool];
   int wcnt[16 * kWaves];
   int total[16];
@@ -300,6 +306,7 @@ __device__ __forceinline__ int compact(Pool& P, bool flag, int key) {
 template <bool LOG>
 __device__ __forceinline__ void end_track(Pool& P, const TransportArgs& a, int s, int fate, int steps) {
   P.status[s] = kEmpty;
+  if (P.dep[s] != 0.0) atomic_add_f64(a.edep_ev + P.event[s], P.dep[s]);
   int slot = fate == GNAV_FATE_ABSORBED ? GNAV_C_PE
            : fate == GNAV_FATE_PAIR     ? GNAV_C_PAIR
            : fate == GNAV_FATE_ESCAPED  ? GNAV_C_ESCAPED
@@ -497,7 +504,10 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
 
   if (tid < GNAV_NCOUNTERS) P.cnt[tid] = 0ull;
   if (tid < 4) P.qr[tid] = 0;
-  if (tid == 0) P.qopen = 1;
+  if (tid == 0) {
+    P.qopen = 1;
+    P.sn = 0;
+  }
   P.status[tid] = kEmpty;
   P.sub_pend[tid] = 0;
   NavCount<COUNT> nc;
@@ -527,6 +537,43 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         start = true;
       }
       bool need = empty && !start;
+      // annihilation photons parked on the block stack go to free slots first
+      const int sn = P.sn;
+      if (sn > 0) {
+        const int w = tid >> 6;
+        unsigned long long mask = __ballot(need);
+        if (lane == 0) P.wcnt[w] = __popcll(mask);
+        __syncthreads();
+        int before = 0, n_need = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ww++) {
+          int c = P.wcnt[ww];
+          if (ww < w) before += c;
+          n_need += c;
+        }
+        if (need) {
+          int rank = before + __popcll(mask & lt_mask);
+          if (rank < sn) {
+            const int e = sn - 1 - rank;
+            P.x[s] = P.sx[e];
+            P.y[s] = P.sy[e];
+            P.z[s] = P.sz[e];
+            P.vx[s] = P.svx[e];
+            P.vy[s] = P.svy[e];
+            P.vz[s] = P.svz[e];
+            P.E[s] = kMe;
+            P.event[s] = P.sev[e];
+            P.key[s] = P.skey[e];
+            P.tbase[s] = P.stb[e];
+            P.prim[s] = P.sprim[e];
+            P.sub_pend[s] = P.skey[e] & 3;
+            start = true;
+            need = false;
+          }
+        }
+        __syncthreads();
+        if (tid == 0) P.sn = sn - min(sn, n_need);
+      }
       long idx = -1;
       if (a.chunk <= 0) {
         // each wave claims exactly the primaries its idle lanes need
@@ -652,6 +699,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         if (mode == kNavStart) {
           atomicAdd(&P.cnt[GNAV_C_TRACKS], 1ull);
           P.draw[s] = 0;
+          P.dep[s] = 0.0;
           P.nrec[s] = 0;
           P.zero_steps[s] = 0;
           P.cnt_a[s] = 0;
@@ -721,7 +769,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         int zero = zs & 0xFF;
         if (E < a.ecut) {
           atomic_add_f64(a.edep_t + T, E);
-          atomic_add_f64(a.edep_ev + P.event[s], E);
+          P.dep[s] += E;
           end_track<LOG>(P, a, s, GNAV_FATE_CUTOFF, steps);
         } else if (steps >= a.max_steps) {
           end_track<LOG>(P, a, s, GNAV_FATE_TRUNCATED, steps);
@@ -801,15 +849,18 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             P.slast[s] = s_phys;
             P.status[s] = kInt;
           } else {
-            P.x[s] = x.x + s_geo * v.x;
-            P.y[s] = x.y + s_geo * v.y;
-            P.z[s] = x.z + s_geo * v.z;
+            // the pure FP32 form steps past the boundary by its surface band, so
+            // the FP64 relocation sees the point on the far side of the face
+            const double s_adv = PREC == kPrecPure ? s_geo + 2.0 * (double)kHalfTolF : s_geo;
+            P.x[s] = x.x + s_adv * v.x;
+            P.y[s] = x.y + s_adv * v.y;
+            P.z[s] = x.z + s_adv * v.z;
             if (mu > 0) {
-              nl = nl - s_geo * mu;
+              nl = nl - s_adv * mu;
               if (nl < 0) nl = 0;
               P.nl[s] = nl;
             }
-            log_rec<LOG>(P, a, s, T, lim, s_geo, 0.0, E);
+            log_rec<LOG>(P, a, s, T, lim, s_adv, 0.0, E);
             P.cnt_b[s] += 1u;
             P.saf[s] = 0.0;
             // zero-length steps and the push that ends a run of them, on the
@@ -820,7 +871,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             P.zero_steps[s] = (steps << 8) | zero;
             if (zero >= kZeroKill) {
               atomic_add_f64(a.edep_t + T, E);
-              atomic_add_f64(a.edep_ev + P.event[s], E);
+              P.dep[s] += E;
               end_track<LOG>(P, a, s, GNAV_FATE_STUCK, steps);
             } else {
               if (zero > 0 && zero % kZeroPush == 0) {
@@ -853,7 +904,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         Philox rs{(uint32_t)event, (uint32_t)P.key[s], (uint32_t)P.draw[s]};
         if (proc == kProcPE) {
           atomic_add_f64(a.edep_t + T, E);
-          atomic_add_f64(a.edep_ev + event, E);
+          P.dep[s] += E;
           log_rec<LOG>(P, a, s, T, kLimPE, sl, E, 0.0);
           end_track<LOG>(P, a, s, GNAV_FATE_ABSORBED, steps);
         } else if (proc == kProcCompton) {
@@ -874,7 +925,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           P.imu_mat[s] = imu;  // cached mu invalid
           P.wmu[s] = w;
           atomic_add_f64(a.edep_t + T, dep);
-          atomic_add_f64(a.edep_ev + event, dep);
+          P.dep[s] += dep;
           P.cnt_a[s] += 1u;
           log_rec<LOG>(P, a, s, T, kLimCompton, sl, dep, E2);
           P.nl[s] = -log(rng_next(rs, a.seed_lo, a.seed_hi));
@@ -883,19 +934,41 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         } else {
           double dep = E - 2.0 * kMe;
           atomic_add_f64(a.edep_t + T, dep);
-          atomic_add_f64(a.edep_ev + event, dep);
+          P.dep[s] += dep;
           double u1 = rng_next(rs, a.seed_lo, a.seed_hi), u2 = rng_next(rs, a.seed_lo, a.seed_hi);
           double ct = 1.0 - 2.0 * u1;
           double st = 2.0 * sqrt(u1 * (1.0 - u1));
           double ph = kTwoPi * u2;
-          double* pd = a.pend + ((long)blockIdx.x * kPool + s) * 6;
-          pd[0] = P.x[s];
-          pd[1] = P.y[s];
-          pd[2] = P.z[s];
-          pd[3] = st * cos(ph);
-          pd[4] = st * sin(ph);
-          pd[5] = ct;
-          P.sub_pend[s] = (P.sub_pend[s] & 15) | (2 << 4);
+          const double wx = st * cos(ph), wy = st * sin(ph), wz = ct;
+          // both photons onto the block stack, so two free slots can take them
+          // at once; when it is full, this slot tracks them one after the other
+          const int e = atomicAdd(&P.sn, 2);
+          if (e + 2 <= kStack) {
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+              const double sg = j == 0 ? 1.0 : -1.0;
+              P.sx[e + j] = P.x[s];
+              P.sy[e + j] = P.y[s];
+              P.sz[e + j] = P.z[s];
+              P.svx[e + j] = sg * wx;
+              P.svy[e + j] = sg * wy;
+              P.svz[e + j] = sg * wz;
+              P.sev[e + j] = event;
+              P.skey[e + j] = (P.key[s] & ~3) | (j + 1);
+              P.stb[e + j] = P.tbase[s];
+              P.sprim[e + j] = P.prim[s];
+            }
+          } else {
+            atomicSub(&P.sn, 2);
+            double* pd = a.pend + ((long)blockIdx.x * kPool + s) * 6;
+            pd[0] = P.x[s];
+            pd[1] = P.y[s];
+            pd[2] = P.z[s];
+            pd[3] = wx;
+            pd[4] = wy;
+            pd[5] = wz;
+            P.sub_pend[s] = (P.sub_pend[s] & 15) | (2 << 4);
+          }
           log_rec<LOG>(P, a, s, T, kLimPair, sl, dep, 0.0);
           end_track<LOG>(P, a, s, GNAV_FATE_PAIR, steps);
         }
