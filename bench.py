@@ -212,6 +212,47 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
     return out
 
 
+def batched_config(ctx, gnav, reps):
+    """Uneven events over eight resident geometries in one launch: autotuned
+    launch settings, then the tuned launch captured in a HIP graph."""
+    import torch
+    import workloads as W
+    t0 = time.perf_counter()
+    geoms, prim, event_geom = W.batched()
+    gids = [ctx.upload_geometry(g)[0] for g in geoms]
+    prim_d = gnav.primaries_to_device(prim, "cuda")
+    eg = torch.from_numpy(np.asarray(event_geom, np.int32) + gids[0]).cuda()
+    tally = ctx.tally_create(prim.n_events)
+    stream = torch.cuda.current_stream()
+    setup_s = time.perf_counter() - t0
+    kw = dict(event_geom=eg)
+    best = ctx.autotune(gids[0], prim_d, tally, trials=2, stream=stream, **kw)
+    ms_e, res, _ = time_batches(ctx, gid=gids[0], prim_d=prim_d, tally=tally, stream=stream, reps=reps,
+                                tuned=True, **kw)
+    g = ctx.graph_create(gids[0], prim_d, tally, stream=stream, tuned=True, **kw)
+    ms_g = []
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tally.reset(stream)
+        a.record(stream)
+        ctx.graph_launch(g, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_g.append(a.elapsed_time(b))
+    gr = tally.read(stream)
+    ctx.graph_free(g)
+    tally.free()
+    steps = res["counters"]["steps"]
+    same = gr["counters"] == res["counters"]
+    return {"workload": f"batched: {prim.n_events} events, {prim.n} photons (lognormal sizes, median "
+                        "2000, 10-50000) over 8 resident geometries (tiny, calorimeter, barrel, 5 barrel "
+                        "variants), log-uniform 0.05-20 MeV",
+            "photons": int(prim.n), "steps": steps, "tuned": best,
+            "ms_eager_tuned": ms_e, "ms_graph_tuned": float(np.median(ms_g[1:])),
+            "steps_per_s": steps / float(np.median(ms_g[1:])) * 1e3,
+            "graph_same_counters": bool(same), "setup_s": setup_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +270,7 @@ def main():
                     help="photons of the barrel variant comparison (0: skip)")
     ap.add_argument("--train-photons", type=int, default=1_000_000,
                     help="photons whose crossings train the learned order (0: skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-events config")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -352,6 +394,9 @@ def main():
     if args.barrel_n > 0:
         out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
         print("barrel variants done", file=sys.stderr, flush=True)
+    if not args.no_batched:
+        out["batched"] = batched_config(ctx, gnav, 3)
+        print("batched config done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
 

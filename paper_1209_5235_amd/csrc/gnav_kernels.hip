@@ -4,11 +4,13 @@
 // Transport follows Sec. 3.1: each photon draws an Exp(1) optical depth
 // (Alg. 1, steps 1-2), spends it boundary to boundary (S_j update, Eq. 6)
 // and interacts where it runs out (T = t_{j-1} + (Y - S_{j-1}) / mu_j,
-// Eq. 7); after a Compton scatter a new depth is drawn.  One lane holds one
-// track in registers; when a lane's track ends the wave refills its idle
-// lanes together from a device work queue with one atomic per wave
-// (ballot + prefix count), so no lane waits for the slowest track of its
-// original batch (the load-balancing idea of Sec. 5, done in registers).
+// Eq. 7); after a Compton scatter a new depth is drawn.  Each block keeps a
+// pool of tracks in LDS and runs rounds of phases (refill, navigate, step,
+// interact); before each phase the slots that need it are compacted into a
+// dense work list so the lanes of a wave follow one code path (the
+// divergence Sec. 5 names, handled by compaction in LDS rather than by a
+// separate compaction pass).  Idle slots refill from a device work queue
+// and from a block stack of annihilation photons.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
