@@ -208,6 +208,29 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
         out["fp64_learned_order"] = e
         ctx.set_mlp(gid, None)
         net.free()
+        # the same comparison with bounding-box voxel node lists (as Geant4's smart
+        # voxels), where start nodes hold many more candidates
+        gid_b, _ = ctx.upload_geometry(geoms[0], voxel_lists=1)
+        tally_b = ctx.tally_create(prim.n_events)
+        ms_p, res_p, w_p = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps)
+        rec = learned.record_crossings(ctx, gid_b, gnav.primaries_to_device(tprim, "cuda"),
+                                       tprim.n_events, capacity=8_000_000, seed=1)
+        x, cls, label = learned.records_to_tensors(rec)
+        net, _ = learned.train(ctx, ctx.ordering_classes(gid_b), x, cls, label, epochs=2, batch=4096)
+        ctx.set_mlp(gid_b, net)
+        ms_l, res_l, w_l = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, order=2)
+        ms_bo, res_bo, w_bo = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, order=1)
+        same = all(res_l["counters"][k] == res_p["counters"][k]
+                   for k in ("steps", "pe", "compton", "pair", "crossings", "escaped", "tracks"))
+        out["bbox_voxel_lists"] = {
+            "fp64_ms": ms_p, "fp64_steps_per_s": res_p["counters"]["steps"] / ms_p * 1e3,
+            "dist_in_fp64": w_p["dist_in"], "learned_ms": ms_l, "learned_speedup": ms_p / ms_l,
+            "learned_dist_in_fp64": w_l["dist_in"], "learned_same_counters": bool(same),
+            "bound_order_ms": ms_bo, "bound_order_speedup": ms_p / ms_bo,
+            "training_crossings": int(x.shape[0])}
+        ctx.set_mlp(gid_b, None)
+        net.free()
+        tally_b.free()
     tally.free()
     return out
 

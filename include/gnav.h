@@ -129,6 +129,10 @@ typedef struct {
   const double* pv_rot;      /* [n_pv][9] row-major R, x_mother = R x_local + t */
   const double* pv_trans;    /* [n_pv][3] t */
   int32_t world_lv;          /* the unplaced top volume (its frame is the global frame) */
+  int32_t voxel_lists;        /* 0: a voxel node lists the daughters whose solid may meet it
+                                 (shape-aware, with a finer-grid search for nested shells);
+                                 1: the daughters whose bounding box meets it, on the
+                                 bounding-box grid search only (as Geant4's smart voxels) */
 } gnav_geometry_desc;
 
 /* Create a context on HIP device `device`. */

@@ -728,8 +728,37 @@ __device__ __forceinline__ double daughter_lower_bound(const DevGeom& G, int pv,
   return dmax(te, saf);
 }
 
-// Candidate orders for the start node of a step walk.
+// True when the ray (pl, vl) certainly meets placement P's bounding box
+// beyond distance s or not at all (parallel outside a slab, or the box behind
+// it on an axis): the bounding-box half of daughter_lower_bound(...)
+// (1 - 1e-12) - kTol > s, written with products instead of quotients.  A ray
+// that misses the box obliquely is not caught (the caller then evaluates the
+// candidate exactly).
+__device__ __forceinline__ bool box_beyond(const PRec& P, V3 pl, V3 vl, double s) {
+  const double pc[3] = {pl.x, pl.y, pl.z};
+  const double vc[3] = {vl.x, vl.y, vl.z};
+  const double reach = s + kTol;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const double lo = P.box_lo[a], hi = P.box_hi[a];
+    if (vc[a] > 0.0) {
+      if (hi < pc[a]) return true;
+      if ((lo - pc[a]) * (1.0 - 1e-12) > reach * vc[a]) return true;
+    } else if (vc[a] < 0.0) {
+      if (lo > pc[a]) return true;
+      if ((pc[a] - hi) * (1.0 - 1e-12) > reach * -vc[a]) return true;
+    } else if (pc[a] < lo || pc[a] > hi) {
+      return true;
+    }
+  }
+  return false;
+}
+
+// Candidate orders for the start node of a step walk.  Nodes with fewer
+// candidates than kOrderMinCand are walked in slot order (with two, an
+// ordering pass costs more than it can save).
 enum : int { kOrderPlain = 0, kOrderBound = 1, kOrderLearned = 2 };
+constexpr int kOrderMinCand = 3;
 
 // ComputeStep in the mother frame (pl, vl) of a touchable with LV record L:
 // the mother's exit distance against daughter entry distances, collected by
@@ -792,7 +821,7 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
     int2 nd = G.vox_node[L.node_base + (idx[0] * L.n[1] + idx[1]) * L.n[2] + idx[2]];
     nc.node();
     if (first && start_node) *start_node = nd;
-    if (ORDER != kOrderPlain && first && nd.y >= 2) {
+    if (ORDER != kOrderPlain && first && nd.y >= kOrderMinCand) {
       int lead = -1;
       if (ORDER == kOrderLearned && pred >= 0 && pred < nd.y) lead = pred;
       if (lead < 0) {
@@ -820,10 +849,10 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
       for (int c = 0; c < nd.y; c++) {
         if (c == lead) continue;
         int k = G.vox_cand[nd.x + c];
-        double sf;
-        double lb = daughter_lower_bound(G, base + k, pl, vl, sf);
+        const double sf = daughter_safety_in(G, base + k, pl);
         saf = dmin(saf, sf);
-        if (lb * (1.0 - 1e-12) - kTol > s) continue;
+        // skip when the candidate's safety or its bounding box lies beyond the best
+        if (sf * (1.0 - 1e-12) > s + kTol || box_beyond(G.pv[base + k], pl, vl, s)) continue;
         double t = daughter_dist_in(G, base + k, pl, vl);
         nc.in();
         if (t < s || (t == s && lim >= 0 && k < lim)) {
@@ -1010,6 +1039,18 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
           float d = solid_d<float>(P.info, P.par, pd);
           saf = dmin(saf, d > 0.f ? (double)d : 0.0);
         }
+        if (t < s || (t == s && lim >= 0 && k < lim)) {
+          s = t;
+          lim = k;
+        }
+      }
+    } else if (nd.y < kOrderMinCand) {
+      // too few candidates to gain from screening: FP64 as in compute_step
+      for (int c = 0; c < nd.y; c++) {
+        const int k = slot(c);
+        double t = daughter_dist_in(G, base + k, pl, vl);
+        nc.in();
+        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl));
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;

@@ -428,7 +428,7 @@ double shape_cost(const Box3& g, const int* n, const std::vector<DauShape>& dau,
   return sum / samples;
 }
 
-VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau) {
+VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau, bool shape_aware) {
   const int cnt = (int)dau.size();
   Box3 g = mother;
   for (const DauShape& d : dau) {
@@ -499,7 +499,7 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau) {
   // Daughters whose bounding boxes overlap heavily (nested shells, sections
   // around an axis) leave many candidates per node: then search again with
   // shape-aware counts over power-of-two grids, allowing finer grids.
-  if (best_cand > 4.0) {
+  if (shape_aware && best_cand > 4.0) {
     double cur = shape_cost(g, bn, dau, pad) + 0.02 * (bn[0] + bn[1] + bn[2]);
     const long max_fine = std::max<long>(max_nodes, std::min<long>(1 << 16, 64L * cnt));
     const int ladder[] = {1, 2, 4, 8, 16, 32, 64, 128};
@@ -537,7 +537,7 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau) {
     for (int i = l[0]; i <= h[0]; i++)
       for (int j = l[1]; j <= h[1]; j++)
         for (int k = l[2]; k <= h[2]; k++)
-          if (shape_meets_box(dau[d], node_box(vb.lo, vb.w, i, j, k, pad), pad))
+          if (!shape_aware || shape_meets_box(dau[d], node_box(vb.lo, vb.w, i, j, k, pad), pad))
             vb.nodes[((size_t)i * ny + j) * nz + k].push_back((uint16_t)d);
   }
   return vb;
@@ -714,6 +714,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
                                                                           !d->pv_trans)))
     return fail(c, GNAV_EINVAL, "null array in geometry description");
   if (d->world_lv < 0 || d->world_lv >= d->n_lv) return fail(c, GNAV_EGEOM, "bad world LV");
+  if (d->voxel_lists != 0 && d->voxel_lists != 1) return fail(c, GNAV_EINVAL, "voxel_lists must be 0 or 1");
   // solids
   std::vector<double> q(d->n_solids * kSolidStride);
   std::vector<int> info(d->n_solids);
@@ -877,7 +878,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
         for (int i = 0; i < 3; i++) sh.t[i] = d->pv_trans[3 * p + i];
         db.push_back(sh);
       }
-      VoxBuild vb = build_voxels(ext[d->lv_solid[l]], db);
+      VoxBuild vb = build_voxels(ext[d->lv_solid[l]], db, d->voxel_lists == 0);
       lr.vox = 1;
       lr.lclass = gr.n_class++;
       lr.node_base = (int)c->vox_node.size();

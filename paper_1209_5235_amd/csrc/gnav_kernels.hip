@@ -207,10 +207,13 @@ struct TransportArgs {
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-// Optional occupancy target for the transport kernel (waves per SIMD), set at
-// build time; 0 leaves register allocation to the compiler.
+// Occupancy target for the transport kernel (waves per SIMD, settable at
+// build time; 0 leaves register allocation to the compiler).  Two waves per
+// SIMD (two 256-slot blocks per compute unit) caps a wave at 256 registers,
+// VGPRs and AGPRs together, which the learned-order instantiation would
+// otherwise exceed.
 #ifndef GNAV_TRANSPORT_WAVES
-#define GNAV_TRANSPORT_WAVES 0
+#define GNAV_TRANSPORT_WAVES 2
 #endif
 #if GNAV_TRANSPORT_WAVES > 0
 #define GNAV_TRANSPORT_ATTR __attribute__((amdgpu_waves_per_eu(GNAV_TRANSPORT_WAVES)))
@@ -363,20 +366,33 @@ __device__ __forceinline__ uint16_t lf2bf(float f) {
 __device__ __forceinline__ float lbf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 struct LearnScratch {
-  uint16_t h[kWaves][16][128];  // activations (bf16) / logits as float [16][64]
+  uint16_t h[kWaves][16][128];  // per wave: activations (bf16), then the logits as float [16][64]
   int cls[kWaves][16];
 };
 
-__device__ __forceinline__ void learned_predict(const TransportArgs& a, Pool& P, LearnScratch& S, int n) {
+// Four consecutive bf16 values as one MFMA operand (8-byte aligned loads).
+__device__ __forceinline__ lbf16x4 load_bf16x4(const uint16_t* p) {
+  return *reinterpret_cast<const lbf16x4*>(p);
+}
+
+// The block's waves score the n listed steps, 16 per MFMA row tile (wave w
+// takes tiles w, w + 4, ...): layer 1 is [16 x 16(6)] x [16 x 128] plus the
+// mother-class row of W1, layers 2 and 3 are [16 x 128] x [128 x 128] and
+// x [128 x 64].  Each 16 x 16 output tile is accumulated over K in FP32 and
+// written back at once; a layer's input row is read into registers before
+// any output is written, so one LDS buffer per wave serves every layer.
+// MFMA operand layout (16x16x16 bf16): lane l holds A row l % 16 and B
+// column l % 16 at k = 4 (l / 16) + 0..3; the result holds column l % 16,
+// rows 4 (l / 16) + 0..3.
+__device__ __attribute__((noinline)) void learned_predict(const TransportArgs& a, Pool& P, LearnScratch& S,
+                                                          int n) {
   const DevGeom& G = a.G;
   const MlpView& M = a.mlp;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
   uint16_t (*h)[128] = S.h[w];
   float (*lg)[64] = reinterpret_cast<float (*)[64]>(&S.h[w][0][0]);
-  for (int mt = 0; mt < 4; mt++) {
-    const int row0 = w * 64 + mt * 16;
-    if (row0 >= n) break;
+  for (int row0 = 16 * w; row0 < n; row0 += 16 * kWaves) {
     // features of row r: point in the mother frame over the grid half size, direction
     const int li = row0 + r;
     const bool valid = li < n;
@@ -409,7 +425,7 @@ __device__ __forceinline__ void learned_predict(const TransportArgs& a, Pool& P,
       xa[j] = (short)(k < 6 ? lf2bf(f[k]) : 0);
     }
     __builtin_amdgcn_wave_barrier();
-    // layer 1: [16 x 16] x [16 x 128] (K padded from 6), + b1 + W1m[cls], ReLU
+    // layer 1 (K padded from 6 to 16) + b1 + W1m[class], ReLU
     for (int ct = 0; ct < 8; ct++) {
       const int nn = 16 * ct + r;
       lbf16x4 wb;
@@ -428,55 +444,41 @@ __device__ __forceinline__ void learned_predict(const TransportArgs& a, Pool& P,
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // layer 2: [16 x 128] x [128 x 128], + b2, ReLU (result kept in registers, then stored)
-    lf32x4 acc2[8];
-    for (int ct = 0; ct < 8; ct++) {
-      const int nn = 16 * ct + r;
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int kt = 0; kt < 8; kt++) {
-        const int k0 = 16 * kt + 4 * q;
-        lbf16x4 av, bv;
+    // layer 2 + b2, ReLU (written over the input rows)
+    // (the row's A operands stay in registers across the output tiles; each
+    // tile's eight B operands are loaded together before its MFMA chain)
+    lbf16x4 a1[8];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          av[j] = (short)h[r][k0 + j];
-          bv[j] = (short)M.w2[nn * 128 + k0 + j];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-      }
-      acc2[ct] = acc;
-    }
-    __builtin_amdgcn_wave_barrier();
+    for (int kt = 0; kt < 8; kt++) a1[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
     for (int ct = 0; ct < 8; ct++) {
       const int nn = 16 * ct + r;
+      lbf16x4 b[8];
+#pragma unroll
+      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w2 + nn * 128 + 16 * kt + 4 * q);
+      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[kt], b[kt], acc, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; j++) {
-        float v = acc2[ct][j] + M.b2[nn];
+        float v = acc[j] + M.b2[nn];
         h[4 * q + j][nn] = lf2bf(v > 0.f ? v : 0.f);
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // layer 3: [16 x 128] x [128 x 64], + b3 -> logits
-    lf32x4 acc3[4];
+    // layer 3 + b3 -> logits (float, over the same buffer)
+    lbf16x4 a2[8];
+#pragma unroll
+    for (int kt = 0; kt < 8; kt++) a2[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
     for (int ct = 0; ct < 4; ct++) {
       const int nn = 16 * ct + r;
+      lbf16x4 b[8];
+#pragma unroll
+      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w3 + nn * 128 + 16 * kt + 4 * q);
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int kt = 0; kt < 8; kt++) {
-        const int k0 = 16 * kt + 4 * q;
-        lbf16x4 av, bv;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          av[j] = (short)h[r][k0 + j];
-          bv[j] = (short)M.w3[nn * 128 + k0 + j];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-      }
-      acc3[ct] = acc;
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int ct = 0; ct < 4; ct++) {
-      const int nn = 16 * ct + r;
+      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], b[kt], acc, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; j++) lg[4 * q + j][nn] = acc3[ct][j] + M.b3[nn];
+      for (int j = 0; j < 4; j++) lg[4 * q + j][nn] = acc[j] + M.b3[nn];
     }
     __builtin_amdgcn_wave_barrier();
     if (q == 0 && valid) {
@@ -733,13 +735,27 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     }
 
     // ---- learned order: score the steps whose mother has a voxel grid -------
+    // (only steps whose start voxel node holds enough candidates for an order
+    // to pay)
     if constexpr (ORDER == kOrderLearned) {
       __shared__ LearnScratch S;
       bool elig = false;
-      if (P.status[tid] == kStep) elig = G.lv[P.lvk[tid] >> 1].lclass >= 0;
+      if (P.status[tid] == kStep) {
+        const int lvk = P.lvk[tid];
+        const LRec& L = G.lv[lvk >> 1];
+        if (L.lclass >= 0) {
+          V3 x{P.x[tid], P.y[tid], P.z[tid]}, v{P.vx[tid], P.vy[tid], P.vz[tid]};
+          V3 pl, vl;
+          touchable_frame(G, P.T[tid], lvk & 1, x, v, pl, vl);
+          const int ix = vox_axis_index(pl.x, L.vlo[0], L.vinv[0], L.n[0]);
+          const int iy = vox_axis_index(pl.y, L.vlo[1], L.vinv[1], L.n[1]);
+          const int iz = vox_axis_index(pl.z, L.vlo[2], L.vinv[2], L.n[2]);
+          elig = G.vox_node[L.node_base + (ix * L.n[1] + iy) * L.n[2] + iz].y >= kOrderMinCand;
+        }
+      }
       P.pred[tid] = -1;
       int n = compact<1>(P, elig, 0);
-      learned_predict(a, P, S, n);
+      if (n > 0) learned_predict(a, P, S, n);
       __syncthreads();
     }
 

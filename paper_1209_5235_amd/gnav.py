@@ -44,7 +44,7 @@ class gnav_geometry_desc(C.Structure):
         ("n_lv", C.c_int32), ("lv_solid", _i32p), ("lv_mat", _i32p), ("lv_dau_off", _i32p),
         ("lv_dau_cnt", _i32p), ("lv_voxelize", _u8p),
         ("n_pv", C.c_int32), ("pv_lv", _i32p), ("pv_rot", _f64p), ("pv_trans", _f64p),
-        ("world_lv", C.c_int32),
+        ("world_lv", C.c_int32), ("voxel_lists", C.c_int32),
     ]
 
 
@@ -194,8 +194,9 @@ class Context:
             msg = gnav_last_error(self.h).decode(errors="replace")
             raise GnavError(f"{what}: {STATUS.get(st, st)}: {msg}")
 
-    def upload_geometry(self, desc):
-        """Upload a workloads.GeometryDesc; returns (geom_id, n_touchables)."""
+    def upload_geometry(self, desc, voxel_lists=0):
+        """Upload a workloads.GeometryDesc; returns (geom_id, n_touchables).  voxel_lists 0:
+        shape-aware node lists, 1: bounding-box lists (gnav_geometry_desc.voxel_lists)."""
         arrs = dict(
             solid_type=_np(desc.solid_type, np.int32), solid_par=_np(desc.solid_par, np.float64),
             mat_density=_np(desc.mat_density, np.float64), mat_el_off=_np(desc.mat_el_off, np.int32),
@@ -218,7 +219,7 @@ class Context:
             desc.n_lv, p("lv_solid", C.c_int32), p("lv_mat", C.c_int32),
             p("lv_dau_off", C.c_int32), p("lv_dau_cnt", C.c_int32), p("lv_voxelize", C.c_uint8),
             desc.n_pv, p("pv_lv", C.c_int32), p("pv_rot", C.c_double), p("pv_trans", C.c_double),
-            int(desc.world_lv))
+            int(desc.world_lv), int(voxel_lists))
         gid = C.c_int32()
         nt = C.c_int32()
         self._check(gnav_upload_geometry(self.h, C.byref(d), C.byref(gid), C.byref(nt)),

@@ -73,7 +73,9 @@ def test_screened_transport_matches_oracle(ctx, torch_dev, oracle_lib, name, n, 
         assert got["counters"][k] == ref["counters"][k], k
     assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
     assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
-    if desc.n_pv:
+    # nodes with fewer than three candidates are walked in FP64 (the calorimeter's
+    # start nodes hold one or two), the others are screened in FP32
+    if name != "calorimeter":
         assert got["counters"]["dist_in_f32"] > 0
 
 
