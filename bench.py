@@ -235,6 +235,51 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
     return out
 
 
+# The paper's Table 1 (Spheres, N = 1e5, free path only), milliseconds, as context.
+PAPER_TABLE1_MS = {"regular": {"gtx470": 33, "cpu_1_thread": 442, "cpu_12_threads": 54},
+                   "random": {"gtx470": 114, "cpu_1_thread": 458, "cpu_12_threads": 56}}
+
+
+def paper_free_path(ctx, gnav, reps, oracle_sample):
+    """Alg. 1 free path alone on the paper's Spheres geometry with its Random and
+    Regular particle sets (mu = rho x 0.06146 cm2/g, Eq. 9), N = 1e5."""
+    import torch
+    import workloads as W
+    desc = W.geometry.spheres()
+    gid, _ = ctx.upload_geometry(desc)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "Spheres: 8000 Al orbs r = 100 mm on a 20^3 grid in a 5 m vacuum cube, "
+                       "particles from the centre, mu = rho x 0.06146 cm2/g, N = 1e5, FP64"}
+    for name, (pos, dirs, life) in (("random", W.primaries.paper_random(100_000, seed=0)),
+                                    ("regular", W.primaries.paper_regular())):
+        p, d, y = (torch.from_numpy(a).cuda() for a in (pos, dirs, life))
+        ctx.free_path(gid, p, d, y, mu_mass=0.06146, stream=stream)
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            t, nb = ctx.free_path(gid, p, d, y, mu_mass=0.06146, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        m = float(np.median(ms))
+        e = {"gpu_ms": m, "particles_per_s": len(life) / m * 1e3,
+             "boundaries_per_particle": float(nb.double().mean().cpu()),
+             "paper_ms_context": PAPER_TABLE1_MS[name]}
+        if oracle_sample > 0:
+            import oracle
+            og = oracle.Geometry(desc)
+            og.set_paper_mode(True, 0.06146)
+            t0 = time.perf_counter()
+            for i in range(oracle_sample):
+                og.free_path(pos[i], dirs[i], 1.0, float(life[i]))
+            dt = time.perf_counter() - t0
+            e["oracle_particles_per_s"] = oracle_sample / dt
+            e["oracle_sample"] = f"first {oracle_sample} particles, one thread, brute-force navigation"
+        out[name] = e
+    return out
+
+
 def batched_config(ctx, gnav, reps):
     """Uneven events over eight resident geometries in one launch: autotuned
     launch settings, then the tuned launch captured in a HIP graph."""
@@ -417,6 +462,8 @@ def main():
     if args.barrel_n > 0:
         out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
         print("barrel variants done", file=sys.stderr, flush=True)
+    out["paper_free_path"] = paper_free_path(ctx, gnav, 5, 0 if args.no_cpu else 3000)
+    print("paper free-path config done", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_config(ctx, gnav, 3)
         print("batched config done", file=sys.stderr, flush=True)

@@ -209,6 +209,20 @@ gnav_status gnav_compute_step_prec(gnav_ctx* ctx, int32_t geom_id, int64_t n, co
 gnav_status gnav_compute_safety(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
                                 const int32_t* touchable_dev, double* safety_dev, void* stream);
 
+/* Free path of Alg. 1 alone, the paper's timed phase (Alg. 2 phase 5, the
+ * measurements of Table 1): for each particle i, starting at pos_dev[i] along
+ * dir_dev[i] with lifetime life_dev[i] (an optical depth, Y in Alg. 1), cross
+ * boundaries accumulating S_j = sum mu s (Eq. 6) and return the first
+ * interaction distance T = t_{j-1} + (Y - S_{j-1}) / mu_j (Eq. 7) in
+ * t_dev[i] (mm; +inf when the particle leaves the world) and the boundaries
+ * crossed in n_bounds_dev[i] (may be NULL).  mu_mass > 0 selects the paper's
+ * attenuation mu = rho mu_mass (Eq. 9, mu_mass in cm2/g, e.g. 0.06146 for
+ * aluminium at 1 MeV); mu_mass = 0 uses the tabulated total attenuation at
+ * `energy` (MeV).  Device arrays of n entries (pos/dir [n][3]). */
+gnav_status gnav_free_path(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                           const double* dir_dev, const double* life_dev, double energy, double mu_mass,
+                           double* t_dev, int32_t* n_bounds_dev, void* stream);
+
 /* Device energy tallies, sized to every touchable resident at creation and to
  * n_events events.  Created zeroed. */
 gnav_status gnav_tally_create(gnav_ctx* ctx, int32_t n_events, gnav_tally** out);

@@ -113,6 +113,7 @@ struct DevGeom {
   const int2* vox_node;     // {candidate offset, count}
   const uint16_t* vox_cand; // daughter slots, ascending within a node
   const double* xs;         // [mat][3][257] attenuation, 1/mm
+  const double* mat_rho;    // [mat] density, g/cm3
   const PRecF* pvf;         // [PV] FP32 twins of the placements
   const float* lv_parf;     // [LV][12] FP32 twins of the LV solid parameters
   double lnE0, dlnE;

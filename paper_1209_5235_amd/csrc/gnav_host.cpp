@@ -571,12 +571,14 @@ struct gnav_ctx {
   std::vector<int2> vox_node;
   std::vector<uint16_t> vox_cand;
   std::vector<double> xs;
+  std::vector<double> mat_rho;
   std::vector<GeomRec> geoms;
   std::vector<int> geom_tbase;
   int n_mats_total = 0;
   double lnE0 = 0, dlnE = 0;
   // device copies
-  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_lv_parf, d_vox_node, d_vox_cand, d_xs, d_geom_tbase;
+  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_lv_parf, d_vox_node, d_vox_cand, d_xs, d_mat_rho,
+      d_geom_tbase;
   DevBuf d_queue, d_pend;
   DevGeom G{};
   // autotuned launch settings by (geometry, precision, order, log2 of the batch size)
@@ -620,6 +622,7 @@ hipError_t upload_all(gnav_ctx* c) {
   UP(d_vox_node, vox_node)
   UP(d_vox_cand, vox_cand)
   UP(d_xs, xs)
+  UP(d_mat_rho, mat_rho)
   UP(d_geom_tbase, geom_tbase)
 #undef UP
   DevGeom& G = c->G;
@@ -632,6 +635,7 @@ hipError_t upload_all(gnav_ctx* c) {
   G.vox_node = c->d_vox_node.as<int2>();
   G.vox_cand = c->d_vox_cand.as<uint16_t>();
   G.xs = c->d_xs.as<double>();
+  G.mat_rho = c->d_mat_rho.as<double>();
   G.lnE0 = c->lnE0;
   G.dlnE = c->dlnE;
   return hipSuccess;
@@ -821,6 +825,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       }
     }
   }
+  for (int m = 0; m < d->n_mats; m++) c->mat_rho.push_back(d->mat_density[m]);
   c->n_mats_total += d->n_mats;
   // placements: M = R^T (row major, M[i][j] = R[j][i]) and t
   for (int p = 0; p < d->n_pv; p++) {
@@ -1069,6 +1074,20 @@ gnav_status gnav_compute_step_prec(gnav_ctx* c, int32_t geom_id, int64_t n, cons
   HIP_TRY(c, launch_step(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, dir, touch, step, lim, next, safety,
                          precision, (hipStream_t)stream),
           "step launch");
+  return GNAV_OK;
+}
+
+gnav_status gnav_free_path(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
+                           const double* life, double energy, double mu_mass, double* t_out, int32_t* nb_out,
+                           void* stream) {
+  gnav_status s = check_geom(c, geom_id);
+  if (s) return s;
+  if (n < 0 || (n > 0 && (!pos || !dir || !life || !t_out))) return fail(c, GNAV_EINVAL, "bad free-path arguments");
+  if (!(mu_mass >= 0) || !std::isfinite(mu_mass)) return fail(c, GNAV_EINVAL, "bad mass attenuation");
+  if (mu_mass == 0 && !(energy > 0 && std::isfinite(energy))) return fail(c, GNAV_EINVAL, "bad energy");
+  int tb = c->geoms[geom_id].t_base;
+  HIP_TRY(c, launch_free_path(c->G, tb, n, pos, dir, life, energy, mu_mass, t_out, nb_out, (hipStream_t)stream),
+          "free-path launch");
   return GNAV_OK;
 }
 

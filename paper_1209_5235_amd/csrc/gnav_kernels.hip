@@ -170,6 +170,59 @@ __device__ __forceinline__ void rotate_dir(V3& v, double cost, double sint, doub
   v = V3{nx / nn, ny / nn, nz / nn};
 }
 
+// Free path of Alg. 1 alone (the paper's timed phase, Alg. 2 phase 5): from
+// the start point, cross boundaries accumulating the optical depth S_j = sum
+// mu_i s_i (Eq. 6) until it reaches the particle's lifetime Y; the first
+// interaction lies at T = t_{j-1} + (Y - S_{j-1}) / mu_j (Eq. 7).  mu is the
+// paper's rho mu_Al (Eq. 9) when mu_mass > 0, else the tabulated total
+// attenuation at energy E.  T = +inf when the particle leaves the world.
+__global__ void __launch_bounds__(256) k_free_path(DevGeom G, int W, long n, const double* pos, const double* dir,
+                                                   const double* life, double E, double mu_mass, double* t_out,
+                                                   int* nb_out) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  NavCount<false> nc;
+  V3 x{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  V3 v{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+  const double Y = life[i];
+  int T = locate(G, W, x, true, v, nc);
+  double t_prev = 0.0, S_prev = 0.0, result = kInf;
+  int nb = 0;
+  int imu = 0;
+  double wmu = 0.0;
+  if (mu_mass <= 0.0) mu_index(G, E, imu, wmu);
+  while (T >= 0) {
+    const TRec tr = G.t[T];
+    const LRec& L = G.lv[tr.lv];
+    double mu;
+    if (mu_mass > 0.0) {
+      mu = G.mat_rho[L.mat] * mu_mass * 0.1;
+    } else {
+      double pe, co, pp;
+      mu_parts(G, L.mat, imu, wmu, E, pe, co, pp);
+      mu = pe + co + pp;
+    }
+    V3 pl, vl;
+    touchable_frame(G, T, trec_kind(tr), x, v, pl, vl);
+    int lim;
+    double saf;
+    const double s = compute_step(G, L, pl, vl, lim, saf, nc);
+    const double S = mu > 0 ? S_prev + s * mu : S_prev;
+    if (mu > 0 && S >= Y) {
+      result = t_prev + (Y - S_prev) / mu;
+      break;
+    }
+    x = V3{x.x + s * v.x, x.y + s * v.y, x.z + s * v.z};
+    t_prev = t_prev + s;
+    S_prev = S;
+    T = relocate(G, T, tr, x, v, lim, nc);
+    nb++;
+    if (nb > 1000000) break;
+  }
+  t_out[i] = result;
+  if (nb_out) nb_out[i] = nb;
+}
+
 struct TransportArgs {
   DevGeom G;
   long n;
@@ -1058,6 +1111,15 @@ hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_safety, dim3(grid_for(n, 256)), dim3(256), 0, st, G, W, tbase, tcount, n, pos, touch,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, const double* dir,
+                            const double* life, double E, double mu_mass, double* t_out, int* nb_out,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_free_path, dim3(grid_for(n, 256)), dim3(256), 0, st, G, W, n, pos, dir, life, E, mu_mass,
+                     t_out, nb_out);
   return hipGetLastError();
 }
 

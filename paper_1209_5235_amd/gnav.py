@@ -85,6 +85,8 @@ def _load():
         "gnav_compute_step_prec": ([P, C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P, P, P, P],
                                    C.c_int32),
         "gnav_compute_safety": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_free_path": ([P, C.c_int32, C.c_int64, P, P, P, C.c_double, C.c_double, P, P, P],
+                           C.c_int32),
         "gnav_tally_create": ([P, C.c_int32, C.POINTER(P)], C.c_int32),
         "gnav_tally_reset": ([P, P, P], C.c_int32),
         "gnav_tally_free": ([P, P], C.c_int32),
@@ -125,6 +127,7 @@ gnav_locate = lib.gnav_locate
 gnav_compute_step = lib.gnav_compute_step
 gnav_compute_step_prec = lib.gnav_compute_step_prec
 gnav_compute_safety = lib.gnav_compute_safety
+gnav_free_path = lib.gnav_free_path
 gnav_tally_create = lib.gnav_tally_create
 gnav_tally_reset = lib.gnav_tally_reset
 gnav_tally_free = lib.gnav_tally_free
@@ -271,6 +274,16 @@ class Context:
         if with_safety:
             return step, lim, nxt, saf
         return step, lim, nxt
+
+    def free_path(self, geom_id, pos, dirs, life, energy=1.0, mu_mass=0.0, stream=None):
+        """gnav_free_path: first interaction distances T and boundaries crossed."""
+        import torch
+        n = pos.shape[0]
+        t = torch.empty(n, dtype=torch.float64, device=pos.device)
+        nb = torch.empty(n, dtype=torch.int32, device=pos.device)
+        self._check(gnav_free_path(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(life), float(energy),
+                                   float(mu_mass), _ptr(t), _ptr(nb), _stream(stream)), "gnav_free_path")
+        return t, nb
 
     def compute_safety(self, geom_id, pos, touch=None, stream=None):
         import torch

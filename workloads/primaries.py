@@ -135,3 +135,30 @@ def source_beam(rng, n, z0=-999.0, sigma=10.0):
 def source_axis_iso(rng, n, half_z=2000.0):
     z = rng.uniform(-half_z, half_z, size=n)
     return np.column_stack([np.zeros(n), np.zeros(n), z]), isotropic(rng, n)
+
+
+# ---------------------------------------------------------------------------
+# The paper's particle sets for the free-path benchmark (Sec. 3.5): every
+# particle starts at the centre of the geometry.
+# ---------------------------------------------------------------------------
+
+def paper_random(n=100_000, seed=0):
+    """Random set: isotropic directions, Exp(1) lifetimes; (pos, dir, life)."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    d = isotropic(rng, n)
+    u = 1.0 - rng.uniform(size=n)  # (0, 1]
+    return np.zeros((n, 3)), d, -np.log(u)
+
+
+def paper_regular(nx=400, ny=250, half_w=1.0):
+    """Regular set: rays from the centre through the pixel centres of an
+    nx x ny grid on the plane z = 1 (x in [-half_w, half_w], square pixels),
+    listed column by column (column-major), all with lifetime 1."""
+    px = 2.0 * half_w / nx
+    col = np.repeat(np.arange(nx), ny)
+    row = np.tile(np.arange(ny), nx)
+    x = -half_w + (col + 0.5) * px
+    y = -0.5 * ny * px + (row + 0.5) * px
+    d = np.column_stack([x, y, np.ones(nx * ny)])
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return np.zeros((nx * ny, 3)), d, np.ones(nx * ny)
