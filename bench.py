@@ -87,21 +87,21 @@ def kernel_source_hash():
     """Hash of the transport kernel sources (ties stored counter readings to a build)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("gnav_kernels.hip", "gnav_device.h", "gnav_internal.h"):
+    for f in ("gnav_transport.hip", "gnav_physics.h", "gnav_device.h", "gnav_internal.h"):
         with open(os.path.join(ROOT, "paper_1209_5235_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(kernel):
     """HBM bytes per launch of the headline kernel from the committed counter
-    summary, or None when it was taken from other kernel sources."""
+    summary, or None when it was taken for another kernel or other sources."""
     path = os.path.join(ROOT, "profiles", "k_transport_calorimeter_1e6_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
@@ -408,7 +408,8 @@ def main():
 
     flops = algorithmic_flops(c)
     achieved_tf = flops / avg_kern_s / 1e12
-    traffic = stored_traffic()
+    kernel = f"gnav::pool{args.block or 128}::k_transport<false, false, 0, 0>"
+    traffic = stored_traffic(kernel)
     out = {
         "metric": "gamma navigation steps/s on 1 GPU",
         "value": value,
@@ -428,7 +429,7 @@ def main():
                         "0.1-10 MeV, Gaussian beam sigma 10 mm, FP64, Philox seed 0",
             "photons_per_batch": prim.n,
             "nav_steps_per_batch": steps_per_batch,
-            "block": args.block or 256,
+            "block": args.block or 128,
             "grid": args.grid or "default",
         },
         "roofline": {
@@ -438,7 +439,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP64_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_transport<false, false, 0, 0>",
+            "kernel": kernel,
             "kernel_ms": avg_kern_s * 1e3,
             "flops_per_launch": flops,
             "kernel_source_hash": kernel_source_hash(),

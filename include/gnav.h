@@ -256,7 +256,7 @@ typedef struct {
   double e_cut;               /* MeV: photons below it deposit locally and stop */
   int64_t max_steps_per_track;/* <= 0: 1e6 */
   int32_t precision;          /* GNAV_PREC_*; FP32 forms need order 0 and no recorder */
-  int32_t block;              /* threads per block (multiple of 64, <= 256), 0 = default */
+  int32_t block;              /* track-pool slots (= threads) per block: 64, 128 or 256; 0 = 128 */
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
   int32_t count_work;         /* 1: also count navigation work (GNAV_C_DIST_IN..VOXEL_NODES) */
   int32_t order;              /* start-node candidate order: 0 slot order, 1 smallest lower bound
@@ -272,7 +272,7 @@ typedef struct {
                                  wave claims exactly what its idle lanes need (one atomic) */
   int32_t sort_period;        /* every sort_period-th round the step phase groups tracks by their
                                  current logical volume instead of solid family; 0: never */
-  int32_t tuned;              /* 1: take grid, chunk and sort_period from gnav_autotune's cache
+  int32_t tuned;              /* 1: take block, grid, chunk and sort_period from gnav_autotune's cache
                                  for this geometry, precision and order when present */
 } gnav_batch;
 
@@ -286,6 +286,7 @@ gnav_status gnav_transport_batch(gnav_ctx* ctx, const gnav_batch* batch, gnav_ta
 
 /* Launch settings of gnav_transport_batch chosen by gnav_autotune. */
 typedef struct {
+  int32_t block;              /* track-pool slots (threads) per block */
   int32_t grid;
   int32_t chunk;
   int32_t sort_period;
@@ -295,9 +296,10 @@ typedef struct {
 /* Autotuner (the scheduling knobs of Sec. 5: how tracks are grouped and
  * refilled).  Times the transport of `batch` (trials runs per setting after
  * one warm-up, median, hipEvents on `stream`) over a coordinate search of
- * grid (1, 2, 3, 4, 6 blocks per compute unit), chunk (0, 256, 1024, 4096)
- * and sort_period (0, 1, 4, 16), keeps the fastest in the context for this
- * geometry, precision, order and batch size (power-of-two class), and
+ * block (256, 128, 64 pool slots, each with the grid that fills the device),
+ * grid (a quarter, half, twice and three times that), chunk (0, 256, 1024,
+ * 4096) and sort_period (0, 1, 4, 16), keeps the fastest in the context for
+ * this geometry, precision, order and batch size (power-of-two class), and
  * returns it in `out` (may be NULL).  Batches with tuned = 1 then use it.
  * `tally` is scratch (left zeroed); batch must not carry a log or recorder.
  * Synchronous; trials in 1..100. */

@@ -15,7 +15,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgnav.so")
 
-SOURCES = ["gnav_host.cpp", "gnav_kernels.hip", "gnav_mlp.hip"]
+# (source, object name, extra defines): the transport kernel is built once per
+# track-pool size.
+SOURCES = [("gnav_host.cpp", "gnav_host", ()), ("gnav_kernels.hip", "gnav_kernels", ()),
+           ("gnav_mlp.hip", "gnav_mlp", ())] + \
+          [("gnav_transport.hip", f"gnav_transport_pool{p}", (f"GNAV_POOL={p}",)) for p in (64, 128, 256)]
 
 # -ffp-contract=off: no fused multiply-add contraction, so each distance is
 # rounded operation by operation.  The packed-fp32 feature is disabled for all
@@ -40,9 +44,9 @@ def build(verbose=False, defines=(), out=None, objdir=None):
     tmpdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
     objs, procs = [], []
-    for src in SOURCES:
-        obj = os.path.join(tmpdir, src + ".o")
-        cmd = [hipcc(), "-x", "hip"] + HIPFLAGS + [f"-D{d}" for d in defines] + \
+    for src, name, extra in SOURCES:
+        obj = os.path.join(tmpdir, name + ".o")
+        cmd = [hipcc(), "-x", "hip"] + HIPFLAGS + [f"-D{d}" for d in tuple(defines) + tuple(extra)] + \
               ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -1144,6 +1144,18 @@ namespace {
 
 // Validate a batch and fill the launch description (may grow the
 // pending-photon buffer, which synchronises the stream).
+// Default track-pool slots per block (the fastest of 64 / 128 / 256 on the
+// calorimeter and close to it on the barrel).
+constexpr int kDefaultBlock = 128;
+
+// Blocks that fill the device: two waves per SIMD are resident (eight per
+// compute unit), so 2 * 256 / block blocks per compute unit, but no more
+// blocks than the batch fills.
+int default_grid(const gnav_ctx* c, int block, long n) {
+  long need = std::max<long>(1, (n + block - 1) / block);
+  return (int)std::min<long>(need, (long)c->n_cu * 2 * (256 / block));
+}
+
 std::array<int, 4> tuning_key(const gnav_batch* b) {
   int lg = 0;
   while (lg < 62 && (1LL << (lg + 1)) <= b->n_primaries) lg++;
@@ -1167,19 +1179,21 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
     return fail(c, GNAV_EINVAL, "log buffers incomplete");
   if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
-  int grid_req = b->grid, chunk_req = b->chunk, sort_req = b->sort_period;
+  int grid_req = b->grid, chunk_req = b->chunk, sort_req = b->sort_period, block_req = b->block;
   if (b->tuned) {
     auto it = c->tuning.find(tuning_key(b));
     if (it != c->tuning.end()) {
+      block_req = it->second.block;
       grid_req = it->second.grid;
       chunk_req = it->second.chunk;
       sort_req = it->second.sort_period;
     }
   }
-  int block = b->block > 0 ? b->block : 256;
-  if (block != 256) return fail(c, GNAV_EINVAL, "block must be 256 (one 256-slot track pool per block)");
+  int block = block_req > 0 ? block_req : kDefaultBlock;
+  if (block != 64 && block != 128 && block != 256)
+    return fail(c, GNAV_EINVAL, "block must be 64, 128 or 256 (the track-pool slots of a block)");
   long need = (b->n_primaries + block - 1) / block;
-  int grid = grid_req > 0 ? grid_req : (int)std::min<long>(std::max<long>(need, 1), (long)c->n_cu * 3);
+  int grid = grid_req > 0 ? grid_req : default_grid(c, block, b->n_primaries);
   TransportLaunch& L = *out;
   L = TransportLaunch{};
   L.G = c->G;
@@ -1302,9 +1316,10 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
   hipStream_t st = (hipStream_t)stream;
   gnav_batch b = *batch;
   b.tuned = 0;
-  long need = std::max<long>(1, (b.n_primaries + 255) / 256);
-  // coordinate descent: grid, then chunk, then sort period
-  gnav_tuning best{(int)std::min<long>(need, (long)c->n_cu * 3), 0, 0, 0.f};
+  // coordinate descent: block (pool size) with its default grid, then grid,
+  // then chunk, then sort period
+  gnav_tuning best{kDefaultBlock, default_grid(c, kDefaultBlock, b.n_primaries), 0, 0, 0.f};
+  b.block = best.block;
   b.grid = best.grid;
   b.chunk = 0;
   b.sort_period = 0;
@@ -1314,24 +1329,40 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
     float ms = 0;
     gnav_status r = time_setting(c, cand, t, st, trials, &ms);
     if (r) return r;
-    if (ms < best.ms) best = gnav_tuning{cand.grid, cand.chunk, cand.sort_period, ms};
+    if (ms < best.ms) best = gnav_tuning{cand.block, cand.grid, cand.chunk, cand.sort_period, ms};
     return GNAV_OK;
   };
-  for (int f : {1, 2, 4, 6}) {
-    int g = (int)std::min<long>(need, (long)c->n_cu * f);
-    if (g == best.grid) continue;
+  for (int bl : {256, 128, 64}) {
+    if (bl == kDefaultBlock) continue;
     gnav_batch cand = b;
-    cand.grid = g;
+    cand.block = bl;
+    cand.grid = default_grid(c, bl, b.n_primaries);
     if ((s = consider(cand))) return s;
+  }
+  {
+    const long need = std::max<long>(1, (b.n_primaries + best.block - 1) / best.block);
+    const int per_cu = 2 * 256 / best.block;  // resident blocks per compute unit
+    for (int f : {1, 2}) {
+      for (int g : {(int)std::min<long>(need, (long)c->n_cu * per_cu / (2 * f)),
+                    (int)std::min<long>(need, (long)c->n_cu * per_cu * (f + 1))}) {
+        if (g == best.grid) continue;
+        gnav_batch cand = b;
+        cand.block = best.block;
+        cand.grid = g;
+        if ((s = consider(cand))) return s;
+      }
+    }
   }
   for (int ch : {256, 1024, 4096}) {
     gnav_batch cand = b;
+    cand.block = best.block;
     cand.grid = best.grid;
     cand.chunk = ch;
     if ((s = consider(cand))) return s;
   }
   for (int sp : {1, 4, 16}) {
     gnav_batch cand = b;
+    cand.block = best.block;
     cand.grid = best.grid;
     cand.chunk = best.chunk;
     cand.sort_period = sp;

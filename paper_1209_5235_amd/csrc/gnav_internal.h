@@ -70,6 +70,10 @@ hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, c
 hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
                          const int* touch, double* out, hipStream_t st);
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);
+// the transport kernel built for track pools of 64, 128 and 256 slots
+hipError_t launch_transport_pool64(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool128(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool256(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, const double* dir,
                             const double* life, double E, double mu_mass, double* t_out, int* nb_out,
                             hipStream_t st);

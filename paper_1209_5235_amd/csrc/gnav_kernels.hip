@@ -1,22 +1,13 @@
-// gnav_kernels.hip -- navigation query kernels and the persistent gamma
-// transport kernel for gfx950 (wave64).
-//
-// Transport follows Sec. 3.1: each photon draws an Exp(1) optical depth
-// (Alg. 1, steps 1-2), spends it boundary to boundary (S_j update, Eq. 6)
-// and interacts where it runs out (T = t_{j-1} + (Y - S_{j-1}) / mu_j,
-// Eq. 7); after a Compton scatter a new depth is drawn.  Each block keeps a
-// pool of tracks in LDS and runs rounds of phases (refill, navigate, step,
-// interact); before each phase the slots that need it are compacted into a
-// dense work list so the lanes of a wave follow one code path (the
-// divergence Sec. 5 names, handled by compaction in LDS rather than by a
-// separate compaction pass).  Idle slots refill from a device work queue
-// and from a block stack of annihilation photons.
+// gnav_kernels.hip -- navigation query kernels (locate, ComputeStep,
+// ComputeSafety), the free path of Alg. 1 alone, small reset kernels, and
+// the dispatch of the transport kernel to the build for the chosen pool size.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "gnav_device.h"
 #include "gnav_internal.h"
+#include "gnav_physics.h"
 
 namespace gnav {
 
@@ -98,78 +89,6 @@ __global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int
   out[i] = saf;
 }
 
-// ---------------------------------------------------------------------------
-// Transport
-// ---------------------------------------------------------------------------
-
-// Table position of energy E: node index i and weight w, linear in ln E
-// over 257 nodes (clamped at both ends).
-__device__ __forceinline__ void mu_index(const DevGeom& G, double E, int& i, double& w) {
-  double x = (log(E) - G.lnE0) / G.dlnE;
-  if (x < 0) i = 0;
-  else if (x >= 255.0) i = 255;
-  else i = (int)x;
-  w = x - (double)i;
-  w = dmin(dmax(w, 0.0), 1.0);
-}
-
-__device__ __forceinline__ void mu_parts(const DevGeom& G, int mat, int i, double w, double E, double& pe,
-                                         double& co, double& pp) {
-  const double* t = G.xs + (size_t)mat * 3 * kNNode;
-  pe = (1.0 - w) * t[i] + w * t[i + 1];
-  co = (1.0 - w) * t[kNNode + i] + w * t[kNNode + i + 1];
-  pp = (1.0 - w) * t[2 * kNNode + i] + w * t[2 * kNNode + i + 1];
-  if (E < 2.0 * kMe) pp = 0.0;
-}
-
-// Butcher-Messel sampling of the Klein-Nishina energy fraction eps = E'/E:
-// a two-branch mixture (weights ln(1+2k) and (1-eps0^2)/2) with acceptance
-// 1 - eps sin^2(theta) / (1 + eps^2); three draws per trial.
-__device__ __forceinline__ void compton_sample(double E, Philox& rs, uint32_t s0, uint32_t s1, double& eps,
-                                               double& onecost, double& sint2) {
-  double k = E / kMe;
-  double eps0 = 1.0 / (1.0 + 2.0 * k);
-  double eps0sq = eps0 * eps0;
-  double a1 = log(1.0 + 2.0 * k);
-  double a2 = 0.5 * (1.0 - eps0sq);
-  for (int trial = 0; trial < kMaxComptonTrials; trial++) {
-    double r1 = rng_next(rs, s0, s1), r2 = rng_next(rs, s0, s1), r3 = rng_next(rs, s0, s1);
-    double epssq;
-    if (r1 * (a1 + a2) < a1) {
-      eps = exp(-a1 * r2);
-      epssq = eps * eps;
-    } else {
-      epssq = eps0sq + (1.0 - eps0sq) * r2;
-      eps = sqrt(epssq);
-    }
-    onecost = (1.0 - eps) / (eps * k);
-    sint2 = onecost * (2.0 - onecost);
-    double g = 1.0 - eps * sint2 / (1.0 + epssq);
-    if (r3 <= g) break;
-  }
-}
-
-// Turn unit vector v by polar angle (cos, sin) and azimuth phi about itself.
-__device__ __forceinline__ void rotate_dir(V3& v, double cost, double sint, double phi) {
-  double cp = cos(phi), sp = sin(phi);
-  double a = v.x, b = v.y, c = v.z;
-  double rp = sqrt(a * a + b * b);
-  double nx, ny, nz;
-  if (rp < 1e-12) {
-    nx = sint * cp;
-    ny = sint * sp;
-    nz = (c >= 0 ? 1.0 : -1.0) * cost;
-  } else {
-    double e1x = a * c / rp, e1y = b * c / rp, e1z = -(a * a + b * b) / rp;
-    double e2x = -b / rp, e2y = a / rp, e2z = 0.0;
-    nx = cost * a + sint * (cp * e1x + sp * e2x);
-    ny = cost * b + sint * (cp * e1y + sp * e2y);
-    nz = cost * c + sint * (cp * e1z + sp * e2z);
-  }
-  double nn = sqrt(nx * nx + ny * ny + nz * nz);
-  v = V3{nx / nn, ny / nn, nz / nn};
-}
-
 // Free path of Alg. 1 alone (the paper's timed phase, Alg. 2 phase 5): from
 // the start point, cross boundaries accumulating the optical depth S_j = sum
 // mu_i s_i (Eq. 6) until it reaches the particle's lifetime Y; the first
@@ -223,848 +142,6 @@ __global__ void __launch_bounds__(256) k_free_path(DevGeom G, int W, long n, con
   if (nb_out) nb_out[i] = nb;
 }
 
-struct TransportArgs {
-  DevGeom G;
-  long n;
-  const int* event;
-  const int* prim_id;
-  const double* pos;
-  const double* dir;
-  const double* energy;
-  const int* event_geom;   // may be null
-  int geom_default;
-  const int* geom_tbase;   // [geoms] first touchable (global) = the world
-  int n_geoms;
-  int n_events;
-  uint32_t seed_lo, seed_hi;
-  double ecut;
-  int max_steps;
-  double* edep_t;
-  double* edep_ev;
-  double* esc_ev;
-  unsigned long long* counters;
-  unsigned long long* queue;  // [0]: next primary
-  double* pend;               // [lanes][6]: pending annihilation photon position and direction
-  gnav_logrec* log;
-  long log_cap;
-  int* log_n;
-  int* log_fate;
-  gnav_crossing* rec;         // optional crossing recorder
-  long rec_cap;
-  unsigned long long* rec_count;
-  MlpView mlp;                // candidate-ordering network (learned order)
-  int chunk;                  // 0: each wave claims what it needs; > 0: the block claims chunks
-  int sort_period;            // every sort_period-th round buckets the step phase by volume (0: never)
-  int n_lv;                   // resident logical volumes (sort keys)
-};
-
-__device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// Occupancy target for the transport kernel (waves per SIMD, settable at
-// build time; 0 leaves register allocation to the compiler).  Two waves per
-// SIMD (two 256-slot blocks per compute unit) caps a wave at 256 registers,
-// VGPRs and AGPRs together, which the learned-order instantiation would
-// otherwise exceed.
-#ifndef GNAV_TRANSPORT_WAVES
-#define GNAV_TRANSPORT_WAVES 2
-#endif
-#if GNAV_TRANSPORT_WAVES > 0
-#define GNAV_TRANSPORT_ATTR __attribute__((amdgpu_waves_per_eu(GNAV_TRANSPORT_WAVES)))
-#else
-#define GNAV_TRANSPORT_ATTR
-#endif
-
-// ---------------------------------------------------------------------------
-// Block track pool.  Each block owns kPool track slots held in LDS as
-// structure of arrays.  One loop iteration runs four block-wide phases:
-//   refill   - empty slots take a pending annihilation photon or a queued
-//              primary (one queue atomic per wave);
-//   navigate - slots that start a track or crossed a boundary relocate;
-//   step     - slots ready to move compute mu, the safety shortcut or a
-//              ComputeStep, and advance;
-//   interact - slots whose step ended in an interaction sample it.
-// Before each phase the slots that need it are compacted into a dense work
-// list with wave ballots and a block prefix sum (optionally bucketed by a
-// small key: the mother's solid type for steps, the process for
-// interactions), so the lanes of a wave run the same code path.
-// ---------------------------------------------------------------------------
-
-constexpr int kPool = 256;
-constexpr int kWaves = kPool / 64;
-constexpr int kStack = 64;  // block stack of annihilation photons (entries)
-
-// slot status
-enum : int { kEmpty = 0, kNav = 1, kStep = 2, kInt = 3 };
-// process codes for kInt
-enum : int { kProcPE = 0, kProcCompton = 1, kProcPair = 2 };
-
-struct Pool {
-  double x[kPool], y[kPool], z[kPool], vx[kPool], vy[kPool], vz[kPool];
-  double E[kPool], nl[kPool], saf[kPool], mu[kPool], wmu[kPool], slast[kPool];
-  int T[kPool], lvk[kPool], tbase[kPool], event[kPool], key[kPool], draw[kPool];
-  int status[kPool];  // kEmpty / kNav / kStep / kInt
-  int aux[kPool];     // kNav: navigation mode | lim << 2 ; kInt: process
-  int zero_steps[kPool];  // zero-step count (low 8 bits) | steps << 8
-  int imu_mat[kPool];     // table node | cached material << 9 (material + 1, 0 = none)
-  int prim[kPool];
-  int sub_pend[kPool];    // photon index (0..2) | pending annihilation photons << 4
-  int nrec[kPool];
-  unsigned cnt_a[kPool];  // Compton scatters | shortcuts << 16
-  unsigned cnt_b[kPool];  // crossings | pushes << 24
-  int pred[kPool];     // learned order: predicted candidate position of the next step
-  double dep[kPool];   // deposits of the slot's current track, added to its event at the end
-  // annihilation photons waiting for any free slot of the block (a stack)
-  double sx[kStack], sy[kStack], sz[kStack], svx[kStack], svy[kStack], svz[kStack];
-  int sev[kStack], skey[kStack], stb[kStack], sprim[kStack];
-  int sn;              // valid stack entries
-  int list[kPool];
-  int wcnt[16 * kWaves];
-  int total[16];
-  unsigned long long cnt[GNAV_NCOUNTERS];
-  long qr[4];          // block-claimed primaries not yet started: [qr0, qr1) then [qr2, qr3)
-  int qopen;           // the device queue may still hold primaries
-  int any_alive;
-};
-
-// Dense work list of the slots with `flag`, bucketed by `key` in [0, K):
-// list entries of bucket 0 first, then bucket 1, ...  Returns the count
-// (block uniform).  Must be called by every thread of the block.
-template <int K>
-__device__ __forceinline__ int compact(Pool& P, bool flag, int key) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  unsigned long long my_mask = 0;
-#pragma unroll
-  for (int b = 0; b < K; b++) {
-    unsigned long long m = __ballot(flag && key == b);
-    if (flag && key == b) my_mask = m;
-    if (lane == 0) P.wcnt[b * kWaves + w] = __popcll(m);
-  }
-  __syncthreads();
-  if (threadIdx.x < K) {
-    int t = 0;
-#pragma unroll
-    for (int ww = 0; ww < kWaves; ww++) t += P.wcnt[threadIdx.x * kWaves + ww];
-    P.total[threadIdx.x] = t;
-  }
-  __syncthreads();
-  int n = 0;
-#pragma unroll
-  for (int b = 0; b < K; b++) n += P.total[b];
-  if (flag) {
-    int base = 0;
-    for (int b = 0; b < key; b++) base += P.total[b];
-    for (int ww = 0; ww < w; ww++) base += P.wcnt[key * kWaves + ww];
-    P.list[base + __popcll(my_mask & lt)] = threadIdx.x;
-  }
-  __syncthreads();
-  return n;
-}
-
-template <bool LOG>
-__device__ __forceinline__ void end_track(Pool& P, const TransportArgs& a, int s, int fate, int steps) {
-  P.status[s] = kEmpty;
-  if (P.dep[s] != 0.0) atomic_add_f64(a.edep_ev + P.event[s], P.dep[s]);
-  int slot = fate == GNAV_FATE_ABSORBED ? GNAV_C_PE
-           : fate == GNAV_FATE_PAIR     ? GNAV_C_PAIR
-           : fate == GNAV_FATE_ESCAPED  ? GNAV_C_ESCAPED
-           : fate == GNAV_FATE_CUTOFF   ? GNAV_C_CUTOFF
-           : fate == GNAV_FATE_STUCK    ? GNAV_C_STUCK
-                                        : GNAV_C_TRUNCATED;
-  atomicAdd(&P.cnt[slot], 1ull);
-  if (steps) atomicAdd(&P.cnt[GNAV_C_STEPS], (unsigned long long)steps);
-  unsigned ca = P.cnt_a[s], cb = P.cnt_b[s];
-  if (ca & 0xFFFF) atomicAdd(&P.cnt[GNAV_C_COMPTON], (unsigned long long)(ca & 0xFFFF));
-  if (ca >> 16) atomicAdd(&P.cnt[GNAV_C_SHORTCUTS], (unsigned long long)(ca >> 16));
-  if (cb & 0xFFFFFF) atomicAdd(&P.cnt[GNAV_C_CROSSINGS], (unsigned long long)(cb & 0xFFFFFF));
-  if (cb >> 24) atomicAdd(&P.cnt[GNAV_C_PUSHES], (unsigned long long)(cb >> 24));
-  if (LOG) {
-    int sub = P.sub_pend[s] & 15;
-    a.log_n[3 * P.prim[s] + sub] = P.nrec[s];
-    a.log_fate[3 * P.prim[s] + sub] = fate;
-  }
-}
-
-template <bool LOG>
-__device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, int T, int code, double step,
-                                        double edep, double energy) {
-  if (LOG) {
-    int n = P.nrec[s];
-    if (n < a.log_cap) {
-      int sub = P.sub_pend[s] & 15;
-      a.log[(long)(3 * P.prim[s] + sub) * a.log_cap + n] = gnav_logrec{T - P.tbase[s], code, step, edep, energy};
-    }
-    P.nrec[s] = n + 1;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Learned order: one wave scores up to 64 queued steps with the network on
-// bf16 MFMA (v_mfma_f32_16x16x16_bf16, float accumulation), 16 queries per
-// M tile.  Per lane l: A rows m = l % 16, k = 4 (l / 16) + 0..3; B columns
-// n = l % 16, same k; D columns n = l % 16, rows 4 (l / 16) + 0..3.  Hidden
-// activations pass through a per-wave LDS tile [16][128] bf16; the logits
-// reuse it as [16][64] float.  The predicted position is the argmax.
-// ---------------------------------------------------------------------------
-
-typedef short lbf16x4 __attribute__((ext_vector_type(4)));
-typedef float lf32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t lf2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float lbf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-
-struct LearnScratch {
-  uint16_t h[kWaves][16][128];  // per wave: activations (bf16), then the logits as float [16][64]
-  int cls[kWaves][16];
-};
-
-// Four consecutive bf16 values as one MFMA operand (8-byte aligned loads).
-__device__ __forceinline__ lbf16x4 load_bf16x4(const uint16_t* p) {
-  return *reinterpret_cast<const lbf16x4*>(p);
-}
-
-// The block's waves score the n listed steps, 16 per MFMA row tile (wave w
-// takes tiles w, w + 4, ...): layer 1 is [16 x 16(6)] x [16 x 128] plus the
-// mother-class row of W1, layers 2 and 3 are [16 x 128] x [128 x 128] and
-// x [128 x 64].  Each 16 x 16 output tile is accumulated over K in FP32 and
-// written back at once; a layer's input row is read into registers before
-// any output is written, so one LDS buffer per wave serves every layer.
-// MFMA operand layout (16x16x16 bf16): lane l holds A row l % 16 and B
-// column l % 16 at k = 4 (l / 16) + 0..3; the result holds column l % 16,
-// rows 4 (l / 16) + 0..3.
-__device__ __attribute__((noinline)) void learned_predict(const TransportArgs& a, Pool& P, LearnScratch& S,
-                                                          int n) {
-  const DevGeom& G = a.G;
-  const MlpView& M = a.mlp;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  uint16_t (*h)[128] = S.h[w];
-  float (*lg)[64] = reinterpret_cast<float (*)[64]>(&S.h[w][0][0]);
-  for (int row0 = 16 * w; row0 < n; row0 += 16 * kWaves) {
-    // features of row r: point in the mother frame over the grid half size, direction
-    const int li = row0 + r;
-    const bool valid = li < n;
-    float f[6] = {0, 0, 0, 0, 0, 0};
-    int cls = 0;
-    if (valid) {
-      const int s = P.list[li];
-      const int lvk = P.lvk[s];
-      const LRec& L = G.lv[lvk >> 1];
-      V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
-      V3 pl, vl;
-      touchable_frame(G, P.T[s], lvk & 1, x, v, pl, vl);
-      const double pc[3] = {pl.x, pl.y, pl.z};
-#pragma unroll
-      for (int ax = 0; ax < 3; ax++) {
-        double half = 0.5 * L.n[ax] * L.vw[ax];
-        f[ax] = (float)((pc[ax] - (L.vlo[ax] + half)) / half);
-      }
-      f[3] = (float)vl.x;
-      f[4] = (float)vl.y;
-      f[5] = (float)vl.z;
-      cls = L.lclass;
-      cls = cls < 0 ? 0 : (cls >= M.n_class ? M.n_class - 1 : cls);
-    }
-    if (q == 0) S.cls[w][r] = cls;
-    lbf16x4 xa;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int k = 4 * q + j;
-      xa[j] = (short)(k < 6 ? lf2bf(f[k]) : 0);
-    }
-    __builtin_amdgcn_wave_barrier();
-    // layer 1 (K padded from 6 to 16) + b1 + W1m[class], ReLU
-    for (int ct = 0; ct < 8; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 wb;
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        int k = 4 * q + j;
-        wb[j] = (short)(k < 6 ? M.w1x[nn * 6 + k] : 0);
-      }
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, wb, acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        int row = 4 * q + j;
-        float v = acc[j] + lbf2f(M.w1m[(long)S.cls[w][row] * 128 + nn]) + M.b1[nn];
-        h[row][nn] = lf2bf(v > 0.f ? v : 0.f);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    // layer 2 + b2, ReLU (written over the input rows)
-    // (the row's A operands stay in registers across the output tiles; each
-    // tile's eight B operands are loaded together before its MFMA chain)
-    lbf16x4 a1[8];
-#pragma unroll
-    for (int kt = 0; kt < 8; kt++) a1[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
-    for (int ct = 0; ct < 8; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 b[8];
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w2 + nn * 128 + 16 * kt + 4 * q);
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[kt], b[kt], acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        float v = acc[j] + M.b2[nn];
-        h[4 * q + j][nn] = lf2bf(v > 0.f ? v : 0.f);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    // layer 3 + b3 -> logits (float, over the same buffer)
-    lbf16x4 a2[8];
-#pragma unroll
-    for (int kt = 0; kt < 8; kt++) a2[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
-    for (int ct = 0; ct < 4; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 b[8];
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w3 + nn * 128 + 16 * kt + 4 * q);
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], b[kt], acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) lg[4 * q + j][nn] = acc[j] + M.b3[nn];
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (q == 0 && valid) {
-      int best = 0;
-      float bv = lg[r][0];
-      for (int c = 1; c < 64; c++) {
-        float v = lg[r][c];
-        if (v > bv) {
-          bv = v;
-          best = c;
-        }
-      }
-      P.pred[P.list[li]] = best;
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-template <bool LOG, bool COUNT, int ORDER, int PREC>
-__global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
-  const DevGeom& G = a.G;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  __shared__ Pool P;
-  double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
-
-  if (tid < GNAV_NCOUNTERS) P.cnt[tid] = 0ull;
-  if (tid < 4) P.qr[tid] = 0;
-  if (tid == 0) {
-    P.qopen = 1;
-    P.sn = 0;
-  }
-  P.status[tid] = kEmpty;
-  P.sub_pend[tid] = 0;
-  NavCount<COUNT> nc;
-  bool queue_open = true;
-  __syncthreads();
-
-  for (int round = 0;; round++) {
-    // ---- refill: thread tid owns slot tid ---------------------------------
-    {
-      const int s = tid;
-      bool empty = P.status[s] == kEmpty;
-      int sp = P.sub_pend[s];
-      int pending = sp >> 4;
-      bool start = false;
-      if (empty && pending > 0) {
-        int sub = 3 - pending;
-        P.sub_pend[s] = sub | ((pending - 1) << 4);
-        P.x[s] = my_pend[0];
-        P.y[s] = my_pend[1];
-        P.z[s] = my_pend[2];
-        double sgn = (sub == 1) ? 1.0 : -1.0;
-        P.vx[s] = sgn * my_pend[3];
-        P.vy[s] = sgn * my_pend[4];
-        P.vz[s] = sgn * my_pend[5];
-        P.E[s] = kMe;
-        P.key[s] = (P.key[s] & ~3) | sub;
-        start = true;
-      }
-      bool need = empty && !start;
-      // annihilation photons parked on the block stack go to free slots first
-      const int sn = P.sn;
-      if (sn > 0) {
-        const int w = tid >> 6;
-        unsigned long long mask = __ballot(need);
-        if (lane == 0) P.wcnt[w] = __popcll(mask);
-        __syncthreads();
-        int before = 0, n_need = 0;
-#pragma unroll
-        for (int ww = 0; ww < kWaves; ww++) {
-          int c = P.wcnt[ww];
-          if (ww < w) before += c;
-          n_need += c;
-        }
-        if (need) {
-          int rank = before + __popcll(mask & lt_mask);
-          if (rank < sn) {
-            const int e = sn - 1 - rank;
-            P.x[s] = P.sx[e];
-            P.y[s] = P.sy[e];
-            P.z[s] = P.sz[e];
-            P.vx[s] = P.svx[e];
-            P.vy[s] = P.svy[e];
-            P.vz[s] = P.svz[e];
-            P.E[s] = kMe;
-            P.event[s] = P.sev[e];
-            P.key[s] = P.skey[e];
-            P.tbase[s] = P.stb[e];
-            P.prim[s] = P.sprim[e];
-            P.sub_pend[s] = P.skey[e] & 3;
-            start = true;
-            need = false;
-          }
-        }
-        __syncthreads();
-        if (tid == 0) P.sn = sn - min(sn, n_need);
-      }
-      long idx = -1;
-      if (a.chunk <= 0) {
-        // each wave claims exactly the primaries its idle lanes need
-        unsigned long long mask = queue_open ? __ballot(need) : 0ull;
-        if (mask) {
-          int cnt = __popcll(mask);
-          int leader = __ffsll((long long)mask) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)cnt);
-          base = __shfl(base, leader);
-          if (base + cnt >= (unsigned long long)a.n) queue_open = false;
-          if (need) {
-            unsigned long long q = base + __popcll(mask & lt_mask);
-            if (q < (unsigned long long)a.n) idx = (long)q;
-          }
-        }
-      } else {
-        // the block claims `chunk` primaries at a time and hands them out in
-        // slot order; at most two claimed ranges are open at once
-        const int w = tid >> 6;
-        unsigned long long mask = __ballot(need);
-        if (lane == 0) P.wcnt[w] = __popcll(mask);
-        __syncthreads();
-        int before = 0, n_need = 0;
-#pragma unroll
-        for (int ww = 0; ww < kWaves; ww++) {
-          int c = P.wcnt[ww];
-          if (ww < w) before += c;
-          n_need += c;
-        }
-        if (tid == 0 && P.qopen) {
-          long have = (P.qr[1] - P.qr[0]) + (P.qr[3] - P.qr[2]);
-          if (have < n_need) {
-            long want = max((long)a.chunk, (long)n_need - have);
-            long base = (long)atomicAdd(a.queue, (unsigned long long)want);
-            long end = min(base + want, a.n);
-            if (base + want >= a.n) P.qopen = 0;
-            if (base < end) {
-              if (P.qr[1] == P.qr[0]) {
-                P.qr[0] = P.qr[2];
-                P.qr[1] = P.qr[3];
-              }
-              if (P.qr[1] == P.qr[0]) {
-                P.qr[0] = base;
-                P.qr[1] = end;
-                P.qr[2] = P.qr[3] = 0;
-              } else {
-                P.qr[2] = base;
-                P.qr[3] = end;
-              }
-            }
-          }
-        }
-        __syncthreads();
-        const long r0 = P.qr[0], r1 = P.qr[1], r2 = P.qr[2], r3 = P.qr[3];
-        if (need) {
-          long rank = before + __popcll(mask & lt_mask);
-          if (rank < r1 - r0) idx = r0 + rank;
-          else if (rank - (r1 - r0) < r3 - r2) idx = r2 + rank - (r1 - r0);
-        }
-        __syncthreads();
-        if (tid == 0) {
-          long take = n_need;
-          long t1 = min(take, r1 - r0);
-          P.qr[0] = r0 + t1;
-          take -= t1;
-          long t2 = min(take, r3 - r2);
-          P.qr[2] = r2 + t2;
-          if (P.qr[2] == P.qr[3]) P.qr[2] = P.qr[3] = 0;
-        }
-      }
-      if (idx >= 0) {
-        V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
-        V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
-        double E = a.energy[idx];
-        int event = a.event[idx];
-        int g = a.geom_default;
-        bool ok = event >= 0 && event < a.n_events;
-        if (ok && a.event_geom) g = a.event_geom[event];
-        ok = ok && g >= 0 && g < a.n_geoms && E > 0 && isfinite(E) && isfinite(x.x) && isfinite(x.y) &&
-             isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
-        if (ok) {
-          P.x[s] = x.x;
-          P.y[s] = x.y;
-          P.z[s] = x.z;
-          P.vx[s] = v.x;
-          P.vy[s] = v.y;
-          P.vz[s] = v.z;
-          P.E[s] = E;
-          P.event[s] = event;
-          P.key[s] = a.prim_id[idx] << 2;
-          P.tbase[s] = a.geom_tbase[g];
-          P.prim[s] = (int)idx;
-          P.sub_pend[s] = 0;
-          start = true;
-        } else {
-          atomicAdd(&P.cnt[GNAV_C_INVALID], 1ull);
-        }
-      }
-      if (start) {
-        P.status[s] = kNav;
-        P.aux[s] = kNavStart;
-        P.T[s] = P.tbase[s];
-      }
-    }
-    // done when no slot holds a track and no claimed or unclaimed primary is
-    // left (a refill that met only invalid primaries does not end the block)
-    {
-      bool more = P.status[tid] != kEmpty;
-      if (a.chunk <= 0) more = more || queue_open;
-      else if (tid == 0) more = more || P.qopen || P.qr[1] > P.qr[0] || P.qr[3] > P.qr[2];
-      if (!__syncthreads_or(more)) break;
-    }
-
-    // ---- navigate: track starts and boundary crossings --------------------
-    {
-      int n = compact<1>(P, P.status[tid] == kNav, 0);
-      if (tid < n) {
-        const int s = P.list[tid];
-        const int mode = P.aux[s] & 3;
-        const int lim = P.aux[s] >> 2;
-        V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
-        if (mode == kNavStart) {
-          atomicAdd(&P.cnt[GNAV_C_TRACKS], 1ull);
-          P.draw[s] = 0;
-          P.dep[s] = 0.0;
-          P.nrec[s] = 0;
-          P.zero_steps[s] = 0;
-          P.cnt_a[s] = 0;
-          P.cnt_b[s] = 0;
-          P.saf[s] = 0.0;
-        }
-        int lvk = 0;
-        int nt = navigate(G, mode, P.T[s], lim, x, v, lvk, nc);
-        if (nt < 0) {
-          atomic_add_f64(a.esc_ev + P.event[s], P.E[s]);
-          end_track<LOG>(P, a, s, GNAV_FATE_ESCAPED, P.zero_steps[s] >> 8);
-        } else {
-          P.T[s] = nt;
-          P.lvk[s] = lvk;
-          P.status[s] = kStep;
-          if (mode == kNavStart) {
-            Philox rs{(uint32_t)P.event[s], (uint32_t)P.key[s], 0u};
-            P.nl[s] = -log(rng_next(rs, a.seed_lo, a.seed_hi));
-            P.draw[s] = (int)rs.draw;
-            int imu;
-            double w;
-            mu_index(G, P.E[s], imu, w);
-            P.imu_mat[s] = imu;  // no cached material
-            P.wmu[s] = w;
-          }
-        }
-      }
-      __syncthreads();
-    }
-
-    // ---- learned order: score the steps whose mother has a voxel grid -------
-    // (only steps whose start voxel node holds enough candidates for an order
-    // to pay)
-    if constexpr (ORDER == kOrderLearned) {
-      __shared__ LearnScratch S;
-      bool elig = false;
-      if (P.status[tid] == kStep) {
-        const int lvk = P.lvk[tid];
-        const LRec& L = G.lv[lvk >> 1];
-        if (L.lclass >= 0) {
-          V3 x{P.x[tid], P.y[tid], P.z[tid]}, v{P.vx[tid], P.vy[tid], P.vz[tid]};
-          V3 pl, vl;
-          touchable_frame(G, P.T[tid], lvk & 1, x, v, pl, vl);
-          const int ix = vox_axis_index(pl.x, L.vlo[0], L.vinv[0], L.n[0]);
-          const int iy = vox_axis_index(pl.y, L.vlo[1], L.vinv[1], L.n[1]);
-          const int iz = vox_axis_index(pl.z, L.vlo[2], L.vinv[2], L.n[2]);
-          elig = G.vox_node[L.node_base + (ix * L.n[1] + iy) * L.n[2] + iz].y >= kOrderMinCand;
-        }
-      }
-      P.pred[tid] = -1;
-      int n = compact<1>(P, elig, 0);
-      if (n > 0) learned_predict(a, P, S, n);
-      __syncthreads();
-    }
-
-    // ---- step: mu, safety shortcut or ComputeStep, advance ------------------
-    {
-      // bucket the step work by solid family and daughters, or, every
-      // sort_period-th round, by the current logical volume (16 ranges of LV id)
-      const bool by_volume = a.sort_period > 0 && round % a.sort_period == 0;
-      int key = 0;
-      if (P.status[tid] == kStep) {
-        const int lv = P.lvk[tid] >> 1;
-        if (by_volume) {
-          key = (int)(((long)lv * 16) / a.n_lv);
-        } else {
-          const LRec& L = G.lv[lv];
-          key = (L.info & 3) | (L.dau_cnt > 0 ? 4 : 0);
-        }
-      }
-      int n = by_volume ? compact<16>(P, P.status[tid] == kStep, key)
-                        : compact<8>(P, P.status[tid] == kStep, key);
-      if (tid < n) {
-        const int s = P.list[tid];
-        const int T = P.T[s];
-        const int lvk = P.lvk[s];
-        const LRec& L = G.lv[lvk >> 1];
-        double E = P.E[s];
-        int zs = P.zero_steps[s];
-        int steps = zs >> 8;
-        int zero = zs & 0xFF;
-        if (E < a.ecut) {
-          atomic_add_f64(a.edep_t + T, E);
-          P.dep[s] += E;
-          end_track<LOG>(P, a, s, GNAV_FATE_CUTOFF, steps);
-        } else if (steps >= a.max_steps) {
-          end_track<LOG>(P, a, s, GNAV_FATE_TRUNCATED, steps);
-        } else {
-          const int mat = L.mat;
-          int im = P.imu_mat[s];
-          const int imu = im & 511;
-          const double wmu = P.wmu[s];
-          double mu;
-          if ((im >> 9) != mat + 1) {
-            double pe, co, pp;
-            mu_parts(G, mat, imu, wmu, E, pe, co, pp);
-            mu = pe + co + pp;
-            P.mu[s] = mu;
-            P.imu_mat[s] = imu | ((mat + 1) << 9);
-          } else {
-            mu = P.mu[s];
-          }
-          double nl = P.nl[s];
-          double safety = P.saf[s];
-          V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
-          double s_phys = mu > 0 ? nl / mu : kInf;
-          bool phys;
-          double s_geo = kInf;
-          int lim = kLimMother;
-          if (s_phys < safety - kTol) {
-            phys = true;
-            P.cnt_a[s] += 1u << 16;
-          } else {
-            V3 pl, vl;
-            touchable_frame(G, T, lvk & 1, x, v, pl, vl);
-            double saf;
-            int2 nd;
-            s_geo = compute_step_p<COUNT, ORDER, PREC>(G, L, lvk >> 1, pl, vl, lim, saf, nc,
-                                                       ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
-            safety = saf;
-            phys = s_phys <= s_geo;
-            // crossing recorder: a daughter-limited step from a node with 2+ candidates
-            if (a.rec && !phys && lim >= 0 && nd.y >= 2 && L.lclass >= 0) {
-              int label = -1;
-              for (int c = 0; c < nd.y && c < 64; c++)
-                if (G.vox_cand[nd.x + c] == lim) label = c;
-              if (label >= 0) {
-                unsigned long long ri = atomicAdd(a.rec_count, 1ull);
-                if (ri < (unsigned long long)a.rec_cap) {
-                  gnav_crossing cr;
-                  cr.cls = L.lclass;
-                  const double pc[3] = {pl.x, pl.y, pl.z};
-#pragma unroll
-                  for (int ax = 0; ax < 3; ax++) {
-                    double half = 0.5 * L.n[ax] * L.vw[ax];
-                    cr.x[ax] = (float)((pc[ax] - (L.vlo[ax] + half)) / half);
-                  }
-                  cr.v[0] = (float)vl.x;
-                  cr.v[1] = (float)vl.y;
-                  cr.v[2] = (float)vl.z;
-                  cr.label = label;
-                  a.rec[ri] = cr;
-                }
-              }
-            }
-          }
-          steps++;
-          if (phys) {
-            P.x[s] = x.x + s_phys * v.x;
-            P.y[s] = x.y + s_phys * v.y;
-            P.z[s] = x.z + s_phys * v.z;
-            P.saf[s] = safety - s_phys;
-            P.zero_steps[s] = steps << 8;
-            // process choice: the first draw after the step (u mu against the partial sums)
-            double pe, co, pp;
-            mu_parts(G, mat, imu, wmu, E, pe, co, pp);
-            Philox rs{(uint32_t)P.event[s], (uint32_t)P.key[s], (uint32_t)P.draw[s]};
-            double u = rng_next(rs, a.seed_lo, a.seed_hi) * mu;
-            P.draw[s] = (int)rs.draw;
-            P.aux[s] = u < pe ? kProcPE : (u < pe + co ? kProcCompton : kProcPair);
-            P.slast[s] = s_phys;
-            P.status[s] = kInt;
-          } else {
-            // the pure FP32 form steps past the boundary by its surface band, so
-            // the FP64 relocation sees the point on the far side of the face
-            const double s_adv = PREC == kPrecPure ? s_geo + 2.0 * (double)kHalfTolF : s_geo;
-            P.x[s] = x.x + s_adv * v.x;
-            P.y[s] = x.y + s_adv * v.y;
-            P.z[s] = x.z + s_adv * v.z;
-            if (mu > 0) {
-              nl = nl - s_adv * mu;
-              if (nl < 0) nl = 0;
-              P.nl[s] = nl;
-            }
-            log_rec<LOG>(P, a, s, T, lim, s_adv, 0.0, E);
-            P.cnt_b[s] += 1u;
-            P.saf[s] = 0.0;
-            // zero-length steps and the push that ends a run of them, on the
-            // length scale of the surface band of the distance arithmetic
-            constexpr double kZeroLen = PREC == kPrecPure ? 2.0 * kHalfTolF : kTol;
-            constexpr double kPushLen = PREC == kPrecPure ? 10.0 * kZeroLen : 100.0 * kTol;
-            zero = (s_geo < kZeroLen) ? zero + 1 : 0;
-            P.zero_steps[s] = (steps << 8) | zero;
-            if (zero >= kZeroKill) {
-              atomic_add_f64(a.edep_t + T, E);
-              P.dep[s] += E;
-              end_track<LOG>(P, a, s, GNAV_FATE_STUCK, steps);
-            } else {
-              if (zero > 0 && zero % kZeroPush == 0) {
-                P.x[s] = P.x[s] + kPushLen * v.x;
-                P.y[s] = P.y[s] + kPushLen * v.y;
-                P.z[s] = P.z[s] + kPushLen * v.z;
-                P.cnt_b[s] += 1u << 24;
-              }
-              // relocation happens in the next iteration's navigation phase
-              P.aux[s] = (lim >= 0 ? kNavEnter : kNavExit) | (lim << 2);
-              P.status[s] = kNav;
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-
-    // ---- interact: photoelectric, Compton, pair ------------------------------
-    {
-      int n = compact<3>(P, P.status[tid] == kInt, P.aux[tid]);
-      if (tid < n) {
-        const int s = P.list[tid];
-        const int proc = P.aux[s];
-        const int T = P.T[s];
-        const int event = P.event[s];
-        const double E = P.E[s];
-        const double sl = P.slast[s];
-        const int steps = P.zero_steps[s] >> 8;
-        Philox rs{(uint32_t)event, (uint32_t)P.key[s], (uint32_t)P.draw[s]};
-        if (proc == kProcPE) {
-          atomic_add_f64(a.edep_t + T, E);
-          P.dep[s] += E;
-          log_rec<LOG>(P, a, s, T, kLimPE, sl, E, 0.0);
-          end_track<LOG>(P, a, s, GNAV_FATE_ABSORBED, steps);
-        } else if (proc == kProcCompton) {
-          double eps, onecost, sint2;
-          compton_sample(E, rs, a.seed_lo, a.seed_hi, eps, onecost, sint2);
-          double phi = kTwoPi * rng_next(rs, a.seed_lo, a.seed_hi);
-          V3 v{P.vx[s], P.vy[s], P.vz[s]};
-          rotate_dir(v, 1.0 - onecost, sqrt(sint2), phi);
-          P.vx[s] = v.x;
-          P.vy[s] = v.y;
-          P.vz[s] = v.z;
-          double dep = E * (1.0 - eps);
-          double E2 = eps * E;
-          P.E[s] = E2;
-          int imu;
-          double w;
-          mu_index(G, E2, imu, w);
-          P.imu_mat[s] = imu;  // cached mu invalid
-          P.wmu[s] = w;
-          atomic_add_f64(a.edep_t + T, dep);
-          P.dep[s] += dep;
-          P.cnt_a[s] += 1u;
-          log_rec<LOG>(P, a, s, T, kLimCompton, sl, dep, E2);
-          P.nl[s] = -log(rng_next(rs, a.seed_lo, a.seed_hi));
-          P.draw[s] = (int)rs.draw;
-          P.status[s] = kStep;
-        } else {
-          double dep = E - 2.0 * kMe;
-          atomic_add_f64(a.edep_t + T, dep);
-          P.dep[s] += dep;
-          double u1 = rng_next(rs, a.seed_lo, a.seed_hi), u2 = rng_next(rs, a.seed_lo, a.seed_hi);
-          double ct = 1.0 - 2.0 * u1;
-          double st = 2.0 * sqrt(u1 * (1.0 - u1));
-          double ph = kTwoPi * u2;
-          const double wx = st * cos(ph), wy = st * sin(ph), wz = ct;
-          // both photons onto the block stack, so two free slots can take them
-          // at once; when it is full, this slot tracks them one after the other
-          const int e = atomicAdd(&P.sn, 2);
-          if (e + 2 <= kStack) {
-#pragma unroll
-            for (int j = 0; j < 2; j++) {
-              const double sg = j == 0 ? 1.0 : -1.0;
-              P.sx[e + j] = P.x[s];
-              P.sy[e + j] = P.y[s];
-              P.sz[e + j] = P.z[s];
-              P.svx[e + j] = sg * wx;
-              P.svy[e + j] = sg * wy;
-              P.svz[e + j] = sg * wz;
-              P.sev[e + j] = event;
-              P.skey[e + j] = (P.key[s] & ~3) | (j + 1);
-              P.stb[e + j] = P.tbase[s];
-              P.sprim[e + j] = P.prim[s];
-            }
-          } else {
-            atomicSub(&P.sn, 2);
-            double* pd = a.pend + ((long)blockIdx.x * kPool + s) * 6;
-            pd[0] = P.x[s];
-            pd[1] = P.y[s];
-            pd[2] = P.z[s];
-            pd[3] = wx;
-            pd[4] = wy;
-            pd[5] = wz;
-            P.sub_pend[s] = (P.sub_pend[s] & 15) | (2 << 4);
-          }
-          log_rec<LOG>(P, a, s, T, kLimPair, sl, dep, 0.0);
-          end_track<LOG>(P, a, s, GNAV_FATE_PAIR, steps);
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  // ---- flush counters -------------------------------------------------------
-  if (COUNT) {
-    unsigned vals[5] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes, nc.dist_in32};
-    const int slots[5] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
-                          GNAV_C_DIST_IN_F32};
-#pragma unroll
-    for (int c = 0; c < 5; c++) {
-      unsigned long long sum = vals[c];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-      if (lane == 0 && sum) atomicAdd(&P.cnt[slots[c]], sum);
-    }
-  }
-  __syncthreads();
-  if (tid < GNAV_NCOUNTERS && P.cnt[tid]) atomicAdd(a.counters + tid, P.cnt[tid]);
-}
-
 // Zero a small device array (a kernel rather than a memset node, so the
 // launch sequence can be captured in a graph).
 __global__ void k_reset_u64(unsigned long long* p, int n) {
@@ -1081,7 +158,6 @@ __global__ void k_zero_words(unsigned long long* p, size_t n) {
 // ---------------------------------------------------------------------------
 
 static inline unsigned grid_for(long n, int block) { return (unsigned)((n + block - 1) / block); }
-
 hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const double* pos,
                          const double* dir, int* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -1131,63 +207,11 @@ hipError_t launch_zero(void* p, size_t words, hipStream_t st) {
 }
 
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
-  TransportArgs a;
-  a.G = L.G;
-  a.n = L.n;
-  a.event = L.event;
-  a.prim_id = L.prim_id;
-  a.pos = L.pos;
-  a.dir = L.dir;
-  a.energy = L.energy;
-  a.event_geom = L.event_geom;
-  a.geom_default = L.geom_default;
-  a.geom_tbase = L.geom_tbase;
-  a.n_geoms = L.n_geoms;
-  a.n_events = L.n_events;
-  a.seed_lo = (uint32_t)L.seed;
-  a.seed_hi = (uint32_t)(L.seed >> 32);
-  a.ecut = L.ecut;
-  a.max_steps = (int)std::min<long>(L.max_steps, 0x7fffffff);
-  a.edep_t = L.edep_t;
-  a.edep_ev = L.edep_ev;
-  a.esc_ev = L.esc_ev;
-  a.counters = L.counters;
-  a.queue = L.queue;
-  a.pend = L.pend;
-  a.log = L.log;
-  a.log_cap = L.log_cap;
-  a.log_n = L.log_n;
-  a.log_fate = L.log_fate;
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, L.queue, 1);
   if (L.n <= 0) return hipGetLastError();
-  a.rec = L.rec;
-  a.rec_cap = L.rec_cap;
-  a.rec_count = L.rec_count;
-  a.mlp = L.mlp;
-  a.chunk = L.chunk;
-  a.sort_period = L.sort_period;
-  a.n_lv = L.G_n_lv;
-  dim3 grid(L.grid), block(kPool);
-#define GNAV_LAUNCH(LOGV, CNTV, ORDV, PRECV) \
-  hipLaunchKernelGGL((k_transport<LOGV, CNTV, ORDV, PRECV>), grid, block, 0, st, a)
-#define GNAV_LAUNCH_ORDER(LOGV, CNTV)                                                    \
-  do {                                                                                   \
-    if (L.prec == kPrecScreened) GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecScreened);    \
-    else if (L.prec == kPrecPure) GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecPure);       \
-    else if (L.order == kOrderBound) GNAV_LAUNCH(LOGV, CNTV, kOrderBound, kPrecFP64);    \
-    else if (L.order == kOrderLearned) GNAV_LAUNCH(LOGV, CNTV, kOrderLearned, kPrecFP64); \
-    else GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecFP64);                                \
-  } while (0)
-  if (L.log) {
-    if (L.count) GNAV_LAUNCH_ORDER(true, true);
-    else GNAV_LAUNCH_ORDER(true, false);
-  } else {
-    if (L.count) GNAV_LAUNCH_ORDER(false, true);
-    else GNAV_LAUNCH_ORDER(false, false);
-  }
-#undef GNAV_LAUNCH_ORDER
-#undef GNAV_LAUNCH
-  return hipGetLastError();
+  if (L.block == 64) return launch_transport_pool64(L, st);
+  if (L.block == 128) return launch_transport_pool128(L, st);
+  return launch_transport_pool256(L, st);
 }
 
 }  // namespace gnav

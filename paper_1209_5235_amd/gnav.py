@@ -63,8 +63,8 @@ class gnav_batch(C.Structure):
 
 
 class gnav_tuning(C.Structure):
-    _fields_ = [("grid", C.c_int32), ("chunk", C.c_int32), ("sort_period", C.c_int32),
-                ("ms", C.c_float)]
+    _fields_ = [("block", C.c_int32), ("grid", C.c_int32), ("chunk", C.c_int32),
+                ("sort_period", C.c_int32), ("ms", C.c_float)]
 
 
 def _load():
@@ -354,7 +354,8 @@ class Context:
         out = gnav_tuning()
         self._check(gnav_autotune(self.h, C.byref(b), tally.h, int(trials), _stream(stream),
                                   C.byref(out)), "gnav_autotune")
-        return dict(grid=out.grid, chunk=out.chunk, sort_period=out.sort_period, ms=out.ms)
+        return dict(block=out.block, grid=out.grid, chunk=out.chunk, sort_period=out.sort_period,
+                    ms=out.ms)
 
     def graph_create(self, geom_id, prim, tally, stream=None, **kw):
         b = self._batch(geom_id, prim, **kw)

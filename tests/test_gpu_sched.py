@@ -12,7 +12,9 @@ from tests.gpu_common import ctx, geom, print_case, run_transport, torch_dev  # 
 pytestmark = pytest.mark.gpu
 
 SETTINGS = [dict(), dict(chunk=256), dict(chunk=4096, grid=7), dict(sort_period=1),
-            dict(chunk=1024, sort_period=4, grid=300), dict(chunk=64, sort_period=16)]
+            dict(chunk=1024, sort_period=4, grid=300), dict(chunk=64, sort_period=16),
+            dict(block=128), dict(block=64, chunk=256, sort_period=4), dict(block=64, grid=3),
+            dict(block=128, grid=1000, sort_period=1)]
 
 
 @pytest.mark.parametrize("name,n,cap", [("calorimeter", 3000, 200), ("barrel", 2000, 512)])
@@ -60,7 +62,7 @@ def test_autotune_picks_a_setting_and_tuned_runs_match(ctx, torch_dev, oracle_li
     tally = ctx.tally_create(prim.n_events)
     best = ctx.autotune(gid, dev, tally, trials=2)
     print("autotune", best, flush=True)
-    assert best["grid"] >= 1 and best["chunk"] in (0, 256, 1024, 4096)
+    assert best["block"] in (64, 128, 256) and best["grid"] >= 1 and best["chunk"] in (0, 256, 1024, 4096)
     assert best["sort_period"] in (0, 1, 4, 16) and best["ms"] > 0
     # the tally is left zeroed
     z = tally.read()
