@@ -64,7 +64,8 @@ struct LRec {
   int n[3];        // grid counts
   int node_base;
   int lclass;      // candidate-ordering class of a voxelised mother (-1: none)
-  int pad_i[6];
+  int wide;        // 1: its voxel nodes hold kOrderMinCand or more candidates on average
+  int pad_i[5];
   double par[kSolidPar];  // solid parameters
   double vlo[3], vinv[3], vw[3];
   double pad_d[3];
@@ -114,6 +115,8 @@ struct DevGeom {
   const uint16_t* vox_cand; // daughter slots, ascending within a node
   const double* xs;         // [mat][3][257] attenuation, 1/mm
   const double* mat_rho;    // [mat] density, g/cm3
+  const float4* pv_cyl;     // [PV] {rho min, rho max, z min, z max} of the placed solid about
+                            //      the mother's z axis, rounded outward
   const PRecF* pvf;         // [PV] FP32 twins of the placements
   const float* lv_parf;     // [LV][12] FP32 twins of the LV solid parameters
   double lnE0, dlnE;
@@ -755,6 +758,17 @@ __device__ __forceinline__ bool box_beyond(const PRec& P, V3 pl, V3 vl, double s
   return false;
 }
 
+// Isotropic lower bound on the distance from a point (rho = its distance to
+// the mother's z axis, z) to a placed solid, from the solid's enclosing
+// annular cylinder c = {rho min, rho max, z min, z max}: a point outside the
+// radial band is at least the radial gap away from every point of it, and
+// likewise along z.  16 bytes per candidate, no placement or solid record.
+__device__ __forceinline__ double cyl_bound(float4 c, double rho, double z) {
+  const double dr = dmax((double)c.x - rho, rho - (double)c.y);
+  const double dz = dmax((double)c.z - z, z - (double)c.w);
+  return dmax(dmax(dr, dz), 0.0);
+}
+
 // Candidate orders for the start node of a step walk.  Nodes with fewer
 // candidates than kOrderMinCand are walked in slot order (with two, an
 // ordering pass costs more than it can save).
@@ -823,13 +837,14 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
     nc.node();
     if (first && start_node) *start_node = nd;
     if (ORDER != kOrderPlain && first && nd.y >= kOrderMinCand) {
+      const double rho = sqrt(pl.x * pl.x + pl.y * pl.y);
       int lead = -1;
       if (ORDER == kOrderLearned && pred >= 0 && pred < nd.y) lead = pred;
       if (lead < 0) {
+        // the candidate nearest by its enclosing cylinder goes first
         double lbmin = kInf;
         for (int c = 0; c < nd.y; c++) {
-          double sf;
-          double lb = daughter_lower_bound(G, base + G.vox_cand[nd.x + c], pl, vl, sf);
+          const double lb = cyl_bound(G.pv_cyl[base + G.vox_cand[nd.x + c]], rho, pl.z);
           if (lb < lbmin) {
             lbmin = lb;
             lead = c;
@@ -850,6 +865,14 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
       for (int c = 0; c < nd.y; c++) {
         if (c == lead) continue;
         int k = G.vox_cand[nd.x + c];
+        // skip, without fetching the candidate's records, when its enclosing
+        // cylinder lies beyond the best distance (the cylinder distance also
+        // serves as the candidate's share of the safety)
+        const double lbc = cyl_bound(G.pv_cyl[base + k], rho, pl.z);
+        if (lbc * (1.0 - 1e-12) > s + kTol) {
+          saf = dmin(saf, lbc);
+          continue;
+        }
         const double sf = daughter_safety_in(G, base + k, pl);
         saf = dmin(saf, sf);
         // skip when the candidate's safety or its bounding box lies beyond the best

@@ -567,6 +567,7 @@ struct gnav_ctx {
   std::vector<LRec> lv_rec;
   std::vector<PRec> pv_rec;
   std::vector<PRecF> pvf;
+  std::vector<float4> pv_cyl;
   std::vector<float> lv_parf;
   std::vector<int2> vox_node;
   std::vector<uint16_t> vox_cand;
@@ -577,8 +578,8 @@ struct gnav_ctx {
   int n_mats_total = 0;
   double lnE0 = 0, dlnE = 0;
   // device copies
-  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_lv_parf, d_vox_node, d_vox_cand, d_xs, d_mat_rho,
-      d_geom_tbase;
+  DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_pv_cyl, d_lv_parf, d_vox_node, d_vox_cand, d_xs,
+      d_mat_rho, d_geom_tbase;
   DevBuf d_queue, d_pend;
   DevGeom G{};
   // autotuned launch settings by (geometry, precision, order, log2 of the batch size)
@@ -618,6 +619,7 @@ hipError_t upload_all(gnav_ctx* c) {
   UP(d_lv_rec, lv_rec)
   UP(d_pv_rec, pv_rec)
   UP(d_pvf, pvf)
+  UP(d_pv_cyl, pv_cyl)
   UP(d_lv_parf, lv_parf)
   UP(d_vox_node, vox_node)
   UP(d_vox_cand, vox_cand)
@@ -631,6 +633,7 @@ hipError_t upload_all(gnav_ctx* c) {
   G.lv = c->d_lv_rec.as<LRec>();
   G.pv = c->d_pv_rec.as<PRec>();
   G.pvf = c->d_pvf.as<PRecF>();
+  G.pv_cyl = c->d_pv_cyl.as<float4>();
   G.lv_parf = c->d_lv_parf.as<float>();
   G.vox_node = c->d_vox_node.as<int2>();
   G.vox_cand = c->d_vox_cand.as<uint16_t>();
@@ -652,6 +655,38 @@ float round_up_f(double x) {
   float f = (float)x;
   if ((double)f < x) f = std::nextafter(f, std::numeric_limits<float>::infinity());
   return f;
+}
+
+// Enclosing annular cylinder {rho min, rho max, z min, z max} of a placed
+// solid about its mother's z axis, rounded outward: from the padded placed
+// bounding box, tightened by the solid's own radii for tube and cone sections
+// on the mother's axis (rotations about z, or a flip of z) and for orbs.
+float4 placed_cylinder(int type, const double* par, const double* R, const double* t, const PRec& pr) {
+  const double* lo = pr.box_lo;
+  const double* hi = pr.box_hi;
+  double ex = lo[0] > 0 ? lo[0] : (hi[0] < 0 ? -hi[0] : 0.0);
+  double ey = lo[1] > 0 ? lo[1] : (hi[1] < 0 ? -hi[1] : 0.0);
+  double fx = std::max(std::fabs(lo[0]), std::fabs(hi[0]));
+  double fy = std::max(std::fabs(lo[1]), std::fabs(hi[1]));
+  double rmin = std::sqrt(ex * ex + ey * ey), rmax = std::sqrt(fx * fx + fy * fy);
+  const double pad = 1e-7 + 1e-12 * std::max(rmax, std::max(std::fabs(lo[2]), std::fabs(hi[2])));
+  const bool zaxis = R[2] == 0.0 && R[5] == 0.0 && R[6] == 0.0 && R[7] == 0.0 && std::fabs(R[8]) == 1.0;
+  if ((type == kTubs || type == kCons) && zaxis && t[0] == 0.0 && t[1] == 0.0) {
+    double r_in = type == kTubs ? par[0] : std::min(par[0], par[2]);
+    double r_out = type == kTubs ? par[1] : std::max(par[1], par[3]);
+    rmin = std::max(rmin, r_in - pad);
+    rmax = std::min(rmax, r_out + pad);
+  } else if (type == kOrb) {
+    double rt = std::sqrt(t[0] * t[0] + t[1] * t[1]);
+    rmin = std::max(rmin, rt - par[0] - pad);
+    rmax = std::min(rmax, rt + par[0] + pad);
+  }
+  float4 c;
+  c.x = round_down_f(std::max(rmin, 0.0));
+  c.y = round_up_f(rmax);
+  c.z = round_down_f(lo[2]);
+  c.w = round_up_f(hi[2]);
+  return c;
 }
 
 bool is_identity(const double* R) {
@@ -850,6 +885,8 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       }
     }
     c->pv_rec.push_back(pr);
+    c->pv_cyl.push_back(placed_cylinder(d->solid_type[d->lv_solid[d->pv_lv[p]]],
+                                        d->solid_par + 8 * d->lv_solid[d->pv_lv[p]], R, t, pr));
   }
   // logical volumes with their solid and voxel grid
   for (int l = 0; l < d->n_lv; l++) {
@@ -906,6 +943,10 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
         }
         c->vox_node.push_back(int2{off, (int)nd.size()});
       }
+      double mean = 0;
+      for (auto& nd : vb.nodes) mean += (double)nd.size();
+      mean /= std::max<size_t>(1, vb.nodes.size());
+      lr.wide = mean >= kOrderMinCand ? 1 : 0;
     }
     c->lv_rec.push_back(lr);
   }

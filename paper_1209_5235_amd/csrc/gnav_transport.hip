@@ -560,23 +560,14 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     }
 
     // ---- learned order: score the steps whose mother has a voxel grid -------
-    // (only steps whose start voxel node holds enough candidates for an order
-    // to pay)
+    // (only steps in mothers whose voxel nodes hold enough candidates on
+    // average for an order to pay)
     if constexpr (ORDER == kOrderLearned) {
       __shared__ LearnScratch S;
       bool elig = false;
       if (P.status[tid] == kStep) {
-        const int lvk = P.lvk[tid];
-        const LRec& L = G.lv[lvk >> 1];
-        if (L.lclass >= 0) {
-          V3 x{P.x[tid], P.y[tid], P.z[tid]}, v{P.vx[tid], P.vy[tid], P.vz[tid]};
-          V3 pl, vl;
-          touchable_frame(G, P.T[tid], lvk & 1, x, v, pl, vl);
-          const int ix = vox_axis_index(pl.x, L.vlo[0], L.vinv[0], L.n[0]);
-          const int iy = vox_axis_index(pl.y, L.vlo[1], L.vinv[1], L.n[1]);
-          const int iz = vox_axis_index(pl.z, L.vlo[2], L.vinv[2], L.n[2]);
-          elig = G.vox_node[L.node_base + (ix * L.n[1] + iy) * L.n[2] + iz].y >= kOrderMinCand;
-        }
+        const LRec& L = G.lv[P.lvk[tid] >> 1];
+        elig = L.lclass >= 0 && L.wide;
       }
       P.pred[tid] = -1;
       int n = compact<1>(P, elig, 0);
