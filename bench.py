@@ -408,7 +408,7 @@ def main():
 
     flops = algorithmic_flops(c)
     achieved_tf = flops / avg_kern_s / 1e12
-    kernel = f"gnav::pool{args.block or 128}::k_transport<false, false, 0, 0>"
+    kernel = f"gnav::pool{args.block or 64}::k_transport<false, false, 0, 0>"
     traffic = stored_traffic(kernel)
     out = {
         "metric": "gamma navigation steps/s on 1 GPU",
@@ -429,7 +429,7 @@ def main():
                         "0.1-10 MeV, Gaussian beam sigma 10 mm, FP64, Philox seed 0",
             "photons_per_batch": prim.n,
             "nav_steps_per_batch": steps_per_batch,
-            "block": args.block or 128,
+            "block": args.block or 64,
             "grid": args.grid or "default",
         },
         "roofline": {

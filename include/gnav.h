@@ -256,7 +256,7 @@ typedef struct {
   double e_cut;               /* MeV: photons below it deposit locally and stop */
   int64_t max_steps_per_track;/* <= 0: 1e6 */
   int32_t precision;          /* GNAV_PREC_*; FP32 forms need order 0 and no recorder */
-  int32_t block;              /* track-pool slots (= threads) per block: 64, 128 or 256; 0 = 128 */
+  int32_t block;              /* track-pool slots (= threads) per block: 64, 128 or 256; 0 = 64 */
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
   int32_t count_work;         /* 1: also count navigation work (GNAV_C_DIST_IN..VOXEL_NODES) */
   int32_t order;              /* start-node candidate order: 0 slot order, 1 smallest lower bound
@@ -296,8 +296,9 @@ typedef struct {
 /* Autotuner (the scheduling knobs of Sec. 5: how tracks are grouped and
  * refilled).  Times the transport of `batch` (trials runs per setting after
  * one warm-up, median, hipEvents on `stream`) over a coordinate search of
- * block (256, 128, 64 pool slots, each with the grid that fills the device),
- * grid (a quarter, half, twice and three times that), chunk (0, 256, 1024,
+ * block (64, 128, 256 pool slots, each with its default grid: 1.5 times the
+ * resident blocks), grid (a half, one, two and three times the resident
+ * blocks), chunk (0, 256, 1024,
  * 4096) and sort_period (0, 1, 4, 16), keeps the fastest in the context for
  * this geometry, precision, order and batch size (power-of-two class), and
  * returns it in `out` (may be NULL).  Batches with tuned = 1 then use it.

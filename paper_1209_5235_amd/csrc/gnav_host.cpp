@@ -1186,15 +1186,15 @@ namespace {
 // Validate a batch and fill the launch description (may grow the
 // pending-photon buffer, which synchronises the stream).
 // Default track-pool slots per block (the fastest of 64 / 128 / 256 on the
-// calorimeter and close to it on the barrel).
-constexpr int kDefaultBlock = 128;
+// calorimeter and on the barrel).
+constexpr int kDefaultBlock = 64;
 
-// Blocks that fill the device: two waves per SIMD are resident (eight per
-// compute unit), so 2 * 256 / block blocks per compute unit, but no more
-// blocks than the batch fills.
+// Default grid: two waves per SIMD are resident (eight per compute unit, so
+// 2 * 256 / block blocks), and half as many again wait to take over from
+// blocks that run out of work early; no more blocks than the batch fills.
 int default_grid(const gnav_ctx* c, int block, long n) {
   long need = std::max<long>(1, (n + block - 1) / block);
-  return (int)std::min<long>(need, (long)c->n_cu * 2 * (256 / block));
+  return (int)std::min<long>(need, (long)c->n_cu * 3 * (256 / block));
 }
 
 std::array<int, 4> tuning_key(const gnav_batch* b) {
@@ -1382,16 +1382,14 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
   }
   {
     const long need = std::max<long>(1, (b.n_primaries + best.block - 1) / best.block);
-    const int per_cu = 2 * 256 / best.block;  // resident blocks per compute unit
-    for (int f : {1, 2}) {
-      for (int g : {(int)std::min<long>(need, (long)c->n_cu * per_cu / (2 * f)),
-                    (int)std::min<long>(need, (long)c->n_cu * per_cu * (f + 1))}) {
-        if (g == best.grid) continue;
-        gnav_batch cand = b;
-        cand.block = best.block;
-        cand.grid = g;
-        if ((s = consider(cand))) return s;
-      }
+    const long resident = (long)c->n_cu * 2 * (256 / best.block);  // blocks resident at once
+    for (long g : {resident / 2, resident, resident * 2, resident * 3}) {
+      const int gg = (int)std::min<long>(need, std::max<long>(1, g));
+      if (gg == best.grid) continue;
+      gnav_batch cand = b;
+      cand.block = best.block;
+      cand.grid = gg;
+      if ((s = consider(cand))) return s;
     }
   }
   for (int ch : {256, 1024, 4096}) {

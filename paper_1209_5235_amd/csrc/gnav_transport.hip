@@ -64,6 +64,7 @@ namespace GNAV_POOL_NS {
 constexpr int kPool = GNAV_POOL;
 constexpr int kWaves = kPool / 64;
 constexpr int kStack = 64;  // block stack of annihilation photons (entries)
+constexpr int kDep = 4 * kPool;  // block cache of touchable deposits (direct mapped)
 
 // slot status
 enum : int { kEmpty = 0, kNav = 1, kStep = 2, kInt = 3 };
@@ -89,6 +90,8 @@ struct Pool {
   double sx[kStack], sy[kStack], sz[kStack], svx[kStack], svy[kStack], svz[kStack];
   int sev[kStack], skey[kStack], stb[kStack], sprim[kStack];
   int sn;              // valid stack entries
+  int dkey[kDep];      // touchable of a cached deposit sum (-1: free)
+  double dval[kDep];
   int list[kPool];
   int wcnt[16 * kWaves];
   int total[16];
@@ -131,6 +134,20 @@ __device__ __forceinline__ int compact(Pool& P, bool flag, int key) {
   }
   __syncthreads();
   return n;
+}
+
+// Deposit d in touchable T: summed in the block's LDS cache when T owns (or
+// can claim) its entry, else added to the device tally directly; the cache
+// is added to the tally when the block ends.
+__device__ __forceinline__ void deposit_t(Pool& P, const TransportArgs& a, int T, double d) {
+  const int h = T & (kDep - 1);
+  int owner = P.dkey[h];
+  if (owner == -1) {
+    owner = atomicCAS(&P.dkey[h], -1, T);
+    if (owner == -1) owner = T;
+  }
+  if (owner == T) atomicAdd(&P.dval[h], d);
+  else atomic_add_f64(a.edep_t + T, d);
 }
 
 template <bool LOG>
@@ -339,6 +356,10 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   }
   P.status[tid] = kEmpty;
   P.sub_pend[tid] = 0;
+  for (int i = tid; i < kDep; i += kPool) {
+    P.dkey[i] = -1;
+    P.dval[i] = 0.0;
+  }
   NavCount<COUNT> nc;
   bool queue_open = true;
   __syncthreads();
@@ -602,7 +623,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         int steps = zs >> 8;
         int zero = zs & 0xFF;
         if (E < a.ecut) {
-          atomic_add_f64(a.edep_t + T, E);
+          deposit_t(P, a, T, E);
           P.dep[s] += E;
           end_track<LOG>(P, a, s, GNAV_FATE_CUTOFF, steps);
         } else if (steps >= a.max_steps) {
@@ -704,7 +725,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             zero = (s_geo < kZeroLen) ? zero + 1 : 0;
             P.zero_steps[s] = (steps << 8) | zero;
             if (zero >= kZeroKill) {
-              atomic_add_f64(a.edep_t + T, E);
+              deposit_t(P, a, T, E);
               P.dep[s] += E;
               end_track<LOG>(P, a, s, GNAV_FATE_STUCK, steps);
             } else {
@@ -737,7 +758,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         const int steps = P.zero_steps[s] >> 8;
         Philox rs{(uint32_t)event, (uint32_t)P.key[s], (uint32_t)P.draw[s]};
         if (proc == kProcPE) {
-          atomic_add_f64(a.edep_t + T, E);
+          deposit_t(P, a, T, E);
           P.dep[s] += E;
           log_rec<LOG>(P, a, s, T, kLimPE, sl, E, 0.0);
           end_track<LOG>(P, a, s, GNAV_FATE_ABSORBED, steps);
@@ -758,7 +779,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           mu_index(G, E2, imu, w);
           P.imu_mat[s] = imu;  // cached mu invalid
           P.wmu[s] = w;
-          atomic_add_f64(a.edep_t + T, dep);
+          deposit_t(P, a, T, dep);
           P.dep[s] += dep;
           P.cnt_a[s] += 1u;
           log_rec<LOG>(P, a, s, T, kLimCompton, sl, dep, E2);
@@ -767,7 +788,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           P.status[s] = kStep;
         } else {
           double dep = E - 2.0 * kMe;
-          atomic_add_f64(a.edep_t + T, dep);
+          deposit_t(P, a, T, dep);
           P.dep[s] += dep;
           double u1 = rng_next(rs, a.seed_lo, a.seed_hi), u2 = rng_next(rs, a.seed_lo, a.seed_hi);
           double ct = 1.0 - 2.0 * u1;
@@ -811,7 +832,10 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     }
   }
 
-  // ---- flush counters -------------------------------------------------------
+  // ---- flush the deposit cache and the counters ---------------------------
+  __syncthreads();
+  for (int i = tid; i < kDep; i += kPool)
+    if (P.dkey[i] >= 0 && P.dval[i] != 0.0) atomic_add_f64(a.edep_t + P.dkey[i], P.dval[i]);
   if (COUNT) {
     unsigned vals[5] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes, nc.dist_in32};
     const int slots[5] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
