@@ -362,6 +362,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   }
   NavCount<COUNT> nc;
   bool queue_open = true;
+  bool int_deferred = false;  // block uniform: the interact pass was held last round
   __syncthreads();
 
   for (int round = 0;; round++) {
@@ -748,6 +749,11 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     // ---- interact: photoelectric, Compton, pair ------------------------------
     {
       int n = compact<3>(P, P.status[tid] == kInt, P.aux[tid]);
+      // With under a quarter of the slots due, hold them for one round so the
+      // next pass serves more of them at once; a held track only waits, so
+      // the results do not change.
+      if (n < kPool / 4 && !int_deferred) { int_deferred = true; n = 0; }
+      else int_deferred = false;
       if (tid < n) {
         const int s = P.list[tid];
         const int proc = P.aux[s];
