@@ -66,6 +66,17 @@ def _oracle_slice(args):
     return r["counters"]["steps"], time.perf_counter() - t0
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_sample, workers):
     """Oracle steps/s on host cores: one thread over the sample, then `workers`
     processes over equal slices of it (each a plain single-threaded oracle)."""
@@ -321,61 +332,17 @@ def batched_config(ctx, gnav, reps):
             "graph_same_counters": bool(same), "setup_s": setup_s}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1_000_000, help="photons per batch")
-    ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
-                    help="primaries of the same workload for the oracle timing (0: skip)")
-    ap.add_argument("--cpu-workers", type=int, default=0,
-                    help="oracle processes for the all-cores figure (0: min(16, cpus))")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--barrel-n", type=int, default=10_000_000,
-                    help="photons of the barrel variant comparison (0: skip)")
-    ap.add_argument("--train-photons", type=int, default=1_000_000,
-                    help="photons whose crossings train the learned order (0: skip)")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-events config")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(events are independent, see the sharding notes in the design document)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    # the CPU baseline runs first, in processes forked before any GPU use
-    cpu = None
-    if not args.no_cpu and args.cpu_sample > 0:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(args.cpu_sample, workers)
-        print(f"cpu baseline done: {cpu}", file=sys.stderr, flush=True)
-
+def headline(args, ctx, gnav, cpu, workers):
+    """The calorimeter throughput line with its roofline and CPU baseline."""
     import torch
     import workloads as W
-    from paper_1209_5235_amd import gnav
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     geoms, prim, _ = W.calorimeter(n=args.n, seed=0)
-    ctx = gnav.Context(0)
     gid, nt = ctx.upload_geometry(geoms[0])
     prim_d = gnav.primaries_to_device(prim, dev)
     tally = ctx.tally_create(prim.n_events)
     stream = torch.cuda.current_stream()
     kw = dict(seed=0, block=args.block, grid=args.grid)
-    if args.calibrate_copy:
-        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     for _ in range(args.warmup):
         tally.reset(stream)
@@ -450,6 +417,7 @@ def main():
         rate, dt, nsteps = cpu["single"]
         out["cpu_baseline"] = {
             "value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "cpu": f"{cpu_model()}, {os.cpu_count()} logical CPUs visible",
             "sample": f"first {args.cpu_sample} primaries of the same calorimeter workload "
                       f"({nsteps} steps in {dt:.1f} s, one thread, brute-force navigation)",
         }
@@ -460,12 +428,71 @@ def main():
                 "sample": f"the same {args.cpu_sample} primaries in {workers} single-threaded "
                           f"oracle processes ({nsteps} steps in {dt:.1f} s wall)"}
     tally.free()
-    if args.barrel_n > 0:
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000, help="photons per batch")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="primaries of the same workload for the oracle timing (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes for the all-cores figure (0: min(16, cpus))")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--barrel-n", type=int, default=10_000_000,
+                    help="photons of the barrel variant comparison (0: skip)")
+    ap.add_argument("--train-photons", type=int, default=1_000_000,
+                    help="photons whose crossings train the learned order (0: skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-events config")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--sections", default="headline,barrel,paper,batched",
+                    help="comma-separated parts to run (profiling runs pick one); without "
+                         "'headline' the line carries only the parts that ran")
+    args = ap.parse_args()
+    sections = set(args.sections.split(","))
+    unknown = sections - {"headline", "barrel", "paper", "batched"}
+    if unknown:
+        ap.error(f"unknown sections {sorted(unknown)}")
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(events are independent, see the sharding notes in the design document)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    # the CPU baseline runs first, in processes forked before any GPU use
+    cpu, workers = None, 0
+    if "headline" in sections and not args.no_cpu and args.cpu_sample > 0:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(args.cpu_sample, workers)
+        print(f"cpu baseline done: {cpu}", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1209_5235_amd import gnav
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = gnav.Context(0)
+    if args.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    out = headline(args, ctx, gnav, cpu, workers) if "headline" in sections else {}
+    if "barrel" in sections and args.barrel_n > 0:
         out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
         print("barrel variants done", file=sys.stderr, flush=True)
-    out["paper_free_path"] = paper_free_path(ctx, gnav, 5, 0 if args.no_cpu else 3000)
-    print("paper free-path config done", file=sys.stderr, flush=True)
-    if not args.no_batched:
+    if "paper" in sections:
+        out["paper_free_path"] = paper_free_path(ctx, gnav, 5, 0 if args.no_cpu else 3000)
+        print("paper free-path config done", file=sys.stderr, flush=True)
+    if "batched" in sections and not args.no_batched:
         out["batched"] = batched_config(ctx, gnav, 3)
         print("batched config done", file=sys.stderr, flush=True)
     ctx.close()

@@ -42,10 +42,13 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uin
 
 // C[m][n] = sum_k A(m, k) B(k, n); A(m, k) = A[m * sam + k * sak], B(k, n) =
 // B[k * sbk + n * sbn] (bf16 bits), C float with row stride ldc.  M, N, K are
-// multiples of 16.  One wave per 16x16 tile; grid covers all tiles.
-__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A,
+// multiples of 16.  One wave per 16x16 tile; grid.x covers all tiles.  With
+// grid.y > 1 the sum over k is split: slice y covers k in [y kc, (y+1) kc) and
+// writes its partial product to C + y cstride (kc a multiple of 16).
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, int kc, const uint16_t* __restrict__ A,
                                                    long sam, long sak, const uint16_t* __restrict__ B,
-                                                   long sbk, long sbn, float* __restrict__ C, long ldc) {
+                                                   long sbk, long sbn, float* __restrict__ C, long ldc,
+                                                   long cstride) {
   const int lane = threadIdx.x & 63;
   const long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int tn = N / 16;
@@ -53,8 +56,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const ui
   if (tile >= tiles) return;
   const int m0 = (int)(tile / tn) * 16, n0 = (int)(tile % tn) * 16;
   const int r = lane & 15, q = lane >> 4;
+  const int kb = (int)blockIdx.y * kc, ke = min(K, kb + kc);
+  C += (long)blockIdx.y * cstride;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     bf16x4 a, b;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
@@ -140,33 +145,71 @@ __global__ void k_relu_grad(long n, float* __restrict__ dh, const float* __restr
   }
 }
 
-// Column sums of a [B x N] float matrix (bias gradients): one thread per column.
-__global__ void k_colsum(int B, int N, const float* __restrict__ d, float* __restrict__ out) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// Sums over the batch are split into row slices: slice p (blockIdx.y) covers
+// rows [p R, min(B, (p+1) R)) and writes its partial sums to part + p n_out;
+// k_sum_parts then adds the slices in slice order, so every sum is taken in
+// the same order on every run.
+
+// Partial column sums of a [B x N] float matrix (bias gradients): 64 columns
+// per block, its four waves take every fourth row, then add in wave order.
+__global__ void __launch_bounds__(256) k_colsum_part(int B, int N, int R, const float* __restrict__ d,
+                                                     float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  const int b0 = blockIdx.y * R, b1 = min(B, b0 + R);
   float s = 0.f;
-  for (int b = 0; b < B; b++) s += d[(long)b * N + n];
-  out[n] = s;
+  if (n < N)
+    for (int b = b0 + w; b < b1; b += 4) s += d[(long)b * N + n];
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && n < N) part[(long)blockIdx.y * N + n] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// First-layer gradients: dW1x[h][k] = sum_b bf16(dA1)[b][h] bf16(x)[b][k];
-// dW1m[cls[b]][h] += dA1[b][h] (float).  One thread per (h, k) or per (b, h).
-__global__ void k_w1_grads(int B, int n_class, const float* __restrict__ da1, const uint16_t* __restrict__ da1b,
-                           const uint16_t* __restrict__ xb, const int* __restrict__ cls,
-                           float* __restrict__ dw1x, float* __restrict__ dw1m) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kNH * kNIn) {
-    int h = (int)(i / kNIn), k = (int)(i % kNIn);
-    float s = 0.f;
-    for (int b = 0; b < B; b++) s += bf2f(da1b[(long)b * kNH + h]) * bf2f(xb[b * 16 + k]);
-    dw1x[i] = s;
+// Partial first-layer input-weight gradients: dW1x[h][k] = sum_b
+// bf16(dA1)[b][h] bf16(x)[b][k] (float accumulation); thread h owns a row of
+// dW1x.  part holds [P][128 x 6].
+__global__ void __launch_bounds__(kNH) k_w1x_part(int B, int R, const uint16_t* __restrict__ da1b,
+                                                  const uint16_t* __restrict__ xb, float* __restrict__ part) {
+  const int h = threadIdx.x;
+  const int b0 = blockIdx.y * R, b1 = min(B, b0 + R);
+  float s[kNIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int b = b0; b < b1; b++) {
+    const float g = bf2f(da1b[(long)b * kNH + h]);
+#pragma unroll
+    for (int k = 0; k < kNIn; k++) s[k] += g * bf2f(xb[(long)b * 16 + k]);
   }
-  long j = i;
-  if (j < (long)B * kNH) {
-    int b = (int)(j / kNH), h = (int)(j % kNH);
+#pragma unroll
+  for (int k = 0; k < kNIn; k++) part[(long)blockIdx.y * (kNH * kNIn) + h * kNIn + k] = s[k];
+}
+
+// Partial class-row gradients of the first layer: dW1m[c][h] = sum over rows
+// b with cls[b] = c of dA1[b][h] (float).  Block (x, y) accumulates classes
+// [16 x, 16 x + 16) over row slice y in LDS; thread h owns column h, so each
+// sum runs in row order.  part holds [P][n_class x 128].
+__global__ void __launch_bounds__(kNH) k_w1m_part(int B, int R, int n_class, const float* __restrict__ da1,
+                                                  const int* __restrict__ cls, float* __restrict__ part) {
+  __shared__ float acc[16][kNH];
+  const int h = threadIdx.x;
+  const int c0 = blockIdx.x * 16;
+  const int b0 = blockIdx.y * R, b1 = min(B, b0 + R);
+#pragma unroll
+  for (int c = 0; c < 16; c++) acc[c][h] = 0.f;
+  for (int b = b0; b < b1; b++) {
     int c = cls[b];
-    c = c < 0 ? 0 : (c >= n_class ? n_class - 1 : c);
-    atomicAdd(&dw1m[(long)c * kNH + h], da1[j]);
+    c = (c < 0 ? 0 : (c >= n_class ? n_class - 1 : c)) - c0;
+    if (c >= 0 && c < 16) acc[c][h] += da1[(long)b * kNH + h];
+  }
+  const int nc = min(16, n_class - c0);
+  for (int c = 0; c < nc; c++) part[(long)blockIdx.y * n_class * kNH + (long)(c0 + c) * kNH + h] = acc[c][h];
+}
+
+// out[i] = sum over p = 0 .. P-1, in order, of part[p n + i].
+__global__ void k_sum_parts(long n, int P, const float* __restrict__ part, float* __restrict__ out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int p = 0; p < P; p++) s += part[(long)p * n + i];
+    out[i] = s;
   }
 }
 
@@ -206,6 +249,7 @@ struct gnav_mlp {
   // activations for max_batch samples
   float *a1 = nullptr, *a2 = nullptr, *z = nullptr, *dz = nullptr, *dh = nullptr, *loss = nullptr;
   uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *dzb = nullptr, *da2b = nullptr, *da1b = nullptr;
+  float* part = nullptr;  // partial sums of split reductions (kPartFloats)
   std::vector<void*> allocs;
   ~gnav_mlp() {
     for (void* q : allocs) (void)hipFree(q);
@@ -242,12 +286,56 @@ namespace {
 
 unsigned blocks_for(long n, int bs = 256) { return (unsigned)std::min<long>((n + bs - 1) / bs, 65535L * 8); }
 
-hipError_t gemm(int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
-                float* C, long ldc, hipStream_t st) {
-  long tiles = (long)(M / 16) * (N / 16);
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, M, N, K, A, sam, sak, B,
-                     sbk, sbn, C, ldc);
+constexpr long kPartFloats = 64L * kNH * kNH;  // 4 MB of partial sums
+constexpr int kMaxSlices = 64;
+constexpr int kMaxClass = 4096;
+// one slice of every split reduction fits: class rows of dW1m, GEMM outputs
+static_assert((long)kMaxClass * kNH <= kPartFloats && (long)kNH * kNH <= kPartFloats, "partial buffer");
+
+// Row slices for a sum over n rows into n_out outputs: slices of at least
+// `min_rows` rows, at most kMaxSlices of them, and within the partial buffer.
+int slices(long n, long n_out, int min_rows, int* rows) {
+  long P = (n + min_rows - 1) / min_rows;
+  P = std::min<long>(P, std::min<long>(kMaxSlices, std::max<long>(1, kPartFloats / n_out)));
+  P = std::max<long>(P, 1);
+  long R = (n + P - 1) / P;
+  *rows = (int)R;
+  return (int)((n + R - 1) / R);
+}
+
+hipError_t sum_parts(long n, int P, const float* part, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(n)), dim3(256), 0, st, n, P, part, out);
   return hipGetLastError();
+}
+
+// C = A B (see k_gemm_bf16).  Products with few output tiles and a long sum
+// (the weight gradients, k = batch) split the sum into slices of at least 128
+// so that enough waves run, then add the slices in order.
+hipError_t gemm(gnav_mlp* q, int M, int N, int K, const uint16_t* A, long sam, long sak, const uint16_t* B,
+                long sbk, long sbn, float* C, long ldc, hipStream_t st) {
+  long tiles = (long)(M / 16) * (N / 16);
+  unsigned gx = (unsigned)((tiles + 3) / 4);
+  if (tiles < 512 && K >= 256 && ldc == N) {
+    int kc = 0;
+    int P = slices(K / 16, (long)M * N, 8, &kc);
+    kc *= 16;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(gx, (unsigned)P), dim3(256), 0, st, M, N, K, kc, A, sam, sak, B, sbk,
+                       sbn, q->part, (long)N, (long)M * N);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_parts((long)M * N, P, q->part, C, st);
+  }
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(gx), dim3(256), 0, st, M, N, K, K, A, sam, sak, B, sbk, sbn, C, ldc, 0L);
+  return hipGetLastError();
+}
+
+// Bias gradient: out[n] = sum over the Bn rows of d[b][n].
+hipError_t colsum(gnav_mlp* q, int Bn, int N, const float* d, float* out, hipStream_t st) {
+  int R = 0;
+  int P = slices(Bn, N, 128, &R);
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((N + 63) / 64), (unsigned)P), dim3(256), 0, st, Bn, N, R, d,
+                     q->part);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : sum_parts(N, P, q->part, out, st);
 }
 
 // Forward and backward for a batch; gradients land in mlp->g.
@@ -262,32 +350,42 @@ hipError_t run_grad(gnav_mlp* q, int Bn, const float* x, const int* cls, const i
   // forward
   hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, Bn, x, cls, q->n_class, w1x,
                      w1m, q->p + q->o_b1, q->xb, q->a1, q->h1b);
-  if ((e = gemm(Bn, kNH, kNH, q->h1b, kNH, 1, w2, 1, kNH, q->a2, kNH, st)) != hipSuccess) return e;
+  if ((e = gemm(q, Bn, kNH, kNH, q->h1b, kNH, 1, w2, 1, kNH, q->a2, kNH, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bias_relu, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, kNH, q->a2,
                      q->p + q->o_b2, q->h2b);
-  if ((e = gemm(Bn, kNOut, kNH, q->h2b, kNH, 1, w3, 1, kNH, q->z, kNOut, st)) != hipSuccess) return e;
+  if ((e = gemm(q, Bn, kNOut, kNH, q->h2b, kNH, 1, w3, 1, kNH, q->z, kNOut, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_softmax_ce, dim3((unsigned)((Bn + 3) / 4)), dim3(256), 0, st, Bn, q->z, q->p + q->o_b3,
                      label, q->dz, q->dzb, q->loss);
   // backward
   float* g = q->g;
   // dW3 = dZb^T H2b : [64 x B] [B x 128]
-  if ((e = gemm(kNOut, kNH, Bn, q->dzb, 1, kNOut, q->h2b, kNH, 1, g + q->o_w3, kNH, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNOut), 0, st, Bn, kNOut, q->dz, g + q->o_b3);
+  if ((e = gemm(q, kNOut, kNH, Bn, q->dzb, 1, kNOut, q->h2b, kNH, 1, g + q->o_w3, kNH, st)) != hipSuccess)
+    return e;
+  if ((e = colsum(q, Bn, kNOut, q->dz, g + q->o_b3, st)) != hipSuccess) return e;
   // dH2 = dZb W3 : [B x 64] [64 x 128]
-  if ((e = gemm(Bn, kNH, kNOut, q->dzb, kNOut, 1, w3, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
+  if ((e = gemm(q, Bn, kNH, kNOut, q->dzb, kNOut, 1, w3, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_relu_grad, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, q->dh, q->a2,
                      q->da2b);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNH), 0, st, Bn, kNH, q->dh, g + q->o_b2);
+  if ((e = colsum(q, Bn, kNH, q->dh, g + q->o_b2, st)) != hipSuccess) return e;
   // dW2 = dA2b^T H1b : [128 x B] [B x 128]
-  if ((e = gemm(kNH, kNH, Bn, q->da2b, 1, kNH, q->h1b, kNH, 1, g + q->o_w2, kNH, st)) != hipSuccess) return e;
+  if ((e = gemm(q, kNH, kNH, Bn, q->da2b, 1, kNH, q->h1b, kNH, 1, g + q->o_w2, kNH, st)) != hipSuccess) return e;
   // dH1 = dA2b W2 : [B x 128] [128 x 128]
-  if ((e = gemm(Bn, kNH, kNH, q->da2b, kNH, 1, w2, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
+  if ((e = gemm(q, Bn, kNH, kNH, q->da2b, kNH, 1, w2, kNH, 1, q->dh, kNH, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_relu_grad, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, q->dh, q->a1,
                      q->da1b);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kNH), 0, st, Bn, kNH, q->dh, g + q->o_b1);
-  hipLaunchKernelGGL(k_w1_grads, dim3(blocks_for(std::max<long>((long)Bn * kNH, kNH * kNIn))), dim3(256), 0, st,
-                     Bn, q->n_class, q->dh, q->da1b, q->xb, cls, g + q->o_w1x, g + q->o_w1m);
-  return hipGetLastError();
+  if ((e = colsum(q, Bn, kNH, q->dh, g + q->o_b1, st)) != hipSuccess) return e;
+  // first layer: dW1x from the bf16 copies, dW1m per class row from dA1
+  int R = 0;
+  int P = slices(Bn, (long)kNH * kNIn, 128, &R);
+  hipLaunchKernelGGL(k_w1x_part, dim3(1, (unsigned)P), dim3(kNH), 0, st, Bn, R, q->da1b, q->xb, q->part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = sum_parts((long)kNH * kNIn, P, q->part, g + q->o_w1x, st)) != hipSuccess) return e;
+  const long n_m = (long)q->n_class * kNH;
+  P = slices(Bn, n_m, 128, &R);
+  hipLaunchKernelGGL(k_w1m_part, dim3((unsigned)((q->n_class + 15) / 16), (unsigned)P), dim3(kNH), 0, st, Bn, R,
+                     q->n_class, q->dh, cls, q->part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return sum_parts(n_m, P, q->part, g + q->o_w1m, st);
 }
 
 }  // namespace
@@ -296,7 +394,7 @@ extern "C" {
 
 gnav_status gnav_mlp_create(gnav_ctx* ctx, int32_t n_class, int32_t max_batch, const float* params,
                             gnav_mlp** out) {
-  if (!ctx || !out || !params || n_class <= 0 || n_class > 4096 || max_batch <= 0 || max_batch % 16 != 0 ||
+  if (!ctx || !out || !params || n_class <= 0 || n_class > kMaxClass || max_batch <= 0 || max_batch % 16 != 0 ||
       max_batch > (1 << 22))
     return GNAV_EINVAL;
   *out = nullptr;
@@ -323,7 +421,7 @@ gnav_status gnav_mlp_create(gnav_ctx* ctx, int32_t n_class, int32_t max_batch, c
       (e = q->alloc(&q->loss, 2)) != hipSuccess || (e = q->alloc(&q->xb, Bn * 16)) != hipSuccess ||
       (e = q->alloc(&q->h1b, Bn * kNH)) != hipSuccess || (e = q->alloc(&q->h2b, Bn * kNH)) != hipSuccess ||
       (e = q->alloc(&q->dzb, Bn * kNOut)) != hipSuccess || (e = q->alloc(&q->da2b, Bn * kNH)) != hipSuccess ||
-      (e = q->alloc(&q->da1b, Bn * kNH)) != hipSuccess) {
+      (e = q->alloc(&q->da1b, Bn * kNH)) != hipSuccess || (e = q->alloc(&q->part, kPartFloats)) != hipSuccess) {
     delete q;
     return e == hipErrorOutOfMemory ? GNAV_ENOMEM : GNAV_EHIP;
   }
@@ -374,10 +472,11 @@ gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* q, int64_t batch, const fl
   int Bn = (int)batch;
   hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, Bn, x_dev, cls_dev, q->n_class,
                      q->pb + q->o_w1x, q->pb + q->o_w1m, q->p + q->o_b1, q->xb, q->a1, q->h1b);
-  if (gemm(Bn, kNH, kNH, q->h1b, kNH, 1, q->pb + q->o_w2, 1, kNH, q->a2, kNH, st) != hipSuccess) return GNAV_EHIP;
+  if (gemm(q, Bn, kNH, kNH, q->h1b, kNH, 1, q->pb + q->o_w2, 1, kNH, q->a2, kNH, st) != hipSuccess)
+    return GNAV_EHIP;
   hipLaunchKernelGGL(k_bias_relu, dim3(blocks_for((long)Bn * kNH)), dim3(256), 0, st, (long)Bn * kNH, kNH, q->a2,
                      q->p + q->o_b2, q->h2b);
-  if (gemm(Bn, kNOut, kNH, q->h2b, kNH, 1, q->pb + q->o_w3, 1, kNH, logits_dev, kNOut, st) != hipSuccess)
+  if (gemm(q, Bn, kNOut, kNH, q->h2b, kNH, 1, q->pb + q->o_w3, 1, kNH, logits_dev, kNOut, st) != hipSuccess)
     return GNAV_EHIP;
   hipLaunchKernelGGL(k_bias_relu_noact, dim3(blocks_for((long)Bn * kNOut)), dim3(256), 0, st, (long)Bn * kNOut,
                      kNOut, logits_dev, q->p + q->o_b3);
