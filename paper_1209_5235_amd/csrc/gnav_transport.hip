@@ -208,8 +208,8 @@ __device__ __forceinline__ uint16_t lf2bf(float f) {
 __device__ __forceinline__ float lbf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 struct LearnScratch {
-  uint16_t h[kWaves][16][128];  // per wave: activations (bf16), then the logits as float [16][64]
-  int cls[kWaves][16];
+  uint16_t xf[kPool][6];  // bf16 features of the listed steps (mother-frame point, direction)
+  uint16_t cls[kPool];    // their ordering classes in, the predicted candidate positions out
 };
 
 // Four consecutive bf16 values as one MFMA operand (8-byte aligned loads).
@@ -217,125 +217,99 @@ __device__ __forceinline__ lbf16x4 load_bf16x4(const uint16_t* p) {
   return *reinterpret_cast<const lbf16x4*>(p);
 }
 
-// The block's waves score the n listed steps, 16 per MFMA row tile (wave w
-// takes tiles w, w + 4, ...): layer 1 is [16 x 16(6)] x [16 x 128] plus the
-// mother-class row of W1, layers 2 and 3 are [16 x 128] x [128 x 128] and
-// x [128 x 64].  Each 16 x 16 output tile is accumulated over K in FP32 and
-// written back at once; a layer's input row is read into registers before
-// any output is written, so one LDS buffer per wave serves every layer.
-// MFMA operand layout (16x16x16 bf16): lane l holds A row l % 16 and B
-// column l % 16 at k = 4 (l / 16) + 0..3; the result holds column l % 16,
-// rows 4 (l / 16) + 0..3.
-__device__ __attribute__((noinline)) void learned_predict(const TransportArgs& a, Pool& P, LearnScratch& S,
-                                                          int n) {
-  const DevGeom& G = a.G;
-  const MlpView& M = a.mlp;
+// Scores the n listed steps whose features are in S.xf / S.cls and writes the
+// highest-scoring candidate position over each step's class in S.cls.
+//
+// Each wave takes 16 steps at a time and computes every layer transposed,
+// H^T = W X^T: the weights are the A operand (row = output unit l % 16,
+// k = 4 (l / 16) + 0..3) and the activations the B operand (column = step
+// l % 16, same k).  The accumulator of output tile t then holds, per lane,
+// units 16 t + 4 (l / 16) + 0..3 of step l % 16, which is exactly the B
+// operand of the next layer's k-slice t: activations stay in registers.
+//
+// Kept out of line (the MFMA operands would otherwise raise the register
+// count of the whole loop); it takes the weights by value so that the
+// kernel's argument block is never addressed from the call.
+__device__ __attribute__((noinline)) void learned_predict(const MlpView M, LearnScratch& S, int n) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
-  uint16_t (*h)[128] = S.h[w];
-  float (*lg)[64] = reinterpret_cast<float (*)[64]>(&S.h[w][0][0]);
   for (int row0 = 16 * w; row0 < n; row0 += 16 * kWaves) {
-    // features of row r: point in the mother frame over the grid half size, direction
     const int li = row0 + r;
     const bool valid = li < n;
-    float f[6] = {0, 0, 0, 0, 0, 0};
-    int cls = 0;
-    if (valid) {
-      const int s = P.list[li];
-      const int lvk = P.lvk[s];
-      const LRec& L = G.lv[lvk >> 1];
-      V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
-      V3 pl, vl;
-      touchable_frame(G, P.T[s], lvk & 1, x, v, pl, vl);
-      const double pc[3] = {pl.x, pl.y, pl.z};
-#pragma unroll
-      for (int ax = 0; ax < 3; ax++) {
-        double half = 0.5 * L.n[ax] * L.vw[ax];
-        f[ax] = (float)((pc[ax] - (L.vlo[ax] + half)) / half);
-      }
-      f[3] = (float)vl.x;
-      f[4] = (float)vl.y;
-      f[5] = (float)vl.z;
-      cls = L.lclass;
-      cls = cls < 0 ? 0 : (cls >= M.n_class ? M.n_class - 1 : cls);
-    }
-    if (q == 0) S.cls[w][r] = cls;
-    lbf16x4 xa;
+    const int cls = valid ? S.cls[li] : 0;
+    // layer 1: K = 6 inputs padded to 16; + W1m[class] + b1, ReLU
+    lbf16x4 x;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-      int k = 4 * q + j;
-      xa[j] = (short)(k < 6 ? lf2bf(f[k]) : 0);
+      const int k = 4 * q + j;
+      x[j] = (short)(k < 6 && valid ? S.xf[li][k] : 0);
     }
-    __builtin_amdgcn_wave_barrier();
-    // layer 1 (K padded from 6 to 16) + b1 + W1m[class], ReLU
-    for (int ct = 0; ct < 8; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 wb;
+    lbf16x4 h1[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+      lbf16x4 wa;
 #pragma unroll
       for (int j = 0; j < 4; j++) {
-        int k = 4 * q + j;
-        wb[j] = (short)(k < 6 ? M.w1x[nn * 6 + k] : 0);
+        const int k = 4 * q + j;
+        wa[j] = (short)(k < 6 ? M.w1x[(16 * t + r) * 6 + k] : 0);
       }
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, wb, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, x, acc, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; j++) {
-        int row = 4 * q + j;
-        float v = acc[j] + lbf2f(M.w1m[(long)S.cls[w][row] * 128 + nn]) + M.b1[nn];
-        h[row][nn] = lf2bf(v > 0.f ? v : 0.f);
+        const int u = 16 * t + 4 * q + j;
+        const float v = acc[j] + lbf2f(M.w1m[(long)cls * 128 + u]) + M.b1[u];
+        h1[t][j] = (short)lf2bf(v > 0.f ? v : 0.f);
       }
     }
-    __builtin_amdgcn_wave_barrier();
-    // layer 2 + b2, ReLU (written over the input rows)
-    // (the row's A operands stay in registers across the output tiles; each
-    // tile's eight B operands are loaded together before its MFMA chain)
-    lbf16x4 a1[8];
+    // layer 2 + b2, ReLU (each tile's eight A operands loaded before its MFMA chain)
+    lbf16x4 h2[8];
 #pragma unroll
-    for (int kt = 0; kt < 8; kt++) a1[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
-    for (int ct = 0; ct < 8; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 b[8];
+    for (int t = 0; t < 8; t++) {
+      lbf16x4 wa[8];
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w2 + nn * 128 + 16 * kt + 4 * q);
+      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w2 + (16 * t + r) * 128 + 16 * kt + 4 * q);
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[kt], b[kt], acc, 0, 0, 0);
+      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h1[kt], acc, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; j++) {
-        float v = acc[j] + M.b2[nn];
-        h[4 * q + j][nn] = lf2bf(v > 0.f ? v : 0.f);
+        const float v = acc[j] + M.b2[16 * t + 4 * q + j];
+        h2[t][j] = (short)lf2bf(v > 0.f ? v : 0.f);
       }
     }
-    __builtin_amdgcn_wave_barrier();
-    // layer 3 + b3 -> logits (float, over the same buffer)
-    lbf16x4 a2[8];
+    // layer 3 + b3: 64 logits; this lane holds candidates 16 t + 4 q + j
+    float best_v = 0.f;
+    int best_c = -1;
 #pragma unroll
-    for (int kt = 0; kt < 8; kt++) a2[kt] = load_bf16x4(&h[r][16 * kt + 4 * q]);
-    for (int ct = 0; ct < 4; ct++) {
-      const int nn = 16 * ct + r;
-      lbf16x4 b[8];
+    for (int t = 0; t < 4; t++) {
+      lbf16x4 wa[8];
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) b[kt] = load_bf16x4(M.w3 + nn * 128 + 16 * kt + 4 * q);
+      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w3 + (16 * t + r) * 128 + 16 * kt + 4 * q);
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], b[kt], acc, 0, 0, 0);
+      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h2[kt], acc, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; j++) lg[4 * q + j][nn] = acc[j] + M.b3[nn];
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (q == 0 && valid) {
-      int best = 0;
-      float bv = lg[r][0];
-      for (int c = 1; c < 64; c++) {
-        float v = lg[r][c];
-        if (v > bv) {
-          bv = v;
-          best = c;
+      for (int j = 0; j < 4; j++) {
+        const int c = 16 * t + 4 * q + j;
+        const float v = acc[j] + M.b3[c];
+        if (best_c < 0 || v > best_v) {  // candidates arrive in increasing order
+          best_v = v;
+          best_c = c;
         }
       }
-      P.pred[P.list[li]] = best;
     }
-    __builtin_amdgcn_wave_barrier();
+    // highest logit over the four lanes of the step; the lowest position on ties
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      const float ov = __shfl_xor(best_v, off);
+      const int oc = __shfl_xor(best_c, off);
+      if (ov > best_v || (ov == best_v && oc < best_c)) {
+        best_v = ov;
+        best_c = oc;
+      }
+    }
+    if (q == 0 && valid) S.cls[li] = (uint16_t)best_c;
   }
 }
 
@@ -593,7 +567,33 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
       }
       P.pred[tid] = -1;
       int n = compact<1>(P, elig, 0);
-      if (n > 0) learned_predict(a, P, S, n);
+      if (n > 0) {
+        // features of listed step i: the point in the mother frame over the
+        // voxel grid's half size (centred on the grid), and the direction
+        if (tid < n) {
+          const int s = P.list[tid];
+          const int lvk = P.lvk[s];
+          const LRec& L = G.lv[lvk >> 1];
+          V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
+          V3 pl, vl;
+          touchable_frame(G, P.T[s], lvk & 1, x, v, pl, vl);
+          const double pc[3] = {pl.x, pl.y, pl.z};
+#pragma unroll
+          for (int ax = 0; ax < 3; ax++) {
+            double half = 0.5 * L.n[ax] * L.vw[ax];
+            S.xf[tid][ax] = lf2bf((float)((pc[ax] - (L.vlo[ax] + half)) / half));
+          }
+          S.xf[tid][3] = lf2bf((float)vl.x);
+          S.xf[tid][4] = lf2bf((float)vl.y);
+          S.xf[tid][5] = lf2bf((float)vl.z);
+          const int c = L.lclass;
+          S.cls[tid] = (uint16_t)(c < 0 ? 0 : (c >= a.mlp.n_class ? a.mlp.n_class - 1 : c));
+        }
+        __syncthreads();
+        learned_predict(a.mlp, S, n);
+        __syncthreads();
+        if (tid < n) P.pred[P.list[tid]] = S.cls[tid];
+      }
       __syncthreads();
     }
 
