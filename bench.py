@@ -54,12 +54,14 @@ def algorithmic_flops(c):
 
 
 def _oracle_slice(args):
-    """Oracle transport of primaries [lo, hi) of the calorimeter workload (worker)."""
-    n_sample, lo, hi = args
+    """Oracle transport of primaries [lo, hi) of the calorimeter workload (worker);
+    `voxels` selects the oracle's cell-grid search instead of brute force."""
+    n_sample, lo, hi, voxels = args
     import oracle
     import workloads as W
     geoms, prim, _ = W.calorimeter(n=n_sample, seed=0)
     og = oracle.Geometry(geoms[0])
+    og.set_voxels(voxels)
     sub = prim.subset(np.arange(lo, hi))
     t0 = time.perf_counter()
     r = og.transport(sub, seed=0, n_events=prim.n_events)
@@ -79,18 +81,23 @@ def cpu_model():
 
 def cpu_baseline(n_sample, workers):
     """Oracle steps/s on host cores: one thread over the sample, then `workers`
-    processes over equal slices of it (each a plain single-threaded oracle)."""
-    steps1, dt1 = _oracle_slice((n_sample, 0, n_sample))
-    out = {"single": (steps1 / dt1, dt1, steps1)}
-    if workers > 1:
-        import multiprocessing as mp
-        cuts = np.linspace(0, n_sample, workers + 1).astype(int)
-        t0 = time.perf_counter()
-        with mp.get_context("fork").Pool(workers) as pool:
-            res = pool.map(_oracle_slice, [(n_sample, int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])])
-        dt = time.perf_counter() - t0
-        steps = sum(r[0] for r in res)
-        out["all"] = (steps / dt, dt, steps)
+    processes over equal slices of it (each a plain single-threaded oracle);
+    both with brute-force navigation and with the oracle's voxel mode."""
+    out = {}
+    for voxels in (False, True):
+        tag = "voxel_" if voxels else ""
+        steps1, dt1 = _oracle_slice((n_sample, 0, n_sample, voxels))
+        out[tag + "single"] = (steps1 / dt1, dt1, steps1)
+        if workers > 1:
+            import multiprocessing as mp
+            cuts = np.linspace(0, n_sample, workers + 1).astype(int)
+            t0 = time.perf_counter()
+            with mp.get_context("fork").Pool(workers) as pool:
+                res = pool.map(_oracle_slice, [(n_sample, int(a), int(b), voxels)
+                                               for a, b in zip(cuts[:-1], cuts[1:])])
+            dt = time.perf_counter() - t0
+            steps = sum(r[0] for r in res)
+            out[tag + "all"] = (steps / dt, dt, steps)
     return out
 
 
@@ -427,6 +434,18 @@ def headline(args, ctx, gnav, cpu, workers):
                 "value": rate, "unit": "steps/s", "cores": workers, "kind": "oracle",
                 "sample": f"the same {args.cpu_sample} primaries in {workers} single-threaded "
                           f"oracle processes ({nsteps} steps in {dt:.1f} s wall)"}
+        # the oracle's own cell-grid search: a faster CPU method, same answers
+        rate, dt, nsteps = cpu["voxel_single"]
+        out["cpu_baseline_voxel"] = {
+            "value": rate, "unit": "steps/s", "cores": 1, "kind": "oracle, voxel mode",
+            "sample": f"the same {args.cpu_sample} primaries, one thread, cell-grid navigation "
+                      f"({nsteps} steps in {dt:.1f} s)"}
+        if "voxel_all" in cpu:
+            rate, dt, nsteps = cpu["voxel_all"]
+            out["cpu_baseline_voxel_all_cores"] = {
+                "value": rate, "unit": "steps/s", "cores": workers, "kind": "oracle, voxel mode",
+                "sample": f"the same {args.cpu_sample} primaries in {workers} single-threaded "
+                          f"processes, cell-grid navigation ({nsteps} steps in {dt:.1f} s wall)"}
     tally.free()
     return out
 

@@ -65,6 +65,8 @@ def lib():
         L.og_n_touchables.restype = C.c_int
         L.og_touchables.argtypes = [P, i32p, i32p, i32p, i32p]
         L.og_set_paper_mode.argtypes = [P, C.c_int, C.c_double]
+        L.og_set_voxels.argtypes = [P, C.c_int]
+        L.og_set_voxels.restype = C.c_int
         L.og_mu.argtypes = [P, C.c_int, C.c_int, f64p, f64p]
         L.og_table.argtypes = [P, f64p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.og_locate.argtypes = [P, C.c_int, f64p, P, i32p]
@@ -183,6 +185,12 @@ class Geometry:
 
     def set_paper_mode(self, on=True, mu_mass=0.06146):
         lib().og_set_paper_mode(self.h, int(on), float(mu_mass))
+
+    def set_voxels(self, on=True):
+        """Search daughters through per-mother cell grids (the oracle's faster
+        CPU method; the answers equal the brute-force ones)."""
+        if lib().og_set_voxels(self.h, int(on)) != 0:
+            raise MemoryError("oracle voxel grids too large")
 
     def mu(self, mat, E):
         E = _c(np.atleast_1d(E), np.float64)

@@ -14,7 +14,9 @@
  *     T = t_{j-1} + (Y - S_{j-1}) / mu_j;
  *   - the two navigation queries of Sec. 3.2 (which volumes contain a point;
  *     where the ray next crosses a boundary), answered by brute force over
- *     every daughter of the current mother: no voxels, no caching;
+ *     every daughter of the current mother: no voxels, no caching (an
+ *     optional cell-grid mode, og_set_voxels, gives the same answers faster
+ *     and serves only as a CPU timing baseline);
  *   - a gamma transport loop that repeats Alg. 1 after every interaction
  *     (photoelectric, Klein-Nishina Compton, Bethe-Heitler pair), with energy
  *     tallies per touchable and per event.
@@ -606,6 +608,9 @@ typedef struct {
   /* mode: 0 = physics tables, 1 = paper mode mu = rho * mu_mass (single process) */
   int paper_mode;
   double paper_mu_mass; /* cm2/g */
+  /* voxel mode (faster CPU search, same answers): per-LV cell grids */
+  struct og_vgrid* vgrid; /* [n_lv] or NULL */
+  int use_voxels;
 } og_geom;
 
 static void* xcalloc(size_t n, size_t sz) {
@@ -670,6 +675,7 @@ static void mu_lookup(const og_geom* g, int mat, double E, double mu[3]) {
 }
 
 void og_destroy(og_geom* g);
+static void og_free_voxels(og_geom* g);
 
 /* Build the oracle's geometry from the flat description.  Touchables are
  * numbered breadth first from the world (0): the children of touchable T
@@ -788,6 +794,7 @@ void og_destroy(og_geom* g) {
   free(g->t_lv);
   free(g->t_child_base);
   free(g->t_depth);
+  og_free_voxels(g);
   free(g);
 }
 
@@ -845,6 +852,214 @@ static void frame_of(const og_geom* g, int T, const double* pg, const double* vg
 
 static const og_solid* lv_solid_of(const og_geom* g, int lv) { return &g->solids[g->lv_solid[lv]]; }
 
+/* ------------------------------------------------------------------------ */
+/* Voxel mode: the oracle's own faster search, for CPU timing.               */
+/*                                                                           */
+/* A uniform grid over each mother's bounding box lists, per cell and in     */
+/* ascending slot order, the daughters whose bounding box grown by           */
+/* kVoxMargin meets the cell (tubs and cons placed along the mother's z axis */
+/* also need the cell to meet their radial range, orbs their sphere).  Any   */
+/* daughter that holds a point, or whose surface band the ray reaches while  */
+/* still inside the cells visited so far, is listed in those cells, so       */
+/* locate and ComputeStep give exactly the brute-force answers.  The GPU     */
+/* library's voxels are built independently and differently.                 */
+/* ------------------------------------------------------------------------ */
+
+static const double kVoxMargin = 1e-6;
+
+typedef struct og_vgrid {
+  int n[3];
+  double lo[3], w[3];
+  int* off; /* [cells + 1], NULL: no grid (brute force) */
+  int* dau;
+} og_vgrid;
+
+/* Bounding box of a solid in its own frame.  A phi segment of a tubs or
+ * cons is bounded by its corner points and by the outer radius at the axis
+ * directions the segment spans. */
+static void solid_box(const og_solid* s, double lo[3], double hi[3]) {
+  const double* p = s->par;
+  if (s->type == OG_BOX || s->type == OG_ORB) {
+    for (int i = 0; i < 3; i++) {
+      double h = s->type == OG_BOX ? p[i] : p[0];
+      lo[i] = -h;
+      hi[i] = h;
+    }
+    return;
+  }
+  double rin = s->type == OG_TUBS ? p[0] : min2(p[0], p[2]);
+  double rout = s->type == OG_TUBS ? p[1] : max2(p[1], p[3]);
+  double dz = s->type == OG_TUBS ? p[2] : p[4];
+  double sphi = s->type == OG_TUBS ? p[3] : p[5];
+  double dphi = s->type == OG_TUBS ? p[4] : p[6];
+  lo[2] = -dz;
+  hi[2] = dz;
+  if (!s->has_phi) {
+    lo[0] = lo[1] = -rout;
+    hi[0] = hi[1] = rout;
+    return;
+  }
+  lo[0] = lo[1] = kInf;
+  hi[0] = hi[1] = -kInf;
+  const double ang[2] = {sphi, sphi + dphi};
+  for (int a = 0; a < 2; a++)
+    for (int r = 0; r < 2; r++) {
+      double rr = r ? rout : rin, x = rr * cos(ang[a]), y = rr * sin(ang[a]);
+      lo[0] = min2(lo[0], x);
+      hi[0] = max2(hi[0], x);
+      lo[1] = min2(lo[1], y);
+      hi[1] = max2(hi[1], y);
+    }
+  for (int k = -8; k <= 8; k++) {
+    double a = k * (M_PI / 2);
+    if (a < sphi || a > sphi + dphi) continue;
+    int q = ((k % 4) + 4) % 4; /* +x, +y, -x, -y */
+    if (q == 0) hi[0] = rout;
+    if (q == 1) hi[1] = rout;
+    if (q == 2) lo[0] = -rout;
+    if (q == 3) lo[1] = -rout;
+  }
+}
+
+/* Does daughter pv (of solid s) possibly meet the cell [c0, c1] (mother frame)? */
+static int dau_meets_cell(const og_geom* g, int pv, const double c0[3], const double c1[3]) {
+  const og_solid* s = lv_solid_of(g, g->pv_lv[pv]);
+  const double* R = g->pv_rot + 9 * pv;
+  const double* t = g->pv_trans + 3 * pv;
+  const double m = kVoxMargin;
+  if (s->type == OG_ORB) {
+    double d2 = 0;
+    for (int i = 0; i < 3; i++) {
+      double d = max2(max2(c0[i] - t[i], t[i] - c1[i]), 0.0);
+      d2 += d * d;
+    }
+    return sqrt(d2) <= s->par[0] + m;
+  }
+  if ((s->type == OG_TUBS || s->type == OG_CONS) && fabs(R[8]) == 1.0) {
+    /* axis parallel to the mother's z: compare the cell's xy distances
+     * from the axis with the solid's radial range */
+    double dx = max2(max2(c0[0] - t[0], t[0] - c1[0]), 0.0);
+    double dy = max2(max2(c0[1] - t[1], t[1] - c1[1]), 0.0);
+    double dmin = sqrt(dx * dx + dy * dy);
+    double fx = max2(fabs(c0[0] - t[0]), fabs(c1[0] - t[0]));
+    double fy = max2(fabs(c0[1] - t[1]), fabs(c1[1] - t[1]));
+    double dmax = sqrt(fx * fx + fy * fy);
+    double rin = s->type == OG_TUBS ? s->par[0] : min2(s->par[0], s->par[2]);
+    double rout = s->type == OG_TUBS ? s->par[1] : max2(s->par[1], s->par[3]);
+    if (dmin > rout + m || dmax < rin - m) return 0;
+  }
+  return 1;
+}
+
+static void og_free_voxels(og_geom* g) {
+  if (!g->vgrid) return;
+  for (int l = 0; l < g->n_lv; l++) {
+    free(g->vgrid[l].off);
+    free(g->vgrid[l].dau);
+  }
+  free(g->vgrid);
+  g->vgrid = NULL;
+}
+
+/* Build the grid of one mother LV with nd >= 4 daughters: about 64 cells per
+ * daughter (at most 2^20), cubic cells where the extents allow. */
+static int build_grid(og_geom* g, int lv, og_vgrid* G) {
+  int nd = g->lv_dau_cnt[lv];
+  double mlo[3], mhi[3];
+  solid_box(lv_solid_of(g, lv), mlo, mhi);
+  double vol = (mhi[0] - mlo[0]) * (mhi[1] - mlo[1]) * (mhi[2] - mlo[2]);
+  double target = min2(64.0 * nd, 1048576.0);
+  double edge = cbrt(vol / target);
+  long cells = 1;
+  for (int i = 0; i < 3; i++) {
+    int n = (int)ceil((mhi[i] - mlo[i]) / edge);
+    n = n < 1 ? 1 : (n > 1024 ? 1024 : n);
+    G->n[i] = n;
+    G->lo[i] = mlo[i];
+    G->w[i] = (mhi[i] - mlo[i]) / n;
+    cells *= n;
+  }
+  if (cells > 4 * 1048576L) return -1;
+  int* cnt = (int*)xcalloc((size_t)cells + 1, sizeof(int));
+  /* two passes over the daughters: count, then fill in slot order */
+  long total = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    for (int k = 0; k < nd; k++) {
+      int pv = g->lv_dau_off[lv] + k;
+      double blo[3], bhi[3], cl[3], hd[3], lo[3], hi[3];
+      solid_box(lv_solid_of(g, g->pv_lv[pv]), blo, bhi);
+      for (int i = 0; i < 3; i++) {
+        cl[i] = 0.5 * (blo[i] + bhi[i]);
+        hd[i] = 0.5 * (bhi[i] - blo[i]);
+      }
+      const double* R = g->pv_rot + 9 * pv;
+      const double* t = g->pv_trans + 3 * pv;
+      int i0[3], i1[3];
+      for (int i = 0; i < 3; i++) {
+        /* mother-frame box of the placed local box: centre R cl + t, half |R| hd */
+        double cm = R[3 * i] * cl[0] + R[3 * i + 1] * cl[1] + R[3 * i + 2] * cl[2] + t[i];
+        double e = fabs(R[3 * i]) * hd[0] + fabs(R[3 * i + 1]) * hd[1] + fabs(R[3 * i + 2]) * hd[2];
+        lo[i] = cm - e - kVoxMargin - 1e-9 * fabs(cm);
+        hi[i] = cm + e + kVoxMargin + 1e-9 * fabs(cm);
+        double a = floor((lo[i] - G->lo[i]) / G->w[i]), b = floor((hi[i] - G->lo[i]) / G->w[i]);
+        i0[i] = a < 0 ? 0 : (a > G->n[i] - 1 ? G->n[i] - 1 : (int)a);
+        i1[i] = b < 0 ? 0 : (b > G->n[i] - 1 ? G->n[i] - 1 : (int)b);
+      }
+      for (int ix = i0[0]; ix <= i1[0]; ix++)
+        for (int iy = i0[1]; iy <= i1[1]; iy++)
+          for (int iz = i0[2]; iz <= i1[2]; iz++) {
+            double c0[3] = {G->lo[0] + ix * G->w[0], G->lo[1] + iy * G->w[1], G->lo[2] + iz * G->w[2]};
+            double c1[3] = {c0[0] + G->w[0], c0[1] + G->w[1], c0[2] + G->w[2]};
+            if (!dau_meets_cell(g, pv, c0, c1)) continue;
+            long c = ((long)ix * G->n[1] + iy) * G->n[2] + iz;
+            if (pass == 0) {
+              cnt[c + 1]++;
+              total++;
+            } else {
+              G->dau[cnt[c]++] = k;
+            }
+          }
+    }
+    if (pass == 0) {
+      if (total > (1L << 28)) {
+        free(cnt);
+        return -1;
+      }
+      for (long c = 0; c < cells; c++) cnt[c + 1] += cnt[c];
+      G->off = (int*)xcalloc((size_t)cells + 1, sizeof(int));
+      G->dau = (int*)xcalloc((size_t)total, sizeof(int));
+      memcpy(G->off, cnt, ((size_t)cells + 1) * sizeof(int));
+    }
+  }
+  free(cnt);
+  return 0;
+}
+
+/* Switch the voxel mode on (building the grids once) or off.  0 on success. */
+int og_set_voxels(og_geom* g, int on) {
+  if (on && !g->vgrid) {
+    g->vgrid = (og_vgrid*)xcalloc(g->n_lv, sizeof(og_vgrid));
+    for (int l = 0; l < g->n_lv; l++) {
+      if (g->lv_dau_cnt[l] >= 4 && build_grid(g, l, &g->vgrid[l]) != 0) {
+        og_free_voxels(g);
+        return -1;
+      }
+    }
+  }
+  g->use_voxels = on;
+  return 0;
+}
+
+static const og_vgrid* grid_of(const og_geom* g, int lv) {
+  if (!g->use_voxels || !g->vgrid || !g->vgrid[lv].off) return NULL;
+  return &g->vgrid[lv];
+}
+
+static int cell_index(const og_vgrid* G, int i, double x) {
+  double a = floor((x - G->lo[i]) / G->w[i]);
+  return a < 0 ? 0 : (a > G->n[i] - 1 ? G->n[i] - 1 : (int)a);
+}
+
 /* Descend from touchable T (assumed to hold the point) into the deepest
  * daughter that holds it; daughters are tried in index order and the first
  * match wins.  `blocked` is a slot skipped at the first level only. */
@@ -855,7 +1070,18 @@ static int descend(const og_geom* g, int T, const double* pg, const double* vg, 
     int lv = g->t_lv[T];
     int found = -1;
     double pd[3], vd[3];
-    for (int k = 0; k < g->lv_dau_cnt[lv]; k++) {
+    /* candidates: every slot, or the slots listed in the point's cell */
+    const og_vgrid* G = grid_of(g, lv);
+    const int* list = NULL;
+    int n_cand = g->lv_dau_cnt[lv];
+    if (G) {
+      long c = ((long)cell_index(G, 0, pl[0]) * G->n[1] + cell_index(G, 1, pl[1])) * G->n[2] +
+               cell_index(G, 2, pl[2]);
+      list = G->dau + G->off[c];
+      n_cand = G->off[c + 1] - G->off[c];
+    }
+    for (int i = 0; i < n_cand; i++) {
+      int k = list ? list[i] : i;
       if (k == blocked) continue;
       int pv = g->lv_dau_off[lv] + k;
       to_local(g->pv_rot + 9 * pv, g->pv_trans + 3 * pv, pl, pd);
@@ -886,10 +1112,15 @@ static int locate(const og_geom* g, const double* pg, const double* vg) {
 
 /* ComputeStep by brute force: the mother's exit distance against every
  * daughter's entry distance; the mother wins ties, then the lowest slot. */
+static double compute_step_voxels(const og_geom* g, const og_vgrid* G, int lv, const double* pl,
+                                  const double* vl, int* lim);
+
 static double compute_step(const og_geom* g, int T, const double* pg, const double* vg, int* lim) {
   double pl[3], vl[3];
   frame_of(g, T, pg, vg, pl, vl);
   int lv = g->t_lv[T];
+  const og_vgrid* G = grid_of(g, lv);
+  if (G) return compute_step_voxels(g, G, lv, pl, vl, lim);
   double s = og_solid_dist_out(lv_solid_of(g, lv), pl, vl);
   *lim = OG_LIM_MOTHER;
   for (int k = 0; k < g->lv_dau_cnt[lv]; k++) {
@@ -903,6 +1134,66 @@ static double compute_step(const og_geom* g, int T, const double* pg, const doub
       *lim = k;
     }
   }
+  return s;
+}
+
+/* ComputeStep through the grid: the cells along the ray in order (a 3D DDA),
+ * each daughter evaluated once; the walk stops once the best distance does
+ * not exceed the current cell's exit, since a daughter not listed so far is
+ * entered only beyond it.  The same minimum and tie rule as brute force: the
+ * mother beats a daughter at equal distance, then the lowest slot. */
+static double compute_step_voxels(const og_geom* g, const og_vgrid* G, int lv, const double* pl,
+                                  const double* vl, int* lim) {
+  double s = og_solid_dist_out(lv_solid_of(g, lv), pl, vl);
+  *lim = OG_LIM_MOTHER;
+  int nd = g->lv_dau_cnt[lv];
+  unsigned char seen_small[512];
+  unsigned char* seen = nd <= 512 ? seen_small : (unsigned char*)xcalloc(nd, 1);
+  memset(seen, 0, nd <= 512 ? (size_t)nd : 0);
+  int c[3], step[3];
+  double tnext[3], dt[3];
+  for (int i = 0; i < 3; i++) {
+    c[i] = cell_index(G, i, pl[i]);
+    if (vl[i] > 0) {
+      step[i] = 1;
+      tnext[i] = (G->lo[i] + (c[i] + 1) * G->w[i] - pl[i]) / vl[i];
+      dt[i] = G->w[i] / vl[i];
+    } else if (vl[i] < 0) {
+      step[i] = -1;
+      tnext[i] = (G->lo[i] + c[i] * G->w[i] - pl[i]) / vl[i];
+      dt[i] = -G->w[i] / vl[i];
+    } else {
+      step[i] = 0;
+      tnext[i] = kInf;
+      dt[i] = kInf;
+    }
+  }
+  for (;;) {
+    long cell = ((long)c[0] * G->n[1] + c[1]) * G->n[2] + c[2];
+    for (int i = G->off[cell]; i < G->off[cell + 1]; i++) {
+      int k = G->dau[i];
+      if (seen[k]) continue;
+      seen[k] = 1;
+      int pv = g->lv_dau_off[lv] + k;
+      double pd[3], vd[3];
+      to_local(g->pv_rot + 9 * pv, g->pv_trans + 3 * pv, pl, pd);
+      dir_to_local(g->pv_rot + 9 * pv, vl, vd);
+      double t = og_solid_dist_in(lv_solid_of(g, g->pv_lv[pv]), pd, vd);
+      if (t < s || (t == s && *lim >= 0 && k < *lim)) {
+        s = t;
+        *lim = k;
+      }
+    }
+    int ax = 0;
+    if (tnext[1] < tnext[ax]) ax = 1;
+    if (tnext[2] < tnext[ax]) ax = 2;
+    double t_exit = tnext[ax];
+    if (s <= t_exit) break;
+    c[ax] += step[ax];
+    if (c[ax] < 0 || c[ax] >= G->n[ax]) break; /* left the grid: every candidate seen */
+    tnext[ax] += dt[ax];
+  }
+  if (seen != seen_small) free(seen);
   return s;
 }
 

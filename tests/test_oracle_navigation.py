@@ -123,3 +123,55 @@ def test_safety_is_lower_bound(oracle_lib, name):
         sph = p + s * (1 - 1e-9) * dirs
         loc, m = locate_bruteforce(desc, parent, pv, lv, depth, sph)
         assert np.all(loc[m > 1e-7] == t)
+
+
+def _surface_queries(desc, g, rng, n):
+    """Points where rays from random points cross a boundary (the brute-force
+    answer), with directions that graze, enter and leave."""
+    pts = _points(desc, rng, n)
+    dirs = W.primaries.isotropic(rng, n)
+    T = g.locate(pts, dirs)
+    ok = T >= 0
+    s, lim, _ = g.compute_step(pts[ok], dirs[ok], T[ok].astype(np.int32))
+    fin = np.isfinite(s)
+    end = pts[ok][fin] + s[fin, None] * dirs[ok][fin]
+    return end, W.primaries.isotropic(rng, end.shape[0])
+
+
+FULL = dict(GEOMS, calorimeter_full=lambda: W.geometry.calorimeter(),
+            barrel_full=lambda: W.geometry.barrel())
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_voxel_mode_equals_bruteforce(oracle_lib, name):
+    """The oracle's cell-grid search returns exactly the brute-force locate,
+    step length, limiter and next touchable, including points on surfaces."""
+    desc = FULL[name]()
+    a = oracle_lib.Geometry(desc)
+    b = oracle_lib.Geometry(desc)
+    b.set_voxels(True)
+    rng = np.random.Generator(np.random.Philox(key=31))
+    pts = _points(desc, rng, 6000)
+    dirs = W.primaries.isotropic(rng, 6000)
+    end, d2 = _surface_queries(desc, a, rng, 3000)
+    pts, dirs = np.concatenate([pts, end]), np.concatenate([dirs, d2])
+    assert np.array_equal(a.locate(pts, dirs), b.locate(pts, dirs))
+    assert np.array_equal(a.locate(pts), b.locate(pts))
+    sa, la, na = a.compute_step(pts, dirs)
+    sb, lb, nb = b.compute_step(pts, dirs)
+    assert np.array_equal(sa.view(np.uint64), sb.view(np.uint64))
+    assert np.array_equal(la, lb) and np.array_equal(na, nb)
+
+
+@pytest.mark.parametrize("name,n", [("tiny", 3000), ("calorimeter", 1500), ("barrel", 400)])
+def test_voxel_mode_transport_identical(oracle_lib, name, n):
+    """Whole transports in voxel mode reproduce the brute-force per-step logs."""
+    geoms, prim, _ = W.WORKLOADS[name](n=n)
+    a = oracle_lib.Geometry(geoms[0])
+    b = oracle_lib.Geometry(geoms[0])
+    b.set_voxels(True)
+    ra = a.transport(prim, seed=0, log_cap=256)
+    rb = b.transport(prim, seed=0, log_cap=256)
+    assert ra["counters"] == rb["counters"]
+    assert np.array_equal(ra["log"], rb["log"]) and np.array_equal(ra["log_n"], rb["log_n"])
+    assert np.array_equal(ra["edep_event"], rb["edep_event"])
