@@ -146,6 +146,10 @@ def time_batches(ctx, gid, prim_d, tally, stream, reps, **kw):
     return float(np.median(ms)), res, work
 
 
+def _progress(what):
+    print(f"done: {what}", file=sys.stderr, flush=True)
+
+
 def barrel_variants(ctx, gnav, n, reps, train_photons):
     """Barrel workload: FP64 plain walk against the bound and learned candidate
     orders (identical results) and the two FP32-distance forms."""
@@ -174,8 +178,11 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
 
     out["fp64"] = {"ms": base_ms, "steps_per_s": steps / base_ms * 1e3, "steps": steps,
                    "dist_in_fp64": base_w["dist_in"]}
+    _progress("barrel fp64")
     out["fp64_bound_order"] = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, order=1))
+    _progress("barrel bound order")
     out["fp32_screened"] = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, precision=1))
+    _progress("barrel fp32 screened")
     pure = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, precision=2))
     # pure FP32: deposit histogram chi-square per degree of freedom against FP64
     tally.reset(stream)
@@ -190,6 +197,7 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
     pure["pushes"] = pr["counters"]["pushes"]
     pure["stuck"] = pr["counters"]["stuck"]
     out["fp32_pure"] = pure
+    _progress("barrel fp32 pure")
     # per-query FP32 error against FP64 (the FP64 query path equals the oracle per query)
     rng = np.random.Generator(np.random.Philox(key=77))
     q = 100_000
@@ -224,6 +232,7 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
                          "accuracy_top1": learned.accuracy(net, x[:200_000], cls[:200_000],
                                                            label[:200_000])}
         out["fp64_learned_order"] = e
+        _progress("barrel learned order")
         ctx.set_mlp(gid, None)
         net.free()
         # the same comparison with bounding-box voxel node lists (as Geant4's smart

@@ -107,26 +107,33 @@ __global__ void k_bias_relu(long n, int N, float* __restrict__ a, const float* _
   }
 }
 
-// Softmax cross-entropy over 64 logits per sample (one wave per sample):
-// dZ = (softmax(z) - onehot(label)) / B, loss += (lse - z_label) / B.
-__global__ void k_softmax_ce(int B, float* __restrict__ z, const float* __restrict__ b3,
-                             const int* __restrict__ label, float* __restrict__ dz, uint16_t* __restrict__ dzb,
-                             float* __restrict__ loss) {
-  const int lane = threadIdx.x & 63;
-  const long b = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (b >= B) return;
-  float v = z[b * kNOut + lane] + b3[lane];
-  z[b * kNOut + lane] = v;
-  float mx = v;
-  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-  float e = expf(v - mx);
-  float s = e;
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  int lab = label[b];
-  float g = (e / s - (lane == lab ? 1.f : 0.f)) / (float)B;
-  dz[b * kNOut + lane] = g;
-  dzb[b * kNOut + lane] = f2bf(g);
-  if (lane == lab && loss) atomicAdd(loss, (logf(s) - (v - mx)) / (float)B);
+// Softmax cross-entropy over 64 logits per sample (one wave per sample, four
+// per block): dZ = (softmax(z) - onehot(label)) / B, loss += (lse - z_label) / B
+// (one atomic per block).
+__global__ void __launch_bounds__(256) k_softmax_ce(int B, float* __restrict__ z, const float* __restrict__ b3,
+                                                    const int* __restrict__ label, float* __restrict__ dz,
+                                                    uint16_t* __restrict__ dzb, float* __restrict__ loss) {
+  __shared__ float part[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long b = (long)blockIdx.x * 4 + w;
+  float l = 0.f;
+  if (b < B) {
+    float v = z[b * kNOut + lane] + b3[lane];
+    z[b * kNOut + lane] = v;
+    float mx = v;
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    float e = expf(v - mx);
+    float s = e;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    int lab = label[b];
+    float g = (e / s - (lane == lab ? 1.f : 0.f)) / (float)B;
+    dz[b * kNOut + lane] = g;
+    dzb[b * kNOut + lane] = f2bf(g);
+    l = __shfl((logf(s) - (v - mx)) / (float)B, lab);
+  }
+  if (lane == 0) part[w] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, ((part[0] + part[1]) + part[2]) + part[3]);
 }
 
 // In place: A += bias (no activation; the logits).
@@ -208,6 +215,7 @@ __global__ void __launch_bounds__(kNH) k_w1m_part(int B, int R, int n_class, con
 __global__ void k_sum_parts(long n, int P, const float* __restrict__ part, float* __restrict__ out) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     float s = 0.f;
+#pragma unroll 8
     for (int p = 0; p < P; p++) s += part[(long)p * n + i];
     out[i] = s;
   }

@@ -567,7 +567,11 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
       }
       P.pred[tid] = -1;
       int n = compact<1>(P, elig, 0);
-      if (n > 0) {
+      // Score only when a full 16-row tile is due: the out-of-line call saves
+      // and restores the live registers of the loop through scratch memory,
+      // which a few rows do not repay.  Unscored steps take the nearest
+      // enclosing cylinder first, as in the bound order; results are the same.
+      if (n >= 16) {
         // features of listed step i: the point in the mother frame over the
         // voxel grid's half size (centred on the grid), and the direction
         if (tid < n) {
