@@ -391,7 +391,10 @@ def headline(args, ctx, gnav, cpu, workers):
 
     flops = algorithmic_flops(c)
     achieved_tf = flops / avg_kern_s / 1e12
-    kernel = f"gnav::pool{args.block or 64}::k_transport<false, false, 0, 0>"
+    # 64-slot blocks on a geometry of boxes only run the box-only build
+    block = args.block or 64
+    boxes = block == 64 and bool(np.all(np.asarray(geoms[0].solid_type) == 0))
+    kernel = f"gnav::pool{block}{'_box' if boxes else ''}::k_transport<false, false, 0, 0>"
     traffic = stored_traffic(kernel)
     out = {
         "metric": "gamma navigation steps/s on 1 GPU",

@@ -476,41 +476,63 @@ __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<
 
 // ---------------------------------------------------------------------------
 // Dispatch over solid families ("fork" by type code)
+//
+// A translation unit built with GNAV_BOX_ONLY compiles the box code alone:
+// the host launches that build of the transport kernel only when every solid
+// of the geometries a batch can reach is a box, and then it gives the same
+// results with fewer registers and branches.  Device code is compiled per
+// translation unit (no device linking), so the two forms never meet.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, bool has_v, V3 v) {
+#ifdef GNAV_BOX_ONLY
+  return box_inside(q, p, has_v, v);
+#else
   switch (info & 15) {
     case kBox: return box_inside(q, p, has_v, v);
     case kOrb: return orb_inside(q[0], p, has_v, v);
     default: return rad_inside(q, info, p, has_v, v);
   }
+#endif
 }
 
 template <typename R>
 __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
+#ifdef GNAV_BOX_ONLY
+  return box_d(q, p);
+#else
   switch (info & 15) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
     default: return rad_dmax(rad_comps(q, info, p));
   }
+#endif
 }
 
 template <typename R>
 __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3<R> v) {
+#ifdef GNAV_BOX_ONLY
+  return box_dist_in(q, p, v);
+#else
   switch (info & 15) {
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
     default: return rad_dist_in(q, info, p, v);
   }
+#endif
 }
 
 template <typename R>
 __device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec3<R> v) {
+#ifdef GNAV_BOX_ONLY
+  return box_dist_out(q, p, v);
+#else
   switch (info & 15) {
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
     default: return rad_dist_out(q, info, p, v);
   }
+#endif
 }
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 // gnav_transport.hip -- the persistent gamma transport kernel for gfx950
 // (wave64), built once per track-pool size (GNAV_POOL slots per block: 64,
-// 128 or 256), each build in its own namespace.
+// 128 or 256), each build in its own namespace, plus a 64-slot build for
+// geometries made of boxes only (GNAV_BOX_ONLY, namespace pool64_box).
 //
 // Transport follows Sec. 3.1: each photon draws an Exp(1) optical depth
 // (Alg. 1, steps 1-2), spends it boundary to boundary (S_j update, Eq. 6)
@@ -25,7 +26,11 @@
 #endif
 #define GNAV_CAT2(a, b) a##b
 #define GNAV_CAT(a, b) GNAV_CAT2(a, b)
+#ifdef GNAV_BOX_ONLY
+#define GNAV_POOL_NS GNAV_CAT(GNAV_CAT(pool, GNAV_POOL), _box)
+#else
 #define GNAV_POOL_NS GNAV_CAT(pool, GNAV_POOL)
+#endif
 
 static_assert(GNAV_POOL == 64 || GNAV_POOL == 128 || GNAV_POOL == 256, "track pool of 64, 128 or 256 slots");
 
@@ -922,7 +927,7 @@ hipError_t launch(const TransportLaunch& L, hipStream_t st) {
 
 }  // namespace GNAV_POOL_NS
 
-hipError_t GNAV_CAT(launch_transport_pool, GNAV_POOL)(const TransportLaunch& L, hipStream_t st) {
+hipError_t GNAV_CAT(launch_transport_, GNAV_POOL_NS)(const TransportLaunch& L, hipStream_t st) {
   return GNAV_POOL_NS::launch(L, st);
 }
 
