@@ -391,10 +391,12 @@ def headline(args, ctx, gnav, cpu, workers):
 
     flops = algorithmic_flops(c)
     achieved_tf = flops / avg_kern_s / 1e12
-    # 64-slot blocks on a geometry of boxes only run the box-only build
+    # 64-slot blocks on a geometry of unrotated boxes run the axis-aligned box build
     block = args.block or 64
-    boxes = block == 64 and bool(np.all(np.asarray(geoms[0].solid_type) == 0))
-    kernel = f"gnav::pool{block}{'_box' if boxes else ''}::k_transport<false, false, 0, 0>"
+    d0 = geoms[0]
+    axis_boxes = (block == 64 and bool(np.all(np.asarray(d0.solid_type) == 0)) and
+                  bool(np.all(np.asarray(d0.pv_rot).reshape(-1, 9) == np.eye(3).ravel())))
+    kernel = f"gnav::pool{block}{'_axis_boxes' if axis_boxes else ''}::k_transport<false, false, 0, 0>"
     traffic = stored_traffic(kernel)
     out = {
         "metric": "gamma navigation steps/s on 1 GPU",

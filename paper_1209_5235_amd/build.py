@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libgnav.so")
 SOURCES = [("gnav_host.cpp", "gnav_host", ()), ("gnav_kernels.hip", "gnav_kernels", ()),
            ("gnav_mlp.hip", "gnav_mlp", ())] + \
           [("gnav_transport.hip", f"gnav_transport_pool{p}", (f"GNAV_POOL={p}",)) for p in (64, 128, 256)] + \
-          [("gnav_transport.hip", "gnav_transport_pool64_box", ("GNAV_POOL=64", "GNAV_BOX_ONLY"))]
+          [("gnav_transport.hip", "gnav_transport_pool64_axis_boxes", ("GNAV_POOL=64", "GNAV_AXIS_BOXES"))]
 
 # -ffp-contract=off: no fused multiply-add contraction, so each distance is
 # rounded operation by operation.  The packed-fp32 feature is disabled for all

@@ -138,12 +138,18 @@ using V3f = Vec3<float>;
 
 __device__ __forceinline__ V3 xf_point(const double* __restrict__ m, int kind, V3 p) {
   double d0 = p.x - m[9], d1 = p.y - m[10], d2 = p.z - m[11];
+#ifdef GNAV_AXIS_BOXES
+  return V3{d0, d1, d2};  // every placement is a translation (see the solid dispatch)
+#endif
   if (kind == 0) return V3{d0, d1, d2};
   return V3{m[0] * d0 + m[1] * d1 + m[2] * d2, m[3] * d0 + m[4] * d1 + m[5] * d2,
             m[6] * d0 + m[7] * d1 + m[8] * d2};
 }
 
 __device__ __forceinline__ V3 xf_dir(const double* __restrict__ m, int kind, V3 v) {
+#ifdef GNAV_AXIS_BOXES
+  return v;
+#endif
   if (kind == 0) return v;
   return V3{m[0] * v.x + m[1] * v.y + m[2] * v.z, m[3] * v.x + m[4] * v.y + m[5] * v.z,
             m[6] * v.x + m[7] * v.y + m[8] * v.z};
@@ -477,15 +483,17 @@ __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<
 // ---------------------------------------------------------------------------
 // Dispatch over solid families ("fork" by type code)
 //
-// A translation unit built with GNAV_BOX_ONLY compiles the box code alone:
-// the host launches that build of the transport kernel only when every solid
-// of the geometries a batch can reach is a box, and then it gives the same
-// results with fewer registers and branches.  Device code is compiled per
-// translation unit (no device linking), so the two forms never meet.
+// A translation unit built with GNAV_AXIS_BOXES compiles the box code alone
+// and treats every placement as a translation (the point and direction maps
+// above): the host launches that build of the transport kernel only when
+// every solid of the geometries a batch can reach is a box placed without
+// rotation, and then it gives the same results with fewer registers and
+// branches.  Device code is compiled per translation unit (no device
+// linking), so the two forms never meet.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, bool has_v, V3 v) {
-#ifdef GNAV_BOX_ONLY
+#ifdef GNAV_AXIS_BOXES
   return box_inside(q, p, has_v, v);
 #else
   switch (info & 15) {
@@ -498,7 +506,7 @@ __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, boo
 
 template <typename R>
 __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
-#ifdef GNAV_BOX_ONLY
+#ifdef GNAV_AXIS_BOXES
   return box_d(q, p);
 #else
   switch (info & 15) {
@@ -511,7 +519,7 @@ __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
 
 template <typename R>
 __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3<R> v) {
-#ifdef GNAV_BOX_ONLY
+#ifdef GNAV_AXIS_BOXES
   return box_dist_in(q, p, v);
 #else
   switch (info & 15) {
@@ -524,7 +532,7 @@ __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3
 
 template <typename R>
 __device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec3<R> v) {
-#ifdef GNAV_BOX_ONLY
+#ifdef GNAV_AXIS_BOXES
   return box_dist_out(q, p, v);
 #else
   switch (info & 15) {

@@ -551,7 +551,7 @@ struct GeomRec {
   gnav_mlp* mlp = nullptr;  // network for the learned candidate order
   int t_base, n_t;
   int n_class = 0;  // voxelised mothers (candidate-ordering classes)
-  bool boxes_only = false;  // every solid is a box
+  bool axis_boxes = false;  // every solid is a box and every placement a translation
   int lv_base, pv_base, solid_base, mat_base;
   std::vector<int> h_parent, h_pv, h_lv, h_depth;  // per-geometry ids
 };
@@ -838,7 +838,8 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
 
   GeomRec gr;
   gr.t_base = (int)c->t_rec.size();
-  gr.boxes_only = std::all_of(d->solid_type, d->solid_type + d->n_solids, [](int32_t ty) { return ty == kBox; });
+  gr.axis_boxes = std::all_of(d->solid_type, d->solid_type + d->n_solids, [](int32_t ty) { return ty == kBox; });
+  for (int p = 0; p < d->n_pv && gr.axis_boxes; p++) gr.axis_boxes = is_identity(d->pv_rot + 9L * p);
   gr.n_t = nt;
   gr.lv_base = (int)c->lv_rec.size();
   gr.pv_base = (int)c->pv_rec.size();
@@ -1293,9 +1294,9 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.block = block;
   L.grid = grid;
   // a batch with per-event geometries can reach every resident geometry
-  L.boxes_only = b->event_geom_dev ? std::all_of(c->geoms.begin(), c->geoms.end(),
-                                                 [](const GeomRec& g) { return g.boxes_only; })
-                                   : c->geoms[b->geom_id].boxes_only;
+  L.axis_boxes = b->event_geom_dev ? std::all_of(c->geoms.begin(), c->geoms.end(),
+                                                 [](const GeomRec& g) { return g.axis_boxes; })
+                                   : c->geoms[b->geom_id].axis_boxes;
   return GNAV_OK;
 }
 

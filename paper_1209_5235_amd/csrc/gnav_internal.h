@@ -48,7 +48,7 @@ struct TransportLaunch {
   int* log_fate;
   int block;
   int grid;
-  bool boxes_only;  // every solid the batch can reach is a box
+  bool axis_boxes;  // every solid the batch can reach is a box placed without rotation
   bool count;
   int order;
   int prec;  // kPrecFP64 / kPrecScreened / kPrecPure (FP32 forms use the plain order)
@@ -73,7 +73,7 @@ hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n,
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);
 // the transport kernel built for track pools of 64, 128 and 256 slots
 hipError_t launch_transport_pool64(const TransportLaunch& L, hipStream_t st);
-hipError_t launch_transport_pool64_box(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool64_axis_boxes(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_transport_pool128(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_transport_pool256(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, const double* dir,

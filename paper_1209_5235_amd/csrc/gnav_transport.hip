@@ -1,7 +1,8 @@
 // gnav_transport.hip -- the persistent gamma transport kernel for gfx950
 // (wave64), built once per track-pool size (GNAV_POOL slots per block: 64,
 // 128 or 256), each build in its own namespace, plus a 64-slot build for
-// geometries made of boxes only (GNAV_BOX_ONLY, namespace pool64_box).
+// geometries made of boxes placed without rotation (GNAV_AXIS_BOXES,
+// namespace pool64_axis_boxes).
 //
 // Transport follows Sec. 3.1: each photon draws an Exp(1) optical depth
 // (Alg. 1, steps 1-2), spends it boundary to boundary (S_j update, Eq. 6)
@@ -26,8 +27,8 @@
 #endif
 #define GNAV_CAT2(a, b) a##b
 #define GNAV_CAT(a, b) GNAV_CAT2(a, b)
-#ifdef GNAV_BOX_ONLY
-#define GNAV_POOL_NS GNAV_CAT(GNAV_CAT(pool, GNAV_POOL), _box)
+#ifdef GNAV_AXIS_BOXES
+#define GNAV_POOL_NS GNAV_CAT(GNAV_CAT(pool, GNAV_POOL), _axis_boxes)
 #else
 #define GNAV_POOL_NS GNAV_CAT(pool, GNAV_POOL)
 #endif
