@@ -139,6 +139,25 @@ def test_transport_parity_rotated_boxes(ctx, torch_dev, oracle_lib):
     assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
 
 
+def test_transport_parity_pair_heavy(ctx, torch_dev, oracle_lib):
+    """20 MeV photons in the calorimeter convert often, so annihilation photons
+    outrun the block stack and also take the per-slot pending path: per-track
+    parity with the oracle."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("transport_pair_heavy")
+    _, prim, _ = W.calorimeter(n=3000)
+    prim.energy[:] = 20.0
+    got = run_transport(ctx, torch, gid, prim, 600)
+    ref = og.transport(prim, seed=0, log_cap=600)
+    assert ref["counters"]["pair"] > 1000
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, 600)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
+
+
 def test_transport_launch_shape_independent(ctx, torch_dev, oracle_lib):
     """Counter-keyed random numbers: any block/grid gives the same tracks."""
     torch = torch_dev
