@@ -307,6 +307,22 @@ def paper_free_path(ctx, gnav, reps, oracle_sample):
     return out
 
 
+def tiny_config(ctx, gnav, reps):
+    """The small configuration: eight boxes in a vacuum world, 1e4 photons of
+    1 MeV from the origin (the parity case the oracle runs in seconds)."""
+    import torch
+    import workloads as W
+    geoms, prim, _ = W.tiny(n=10_000, seed=0)
+    gid, _ = ctx.upload_geometry(geoms[0])
+    prim_d = gnav.primaries_to_device(prim, "cuda")
+    tally = ctx.tally_create(prim.n_events)
+    ms, res, _ = time_batches(ctx, gid, prim_d, tally, torch.cuda.current_stream(), reps)
+    tally.free()
+    steps = res["counters"]["steps"]
+    return {"workload": "tiny: 8 water/Pb boxes in a vacuum world, 1e4 photons of 1 MeV from the origin",
+            "ms": ms, "steps": steps, "steps_per_s": steps / ms * 1e3}
+
+
 def batched_config(ctx, gnav, reps):
     """Uneven events over eight resident geometries in one launch: autotuned
     launch settings, then the tuned launch captured in a HIP graph."""
@@ -484,12 +500,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-events config")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
-    ap.add_argument("--sections", default="headline,barrel,paper,batched",
+    ap.add_argument("--sections", default="headline,tiny,barrel,paper,batched",
                     help="comma-separated parts to run (profiling runs pick one); without "
                          "'headline' the line carries only the parts that ran")
     args = ap.parse_args()
     sections = set(args.sections.split(","))
-    unknown = sections - {"headline", "barrel", "paper", "batched"}
+    unknown = sections - {"headline", "tiny", "barrel", "paper", "batched"}
     if unknown:
         ap.error(f"unknown sections {sorted(unknown)}")
 
@@ -519,6 +535,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     out = headline(args, ctx, gnav, cpu, workers) if "headline" in sections else {}
+    if "tiny" in sections:
+        out["tiny"] = tiny_config(ctx, gnav, 5)
+        _progress("tiny config")
     if "barrel" in sections and args.barrel_n > 0:
         out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
         print("barrel variants done", file=sys.stderr, flush=True)
