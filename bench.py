@@ -511,8 +511,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(events are independent, see the sharding notes in the design document)",
+        print("bench.py: the library drives one GPU; --gpus must be 1 (events are independent: "
+              "a multi-GPU run would split the event range and sum the tallies)",
               file=sys.stderr)
         sys.exit(2)
 
