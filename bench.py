@@ -247,13 +247,19 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
         ctx.set_mlp(gid_b, net)
         ms_l, res_l, w_l = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, order=2)
         ms_bo, res_bo, w_bo = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, order=1)
-        same = all(res_l["counters"][k] == res_p["counters"][k]
-                   for k in ("steps", "pe", "compton", "pair", "crossings", "escaped", "tracks"))
+        ms_s, res_s, w_s = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, precision=1)
+        ms_f, res_f, _ = time_batches(ctx, gid_b, prim_d, tally_b, stream, reps, precision=2)
+        keys = ("steps", "pe", "compton", "pair", "crossings", "escaped", "tracks")
+        same = all(res_l["counters"][k] == res_p["counters"][k] for k in keys)
         out["bbox_voxel_lists"] = {
             "fp64_ms": ms_p, "fp64_steps_per_s": res_p["counters"]["steps"] / ms_p * 1e3,
             "dist_in_fp64": w_p["dist_in"], "learned_ms": ms_l, "learned_speedup": ms_p / ms_l,
             "learned_dist_in_fp64": w_l["dist_in"], "learned_same_counters": bool(same),
             "bound_order_ms": ms_bo, "bound_order_speedup": ms_p / ms_bo,
+            "fp32_screened_ms": ms_s, "fp32_screened_speedup": ms_p / ms_s,
+            "fp32_screened_dist_in_fp64": w_s["dist_in"], "fp32_screened_dist_in_fp32": w_s["dist_in_f32"],
+            "fp32_screened_same_counters": all(res_s["counters"][k] == res_p["counters"][k] for k in keys),
+            "fp32_pure_ms": ms_f, "fp32_pure_speedup": ms_p / ms_f,
             "training_crossings": int(x.shape[0])}
         ctx.set_mlp(gid_b, None)
         net.free()

@@ -804,6 +804,11 @@ __device__ __forceinline__ double cyl_bound(float4 c, double rho, double z) {
 // ordering pass costs more than it can save).
 enum : int { kOrderPlain = 0, kOrderBound = 1, kOrderLearned = 2 };
 constexpr int kOrderMinCand = 3;
+// FP32 screening ranks every candidate of a node by its FP32 entry distance
+// before the FP64 evaluations; a candidate's FP32 distance costs about what
+// its FP64 one does (both wait on the same placement and solid records), so
+// nodes with fewer than kScreenMinCand candidates are walked in FP64.
+constexpr int kScreenMinCand = 6;
 
 // ComputeStep in the mother frame (pl, vl) of a touchable with LV record L:
 // the mother's exit distance against daughter entry distances, collected by
@@ -1098,7 +1103,7 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
           lim = k;
         }
       }
-    } else if (nd.y < kOrderMinCand) {
+    } else if (nd.y < kScreenMinCand) {
       // too few candidates to gain from screening: FP64 as in compute_step
       for (int c = 0; c < nd.y; c++) {
         const int k = slot(c);

@@ -73,10 +73,30 @@ def test_screened_transport_matches_oracle(ctx, torch_dev, oracle_lib, name, n, 
         assert got["counters"][k] == ref["counters"][k], k
     assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
     assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
-    # nodes with fewer than three candidates are walked in FP64 (the calorimeter's
-    # start nodes hold one or two), the others are screened in FP32
-    if name != "calorimeter":
+    # nodes with fewer than six candidates are walked in FP64 (every node of the
+    # calorimeter and of the barrel's shape-aware grids); the tiny world's eight
+    # daughters (no grid) are screened in FP32
+    if name == "tiny":
         assert got["counters"]["dist_in_f32"] > 0
+
+
+def test_screened_transport_bbox_lists_matches_oracle(ctx, torch_dev, oracle_lib):
+    """Bounding-box node lists hold many candidates, so nearly every daughter
+    search is screened in FP32: per-track parity with the oracle still holds."""
+    torch = torch_dev
+    desc = W.geometry.barrel(seed=1)
+    gid, _ = ctx.upload_geometry(desc, voxel_lists=1)
+    og = oracle_lib.Geometry(desc)
+    print_case("fp32_screened_transport_bbox_lists")
+    _, prim, _ = W.barrel(n=2000)
+    got = run_transport(ctx, torch, gid, prim, 512, precision=SCREENED, count_work=True)
+    ref = og.transport(prim, seed=0, log_cap=512)
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, 512)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
+    assert got["counters"]["dist_in_f32"] > 5 * got["counters"]["dist_in"]
 
 
 def query_error_stats(s, l, s_ref, l_ref):
