@@ -146,11 +146,28 @@ def time_batches(ctx, gid, prim_d, tally, stream, reps, **kw):
     return float(np.median(ms)), res, work
 
 
+def oracle_rates(desc, prim, n_sample):
+    """Oracle steps/s (one thread) on the first n_sample primaries, brute force and
+    voxel mode; the same deterministic subset for both."""
+    import oracle
+    sub = prim.subset(np.arange(min(n_sample, prim.n)))
+    out = {}
+    for voxels in (False, True):
+        og = oracle.Geometry(desc)
+        og.set_voxels(voxels)
+        t0 = time.perf_counter()
+        r = og.transport(sub, seed=0, n_events=prim.n_events)
+        dt = time.perf_counter() - t0
+        out["voxel" if voxels else "brute_force"] = r["counters"]["steps"] / dt
+    out["sample"] = f"first {sub.n} primaries, one thread"
+    return out
+
+
 def _progress(what):
     print(f"done: {what}", file=sys.stderr, flush=True)
 
 
-def barrel_variants(ctx, gnav, n, reps, train_photons):
+def barrel_variants(ctx, gnav, n, reps, train_photons, oracle_sample=0):
     """Barrel workload: FP64 plain walk against the bound and learned candidate
     orders (identical results) and the two FP32-distance forms."""
     import torch
@@ -178,6 +195,8 @@ def barrel_variants(ctx, gnav, n, reps, train_photons):
 
     out["fp64"] = {"ms": base_ms, "steps_per_s": steps / base_ms * 1e3, "steps": steps,
                    "dist_in_fp64": base_w["dist_in"]}
+    if oracle_sample > 0:
+        out["fp64"]["oracle_steps_per_s"] = oracle_rates(geoms[0], prim, oracle_sample)
     _progress("barrel fp64")
     out["fp64_bound_order"] = entry(*time_batches(ctx, gid, prim_d, tally, stream, reps, order=1))
     _progress("barrel bound order")
@@ -313,7 +332,7 @@ def paper_free_path(ctx, gnav, reps, oracle_sample):
     return out
 
 
-def tiny_config(ctx, gnav, reps):
+def tiny_config(ctx, gnav, reps, with_oracle):
     """The small configuration: eight boxes in a vacuum world, 1e4 photons of
     1 MeV from the origin (the parity case the oracle runs in seconds)."""
     import torch
@@ -325,8 +344,11 @@ def tiny_config(ctx, gnav, reps):
     ms, res, _ = time_batches(ctx, gid, prim_d, tally, torch.cuda.current_stream(), reps)
     tally.free()
     steps = res["counters"]["steps"]
-    return {"workload": "tiny: 8 water/Pb boxes in a vacuum world, 1e4 photons of 1 MeV from the origin",
-            "ms": ms, "steps": steps, "steps_per_s": steps / ms * 1e3}
+    out = {"workload": "tiny: 8 water/Pb boxes in a vacuum world, 1e4 photons of 1 MeV from the origin",
+           "ms": ms, "steps": steps, "steps_per_s": steps / ms * 1e3}
+    if with_oracle:
+        out["oracle_steps_per_s"] = oracle_rates(geoms[0], prim, prim.n)
+    return out
 
 
 def batched_config(ctx, gnav, reps):
@@ -542,10 +564,11 @@ def main():
         del src, dst
     out = headline(args, ctx, gnav, cpu, workers) if "headline" in sections else {}
     if "tiny" in sections:
-        out["tiny"] = tiny_config(ctx, gnav, 5)
+        out["tiny"] = tiny_config(ctx, gnav, 5, not args.no_cpu)
         _progress("tiny config")
     if "barrel" in sections and args.barrel_n > 0:
-        out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons)
+        out["variants"] = barrel_variants(ctx, gnav, args.barrel_n, 3, args.train_photons,
+                                          0 if args.no_cpu else 20_000)
         print("barrel variants done", file=sys.stderr, flush=True)
     if "paper" in sections:
         out["paper_free_path"] = paper_free_path(ctx, gnav, 5, 0 if args.no_cpu else 3000)
