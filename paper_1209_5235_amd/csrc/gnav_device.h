@@ -801,7 +801,9 @@ __device__ __forceinline__ double cyl_bound(float4 c, double rho, double z) {
 
 // Candidate orders for the start node of a step walk.  Nodes with fewer
 // candidates than kOrderMinCand are walked in slot order (with two, an
-// ordering pass costs more than it can save).
+// ordering pass costs more than it can save), and so are all nodes of mothers
+// whose nodes hold fewer than kOrderMinCand candidates on average (LRec.wide
+// unset): there the ordering pass costs more than its rare skips save.
 enum : int { kOrderPlain = 0, kOrderBound = 1, kOrderLearned = 2 };
 constexpr int kOrderMinCand = 3;
 // FP32 screening ranks every candidate of a node by its FP32 entry distance
@@ -871,7 +873,7 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
     int2 nd = G.vox_node[L.node_base + (idx[0] * L.n[1] + idx[1]) * L.n[2] + idx[2]];
     nc.node();
     if (first && start_node) *start_node = nd;
-    if (ORDER != kOrderPlain && first && nd.y >= kOrderMinCand) {
+    if (ORDER != kOrderPlain && first && nd.y >= kOrderMinCand && L.wide) {
       const double rho = sqrt(pl.x * pl.x + pl.y * pl.y);
       int lead = -1;
       if (ORDER == kOrderLearned && pred >= 0 && pred < nd.y) lead = pred;

@@ -552,6 +552,7 @@ struct GeomRec {
   int t_base, n_t;
   int n_class = 0;  // voxelised mothers (candidate-ordering classes)
   bool axis_boxes = false;  // every solid is a box and every placement a translation
+  bool any_wide = false;    // some mother's voxel nodes hold enough candidates for ordered walks
   int lv_base, pv_base, solid_base, mat_base;
   std::vector<int> h_parent, h_pv, h_lv, h_depth;  // per-geometry ids
 };
@@ -950,6 +951,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
       for (auto& nd : vb.nodes) mean += (double)nd.size();
       mean /= std::max<size_t>(1, vb.nodes.size());
       lr.wide = mean >= kOrderMinCand ? 1 : 0;
+      gr.any_wide = gr.any_wide || lr.wide;
     }
     c->lv_rec.push_back(lr);
   }
@@ -1269,7 +1271,9 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.pend = c->d_pend.as<double>();
   L.count = b->count_work != 0;
   if (b->order < 0 || b->order > 2) return fail(c, GNAV_EINVAL, "order must be 0, 1 or 2");
-  L.order = b->order;
+  // With no mother wide enough for ordered walks the learned order scores
+  // nothing and walks like the bound order; launch that instantiation.
+  L.order = (b->order == 2 && !c->geoms[b->geom_id].any_wide) ? 1 : b->order;
   L.prec = b->precision;
   if (chunk_req < 0 || chunk_req > (1 << 24)) return fail(c, GNAV_EINVAL, "chunk out of range");
   if (sort_req < 0) return fail(c, GNAV_EINVAL, "negative sort period");

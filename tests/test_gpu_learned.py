@@ -56,11 +56,16 @@ def test_recorder_records_valid_crossings(barrel):
     assert np.all(np.abs(r["x"]) <= 1.0 + 1e-5)
 
 
-def test_orders_give_identical_results(barrel):
-    """Plain, lower-bound and learned orders: bitwise identical per-track logs."""
+@pytest.mark.parametrize("voxel_lists", [0, 1])
+def test_orders_give_identical_results(barrel, voxel_lists):
+    """Plain, lower-bound and learned orders: bitwise identical per-track logs, with
+    the shape-aware node lists (no mother holds enough candidates per node for the
+    orders to engage) and with bounding-box lists (the envelope's nodes do)."""
     torch, gnav, ctx, gid, desc = barrel
-    print_case("order_identity")
+    print_case("order_identity", voxel_lists)
     from paper_1209_5235_amd import learned
+    if voxel_lists:
+        gid, _ = ctx.upload_geometry(desc, voxel_lists=1)
     n_class = ctx.ordering_classes(gid)
     # train briefly on crossings recorded with other seeds
     _, tprim, _ = W.barrel(n=20000, seed=1)
@@ -83,9 +88,12 @@ def test_orders_give_identical_results(barrel):
             other["edep_event"], plain["edep_event"], rtol=1e-12, atol=0)
         for k in ["steps", "pe", "compton", "pair", "crossings", "escaped"]:
             assert other["counters"][k] == plain["counters"][k]
-    # the orders examine fewer exact daughter distances than the plain walk
-    assert bound["counters"]["dist_in"] < plain["counters"]["dist_in"]
-    assert learn["counters"]["dist_in"] < plain["counters"]["dist_in"]
+    if voxel_lists:
+        # where they engage, the orders examine fewer exact daughter distances
+        assert bound["counters"]["dist_in"] < plain["counters"]["dist_in"]
+        assert learn["counters"]["dist_in"] < plain["counters"]["dist_in"]
+    else:
+        assert bound["counters"]["dist_in"] == plain["counters"]["dist_in"]
     print("dist_in evaluations plain/bound/learned:", plain["counters"]["dist_in"],
           bound["counters"]["dist_in"], learn["counters"]["dist_in"], flush=True)
     ctx.set_mlp(gid, None)
