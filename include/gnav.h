@@ -260,7 +260,9 @@ typedef struct {
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
   int32_t count_work;         /* 1: also count navigation work (GNAV_C_DIST_IN..VOXEL_NODES) */
   int32_t order;              /* start-node candidate order: 0 slot order, 1 smallest lower bound
-                                 first, 2 learned (network set with gnav_set_mlp); same results */
+                                 first, 2 learned (network set with gnav_set_mlp); same results.
+                                 Orders 1 and 2 apply in mothers whose voxel nodes hold three or
+                                 more candidates on average; elsewhere the walk is in slot order */
   struct gnav_crossing* record_dev; /* optional recorder of daughter-limited steps (training data) */
   int64_t record_capacity;
   uint64_t* record_count_dev; /* crossings seen (may exceed the capacity; extra ones dropped) */
