@@ -51,3 +51,12 @@ def test_stored_traffic_is_tied_to_the_kernel_sources():
         assert np.isclose(bench.stored_traffic(t["kernel"]), t["bytes_per_launch"])
     else:
         assert bench.stored_traffic(t["kernel"]) is None
+
+
+def test_oracle_rates_both_modes_on_a_small_sample():
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    geoms, prim, _ = W.tiny(n=300)
+    r = bench.oracle_rates(geoms[0], prim, 200)
+    assert r["brute_force"] > 0 and r["voxel"] > 0 and "200" in r["sample"]
