@@ -80,9 +80,11 @@ constexpr int kWaves = kPool / 64;
 #ifdef GNAV_AXIS_BOXES
 constexpr int kStack = 16;       // block stack of annihilation photons (entries)
 constexpr int kDep = kPool;      // block cache of touchable deposits (direct mapped)
+constexpr int kIntHold = (3 * kPool) / 8;  // interact passes with fewer slots due wait a round
 #else
 constexpr int kStack = 64;
 constexpr int kDep = 4 * kPool;
+constexpr int kIntHold = kPool / 4;
 #endif
 
 // slot status
@@ -772,10 +774,11 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     // ---- interact: photoelectric, Compton, pair ------------------------------
     {
       int n = compact<3>(P, P.status[tid] == kInt, P.aux[tid]);
-      // With under a quarter of the slots due, hold them for one round so the
-      // next pass serves more of them at once; a held track only waits, so
-      // the results do not change.
-      if (n < kPool / 4 && !int_deferred) { int_deferred = true; n = 0; }
+      // With few slots due (under a quarter of the pool, three eighths in the
+      // axis-aligned box build: measured best for each), hold them for one
+      // round so the next pass serves more of them at once; a held track only
+      // waits, so the results do not change.
+      if (n < kIntHold && !int_deferred) { int_deferred = true; n = 0; }
       else int_deferred = false;
       if (tid < n) {
         const int s = P.list[tid];
