@@ -123,6 +123,25 @@ def test_transport_parity_per_track(ctx, torch_dev, oracle_lib, name, n, cap):
     assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
 
 
+@pytest.mark.parametrize("name,n,prim_seed,seed", [("calorimeter", 3000, 5, 3), ("barrel", 2000, 9, 11),
+                                                   ("tiny", 5000, 2, 7)])
+def test_transport_parity_other_seeds(ctx, torch_dev, oracle_lib, name, n, prim_seed, seed):
+    """Other primary sets and other transport streams: per-track parity."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("transport_seeds", name, prim_seed, seed)
+    _, prim, _ = W.WORKLOADS[name](n=n, seed=prim_seed)
+    cap = 512
+    got = run_transport(ctx, torch, gid, prim, cap, seed=seed)
+    ref = og.transport(prim, seed=seed, log_cap=cap)
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, cap)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
+    assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
+
+
 def test_transport_parity_rotated_boxes(ctx, torch_dev, oracle_lib):
     """Boxes placed with rotations run the general kernel (the axis-aligned box
     build serves unrotated boxes only): per-track parity with the oracle."""
