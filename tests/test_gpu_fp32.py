@@ -184,3 +184,28 @@ def test_pure_transport_barrel_deposits(ctx, torch_dev, oracle_lib):
     assert c_ev < 2.0
     assert rel_lv < 0.02
     assert b["counters"]["stuck"] <= 1e-4 * prim.n + 1
+
+
+def test_pure_transport_calorimeter_conserves_energy(ctx, torch_dev, oracle_lib):
+    """Pure FP32 on the calorimeter (the axis-aligned box build's FP32 instantiation):
+    energy conserved per event, nearly every track follows the FP64 volume sequence."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("fp32_pure_calorimeter")
+    _, prim, _ = W.calorimeter(n=4000)
+    cap = 400
+    a = run_transport(ctx, torch, gid, prim, cap)
+    b = run_transport(ctx, torch, gid, prim, cap, precision=PURE)
+    tot = b["edep_event"] + b["escaped_event"]
+    assert np.allclose(tot, prim.energy, rtol=1e-12, atol=0)
+    assert b["counters"]["stuck"] == 0
+    used = np.nonzero(a["log_fate"] != 0)[0]
+    same = 0
+    for slot in used:
+        ka, kb = min(int(a["log_n"][slot]), cap), min(int(b["log_n"][slot]), cap)
+        ta, tb = a["log"][slot, :ka], b["log"][slot, :kb]
+        same += int(a["log_fate"][slot] == b["log_fate"][slot] and
+                    np.array_equal(ta["touchable"], tb["touchable"]) and np.array_equal(ta["code"], tb["code"]))
+    ident = same / len(used)
+    print("pure FP32 calorimeter: identical volume sequences", ident, flush=True)
+    assert ident > 0.95

@@ -77,3 +77,16 @@ def test_autotune_picks_a_setting_and_tuned_runs_match(ctx, torch_dev, oracle_li
     tally.free()
     assert a["counters"] == b["counters"]
     assert np.allclose(a["edep_event"], b["edep_event"], rtol=1e-12, atol=1e-15)
+
+
+def test_bound_order_on_box_geometry_is_identical(ctx, torch_dev, oracle_lib):
+    """The axis-aligned box build's ordered-walk instantiation: identical logs."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("bound_order_boxes")
+    _, prim, _ = W.calorimeter(n=3000)
+    a = run_transport(ctx, torch, gid, prim, 200)
+    b = run_transport(ctx, torch, gid, prim, 200, order=1)
+    assert np.array_equal(a["log_n"], b["log_n"]) and np.array_equal(a["log_fate"], b["log_fate"])
+    for f in ("touchable", "code", "step", "edep", "energy"):
+        assert np.array_equal(a["log"][f], b["log"][f]), f
