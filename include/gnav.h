@@ -24,6 +24,10 @@
  *   message.  Outputs are unspecified after an error.  After GNAV_EHIP the
  *   context should be destroyed.  No exception or abort crosses the ABI.
  *   One context per host thread; calls on one context are not thread safe.
+ *   Transport launches of one context share its work-queue counter and
+ *   pending-photon buffer: a launch (or graph replay) on another stream than
+ *   the context's previous launch first waits, on the device, for that
+ *   launch, so launches of one context never overlap.
  */
 #ifndef GNAV_H
 #define GNAV_H
@@ -58,6 +62,10 @@ typedef int32_t gnav_status;
 /* Surface tolerance (mm): points within half of it of a surface lie on it. */
 #define GNAV_TOLERANCE 1e-9
 
+/* Largest max_steps_per_track of a batch (the per-track step count is kept
+ * in 23 bits). */
+#define GNAV_MAX_STEPS_PER_TRACK 8388607
+
 /* Counter slots returned by gnav_read_tallies. */
 #define GNAV_C_STEPS 0          /* navigation steps (one per transport-loop iteration) */
 #define GNAV_C_PE 1             /* photoelectric absorptions */
@@ -84,6 +92,7 @@ typedef int32_t gnav_status;
 #define GNAV_LIM_PE (-2)
 #define GNAV_LIM_COMPTON (-3)
 #define GNAV_LIM_PAIR (-4)
+#define GNAV_LIM_MAX_STEP (-5)  /* ComputeStep queries: the caller's maximum step was shorter */
 
 /* Track fates in the per-track log. */
 #define GNAV_FATE_ABSORBED 1
@@ -147,42 +156,25 @@ const char* gnav_last_error(const gnav_ctx* ctx);
 /* Validate a geometry, expand its touchables (distinct placement paths,
  * numbered breadth first from the world = 0, children of touchable T at
  * child_base[T] + slot), build voxel grids and attenuation tables, and copy
- * everything to the device (Alg. 2, phase 1).  Several geometries may be
- * resident; each gets an id.  Synchronous.  GNAV_EGEOM on bad parameters,
- * indices or a touchable count above 2^30. */
+ * everything to the device (Alg. 2, phase 1: load the geometry and transfer
+ * it to the GPU once).  Several geometries may be resident; each gets an id.
+ * The copies are ordered on `stream` and the call returns once they are
+ * complete.  Every resident table is reallocated, so graphs captured before
+ * the call become stale (gnav_graph_launch then returns GNAV_ESTATE).
+ * GNAV_EGEOM on bad parameters, indices or a touchable count above 2^30. */
 gnav_status gnav_upload_geometry(gnav_ctx* ctx, const gnav_geometry_desc* desc, int32_t* geom_id,
-                                 int32_t* n_touchables);
+                                 int32_t* n_touchables, void* stream);
 
 /* Host copies of the touchable table of one geometry; each output may be
  * NULL, otherwise it has n_touchables entries. */
 gnav_status gnav_touchables(gnav_ctx* ctx, int32_t geom_id, int32_t* parent, int32_t* pv,
                             int32_t* lv, int32_t* depth);
 
-/* LocateGlobalPoint (Sec. 3.2, first question): the deepest touchable holding
- * each point.  pos_dev [n][3]; dir_dev [n][3] or NULL.  On a surface a point
- * belongs to a volume only when its direction points strictly inward through
- * every face it lies on (without a direction, surface points count as in).
- * touchable_dev [n] receives the per-geometry touchable id, -1 outside. */
-gnav_status gnav_locate(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
-                        const double* dir_dev, int32_t* touchable_dev, void* stream);
-
-/* ComputeStep (Sec. 3.2, second question): distance along dir to the next
- * boundary from each point of its touchable: the smaller of the mother's exit
- * distance and the daughters' entry distances, the mother winning ties, then
- * the lowest daughter slot.  touchable_dev NULL: locate first.  Outputs:
- * step_dev [n] (mm), limiter_dev [n] (GNAV_LIM_MOTHER or the daughter slot),
- * next_touchable_dev [n] (touchable after relocation at the end point, -1 =
- * left the world) which may be NULL. */
-gnav_status gnav_compute_step(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
-                              const double* dir_dev, const int32_t* touchable_dev,
-                              double* step_dev, int32_t* limiter_dev,
-                              int32_t* next_touchable_dev, void* stream);
-
-/* Distance arithmetic of ComputeStep (Sec. 5 names FP64 throughput as a
- * limit of the GPU port).  In both FP32 forms positions, optical depths,
- * point-in-volume decisions, the voxel walk and tallies stay FP64 and the
- * daughter candidates' solid arithmetic runs in FP32 on coordinates local to
- * each candidate.
+/* Distance arithmetic of the navigation queries and of transport (Sec. 5
+ * names FP64 throughput as a limit of the GPU port).  In both FP32 forms
+ * positions, optical depths, point-in-volume decisions, the voxel walk and
+ * tallies stay FP64 and the daughter candidates' solid arithmetic runs in
+ * FP32 on coordinates local to each candidate.
  *   GNAV_PREC_FP64: every distance in FP64.
  *   GNAV_PREC_FP32_SCREENED: FP32 entry distances rank the candidates; the
  *     first is evaluated in FP64, the others in FP64 unless a rigorous FP32
@@ -194,20 +186,84 @@ gnav_status gnav_compute_step(gnav_ctx* ctx, int32_t geom_id, int64_t n, const d
 #define GNAV_PREC_FP32_SCREENED 1
 #define GNAV_PREC_FP32 2
 
-/* ComputeStep at a chosen precision.  Arguments as gnav_compute_step, plus
- * safety_dev [n] (may be NULL): the voxel-limited safety at each point (a
- * lower bound on the distance to any boundary in the FP64 and screened
- * forms, the FP32 value in the GNAV_PREC_FP32 form). */
-gnav_status gnav_compute_step_prec(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
-                                   const double* dir_dev, const int32_t* touchable_dev, int32_t precision,
-                                   double* step_dev, int32_t* limiter_dev, int32_t* next_touchable_dev,
-                                   double* safety_dev, void* stream);
+/* LocateGlobalPoint (Sec. 3.2, first question: which volumes hold a point):
+ * the deepest touchable holding each point.  pos_dev [n][3]; dir_dev [n][3]
+ * or NULL.  On a surface a point belongs to a volume only when its direction
+ * points strictly inward through every face it lies on (without a
+ * direction, surface points count as in).  touchable_dev [n] receives the
+ * per-geometry touchable id, -1 outside.  `precision` is one of GNAV_PREC_*;
+ * point-in-volume decisions are FP64 in every form, so all three give the
+ * same answer. */
+gnav_status gnav_locate(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                        const double* dir_dev, int32_t* touchable_dev, int32_t precision,
+                        void* stream);
+
+/* ComputeStep (Sec. 3.2, second question: where a ray next crosses a volume
+ * boundary): the distance along dir to the next boundary from each point of
+ * its touchable, the smaller of the mother's exit distance and the
+ * daughters' entry distances, the mother winning ties, then the lowest
+ * daughter slot.
+ *   touchable_dev [n] or NULL (locate first, with the direction);
+ *   max_step_dev [n] or NULL (no limit): when max_step <= the geometric
+ *     step, the step is max_step, the limiter GNAV_LIM_MAX_STEP and the next
+ *     touchable the current one (ties go to the caller's limit, as an
+ *     interaction wins a tie with the boundary in transport);
+ *   step_dev [n] (mm, +inf when no boundary lies ahead), limiter_dev [n]
+ *     (GNAV_LIM_MOTHER, a daughter slot >= 0, or GNAV_LIM_MAX_STEP);
+ *   next_touchable_dev [n] or NULL: the touchable after relocation at the
+ *     end point (-1 = left the world);
+ *   precision: GNAV_PREC_*;
+ *   learned: order in which the start voxel node's candidates are examined,
+ *     0 slot order, 1 smallest lower bound first, 2 the network set with
+ *     gnav_set_mlp (GNAV_ESTATE without one); every order gives the same
+ *     results (see gnav_batch.order); 1 and 2 need GNAV_PREC_FP64. */
+gnav_status gnav_compute_step(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                              const double* dir_dev, const int32_t* touchable_dev,
+                              const double* max_step_dev, double* step_dev, int32_t* limiter_dev,
+                              int32_t* next_touchable_dev, int32_t precision, int32_t learned,
+                              void* stream);
+
+/* Validity codes of the surface normal (gnav_step_outputs.normal_valid_dev). */
+#define GNAV_NORMAL_NONE 0  /* no boundary reached: infinite or max-step limited step */
+#define GNAV_NORMAL_FACE 1  /* the end point lies on exactly one face of the crossed solid */
+#define GNAV_NORMAL_EDGE 2  /* it lies on two or more faces (edge or corner): the normal is that
+                               of the face with the largest signed value, lowest face on ties */
+
+/* Outputs of gnav_compute_step_ex: device arrays of n entries. */
+typedef struct {
+  double* step_dev;            /* [n] required */
+  int32_t* limiter_dev;        /* [n] required */
+  int32_t* next_touchable_dev; /* [n] or NULL */
+  double* safety_dev;          /* [n] or NULL: voxel-limited safety at the start point (a lower
+                                  bound on the distance to any boundary in the FP64 and screened
+                                  forms, the FP32 value in the GNAV_PREC_FP32 form) */
+  double* normal_dev;          /* [n][3] or NULL: exit normal of the boundary crossed at the end
+                                  point, global frame, unit length: the outward normal of the
+                                  mother when the mother limits the step, the inward normal of
+                                  the entered daughter otherwise, so it points along the
+                                  direction of travel (the entering normal is its negation);
+                                  (0, 0, 0) with GNAV_NORMAL_NONE */
+  int32_t* normal_valid_dev;   /* [n] or NULL: GNAV_NORMAL_* */
+} gnav_step_outputs;
+
+/* ComputeStep with the outputs above.  The normal answers the second half
+ * of the navigation question of Sec. 3.2 (the normal of the boundary surface
+ * at the crossing point), which the navigator state of Sec. 3.2 also keeps
+ * for the last crossed boundaries.  Arguments as gnav_compute_step. */
+gnav_status gnav_compute_step_ex(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
+                                 const double* dir_dev, const int32_t* touchable_dev,
+                                 const double* max_step_dev, int32_t precision, int32_t learned,
+                                 const gnav_step_outputs* out, void* stream);
 
 /* ComputeSafety: a lower bound >= 0 on the isotropic distance from each point
  * to any boundary of its touchable (mother or daughter), limited to the
- * point's voxel node.  touchable_dev NULL: locate first. */
+ * point's voxel node.  touchable_dev NULL: locate first.  precision
+ * GNAV_PREC_*: FP64 and screened give lower bounds (screened from rigorously
+ * lowered FP32 safeties in nodes of six or more candidates); GNAV_PREC_FP32
+ * gives the FP32 value. */
 gnav_status gnav_compute_safety(gnav_ctx* ctx, int32_t geom_id, int64_t n, const double* pos_dev,
-                                const int32_t* touchable_dev, double* safety_dev, void* stream);
+                                const int32_t* touchable_dev, double* safety_dev, int32_t precision,
+                                void* stream);
 
 /* Free path of Alg. 1 alone, the paper's timed phase (Alg. 2 phase 5, the
  * measurements of Table 1): for each particle i, starting at pos_dev[i] along
@@ -254,7 +310,7 @@ typedef struct {
   int32_t geom_id;
   uint64_t seed;              /* Philox key of the transport stream */
   double e_cut;               /* MeV: photons below it deposit locally and stop */
-  int64_t max_steps_per_track;/* <= 0: 1e6 */
+  int64_t max_steps_per_track;/* <= 0: 1e6; at most GNAV_MAX_STEPS_PER_TRACK (GNAV_EINVAL above) */
   int32_t precision;          /* GNAV_PREC_*; FP32 forms need order 0 and no recorder */
   int32_t block;              /* track-pool slots (= threads) per block: 64, 128 or 256; 0 = 64 */
   int32_t grid;               /* blocks, 0 = library default (fills the device) */
@@ -321,7 +377,13 @@ gnav_status gnav_read_tallies(gnav_ctx* ctx, const gnav_tally* tally, double* ed
  * transport} captured once for a batch description (same device buffers,
  * same tally) and replayed with gnav_graph_launch.  The graph holds only
  * kernel nodes (no memset nodes).  The batch's buffers and the tally must
- * outlive the graph; the call synchronises `stream` while capturing. */
+ * outlive the graph; the call synchronises `stream` while capturing.
+ * The graph also holds the library's geometry tables, its pending-photon
+ * buffer and (order 2) the network's weights: gnav_graph_launch returns
+ * GNAV_ESTATE, without touching the device, once any of them has been
+ * reallocated or unbound since the capture (a later gnav_upload_geometry, a
+ * batch needing a larger grid than any before, gnav_set_mlp or
+ * gnav_mlp_free of the bound network); capture the graph again then. */
 typedef struct gnav_graph gnav_graph;
 gnav_status gnav_graph_create(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally, void* stream,
                               gnav_graph** out);
@@ -352,12 +414,15 @@ gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* mlp, int64_t batch, const 
                              const int32_t* cls_dev, float* logits_dev, void* stream);
 /* Host copy of the float parameters (synchronous). */
 gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* mlp, float* params_host);
+/* Free a network (after the device has passed its last use); every binding
+ * of it made with gnav_set_mlp is dropped. */
 gnav_status gnav_mlp_free(gnav_ctx* ctx, gnav_mlp* mlp);
 
 /* Number of ordering classes (voxelised mothers) of a geometry. */
 gnav_status gnav_ordering_classes(gnav_ctx* ctx, int32_t geom_id, int32_t* n_class);
-/* Use `mlp` (NULL to clear) for order 2 on geometry geom_id; its class count
- * must equal the geometry's.  The network must outlive its use. */
+/* Use `mlp` (NULL to clear) for order 2 on geometry geom_id; the network must
+ * have been created on the same context and its class count must equal the
+ * geometry's.  Batches and graphs read its weights when they run. */
 gnav_status gnav_set_mlp(gnav_ctx* ctx, int32_t geom_id, gnav_mlp* mlp);
 
 /* Total touchables over all resident geometries, and the offset of one

@@ -34,7 +34,7 @@ constexpr int kMaxComptonTrials = 1000;
 
 enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3 };
 enum : int { kOut = -1, kIn = 1 };
-enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4 };
+enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4, kLimMaxStep = -5 };
 
 // Solid info bits: type in the low nibble, then has_inner, has_phi.
 constexpr int kInfoInner = 1 << 4;
@@ -478,6 +478,60 @@ __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<
     if (dv > zero) t = tmin(t, tmax(-k.pb / dv, zero));
   }
   return t;
+}
+
+// ---------------------------------------------------------------------------
+// Surface normal (Sec. 3.2 asks for the normal of the boundary surface at the
+// crossing point).  A solid's signed value is the largest of its components,
+// so at a surface point its outward normal is the gradient of the largest
+// component (the lowest component on ties); components within the tolerance
+// of that largest value also hold the point, and two or more of them mean an
+// edge or a corner.  Returns that count and writes the unit normal in the
+// solid's frame.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3& n) {
+#ifndef GNAV_AXIS_BOXES
+  if ((info & 15) == kOrb) {
+    const double r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+    n = r > 0 ? V3{p.x / r, p.y / r, p.z / r} : V3{0.0, 0.0, 1.0};
+    return 1;
+  }
+  if ((info & 15) != kBox) {
+    const RadComps<double> k = rad_comps(q, info, p);
+    const double c[5] = {k.ro, k.ri, k.z, k.pa, k.pb};
+    int m = 0;
+#pragma unroll
+    for (int i = 1; i < 5; i++)
+      if (c[i] > c[m]) m = i;
+    int faces = 0;
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+      if (c[i] >= c[m] - kTol) faces++;
+    const double rho = sqrt(p.x * p.x + p.y * p.y);
+    const double ux = rho > 0 ? p.x / rho : 1.0, uy = rho > 0 ? p.y / rho : 0.0;
+    switch (m) {
+      case 0: n = V3{ux * q[R_CO], uy * q[R_CO], -q[R_BO] * q[R_CO]}; break;
+      case 1: n = V3{-ux * q[R_CI], -uy * q[R_CI], q[R_BI] * q[R_CI]}; break;
+      case 2: n = V3{0.0, 0.0, p.z < 0 ? -1.0 : 1.0}; break;
+      case 3: n = V3{q[R_NS0], q[R_NS1], 0.0}; break;
+      default: n = V3{q[R_NE0], q[R_NE1], 0.0}; break;
+    }
+    return faces;
+  }
+#endif
+  const double c[3] = {fabs(p.x) - q[0], fabs(p.y) - q[1], fabs(p.z) - q[2]};
+  int m = 0;
+  if (c[1] > c[m]) m = 1;
+  if (c[2] > c[m]) m = 2;
+  int faces = 0;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+    if (c[i] >= c[m] - kTol) faces++;
+  const double pc[3] = {p.x, p.y, p.z};
+  const double sg = pc[m] < 0 ? -1.0 : 1.0;
+  n = V3{m == 0 ? sg : 0.0, m == 1 ? sg : 0.0, m == 2 ? sg : 0.0};
+  return faces;
 }
 
 // ---------------------------------------------------------------------------

@@ -45,17 +45,20 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
-  hipError_t upload(const void* src, size_t n) {
+  // Reallocate to n bytes (at least 8, so empty tables keep a valid
+  // pointer) and fill from host memory src, or with zeros; the copy is
+  // ordered on `stream` (the caller keeps src alive until the stream passes it).
+  hipError_t upload(const void* src, size_t n, hipStream_t stream = nullptr) {
     release();
-    if (n == 0) n = 8;  // keep a valid pointer for empty tables
+    if (n == 0) n = 8;
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
       p = nullptr;
       return e;
     }
     bytes = n;
-    if (src) return hipMemcpy(p, src, n, hipMemcpyHostToDevice);
-    return hipMemset(p, 0, n);
+    if (src) return hipMemcpyAsync(p, src, n, hipMemcpyHostToDevice, stream);
+    return hipMemsetAsync(p, 0, n, stream);
   }
   template <class T>
   T* as() const {
@@ -64,8 +67,8 @@ struct DevBuf {
 };
 
 template <class T>
-hipError_t up(DevBuf& b, const std::vector<T>& v) {
-  return b.upload(v.empty() ? nullptr : v.data(), v.size() * sizeof(T));
+hipError_t up(DevBuf& b, const std::vector<T>& v, hipStream_t stream) {
+  return b.upload(v.empty() ? nullptr : v.data(), v.size() * sizeof(T), stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,6 +552,7 @@ VoxBuild build_voxels(const Box3& mother, const std::vector<DauShape>& dau, bool
 
 struct GeomRec {
   gnav_mlp* mlp = nullptr;  // network for the learned candidate order
+  uint64_t mlp_gen = 0;     // bumped whenever the binding changes
   int t_base, n_t;
   int n_class = 0;  // voxelised mothers (candidate-ordering classes)
   bool axis_boxes = false;  // every solid is a box and every placement a translation
@@ -584,6 +588,15 @@ struct gnav_ctx {
       d_mat_rho, d_geom_tbase;
   DevBuf d_queue, d_pend;
   DevGeom G{};
+  // Generations of what a captured graph holds: the resident tables (every
+  // upload reallocates them) and the pending-photon buffer (reallocated when
+  // a batch needs a larger grid).
+  uint64_t tables_gen = 0, pend_gen = 0;
+  // Launches of one context share d_queue and d_pend: a launch on another
+  // stream than the previous one waits for it on the device.
+  hipEvent_t last_launch = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool launched = false;
   // autotuned launch settings by (geometry, precision, order, log2 of the batch size)
   std::map<std::array<int, 4>, gnav_tuning> tuning;
 };
@@ -612,10 +625,11 @@ gnav_status hip_fail(gnav_ctx* c, hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
   } while (0)
 
-hipError_t upload_all(gnav_ctx* c) {
+hipError_t upload_all(gnav_ctx* c, hipStream_t stream) {
   hipError_t e;
+  c->tables_gen++;
 #define UP(buf, vec) \
-  if ((e = up(c->buf, c->vec)) != hipSuccess) return e;
+  if ((e = up(c->buf, c->vec, stream)) != hipSuccess) return e;
   UP(d_t_rec, t_rec)
   UP(d_t_xf, t_xf)
   UP(d_lv_rec, lv_rec)
@@ -643,7 +657,7 @@ hipError_t upload_all(gnav_ctx* c) {
   G.mat_rho = c->d_mat_rho.as<double>();
   G.lnE0 = c->lnE0;
   G.dlnE = c->dlnE;
-  return hipSuccess;
+  return hipStreamSynchronize(stream);
 }
 
 // Nearest float not above / not below x.
@@ -726,9 +740,17 @@ gnav_status gnav_create(int32_t device, gnav_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
-  if (c->d_queue.upload(nullptr, 64) != hipSuccess) {
+  // the pending-photon buffer sized for the largest default grid (every pool
+  // size fills the same slot count), so default batches never reallocate it
+  const size_t pend_bytes = (size_t)c->n_cu * 3 * 256 * 6 * sizeof(double);
+  if (c->d_queue.upload(nullptr, 64) != hipSuccess || c->d_pend.upload(nullptr, pend_bytes) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     delete c;
     return GNAV_ENOMEM;
+  }
+  if (hipEventCreateWithFlags(&c->last_launch, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return GNAV_EHIP;
   }
   c->lnE0 = std::log(1e-3);
   c->dlnE = std::log(1e5) / 256.0;
@@ -739,13 +761,15 @@ gnav_status gnav_create(int32_t device, gnav_ctx** out) {
 void gnav_destroy(gnav_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->last_launch) (void)hipEventDestroy(ctx->last_launch);
   delete ctx;
 }
 
 const char* gnav_last_error(const gnav_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32_t* geom_id,
-                                 int32_t* n_touchables) {
+                                 int32_t* n_touchables, void* stream) {
   if (!c || !d) return GNAV_EINVAL;
   c->err.clear();
   if (d->n_solids <= 0 || d->n_lv <= 0 || d->n_mats <= 0 || d->n_pv < 0)
@@ -1045,7 +1069,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
   int id = (int)c->geoms.size();
   c->geoms.push_back(std::move(gr));
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-  hipError_t e = upload_all(c);
+  hipError_t e = upload_all(c, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "geometry upload");
   if (geom_id) *geom_id = id;
   if (n_touchables) *n_touchables = nt;
@@ -1066,6 +1090,22 @@ gnav_status gnav_touchables(gnav_ctx* c, int32_t geom_id, int32_t* parent, int32
   return GNAV_OK;
 }
 
+}  // extern "C"
+
+namespace gnav {
+// A network is being freed: unbind it from every geometry of the context.
+void unbind_mlp(gnav_ctx* c, const gnav_mlp* mlp) {
+  if (!c || !mlp) return;
+  for (GeomRec& g : c->geoms)
+    if (g.mlp == mlp) {
+      g.mlp = nullptr;
+      g.mlp_gen++;
+    }
+}
+}  // namespace gnav
+
+extern "C" {
+
 gnav_status gnav_ordering_classes(gnav_ctx* c, int32_t geom_id, int32_t* n_class) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
@@ -1078,9 +1118,11 @@ gnav_status gnav_set_mlp(gnav_ctx* c, int32_t geom_id, gnav_mlp* mlp) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
   MlpView v;
+  if (mlp && mlp_owner(mlp) != c) return fail(c, GNAV_EINVAL, "network belongs to another context");
   if (mlp && (!mlp_view(mlp, &v) || v.n_class != c->geoms[geom_id].n_class))
     return fail(c, GNAV_EINVAL, "network class count differs from the geometry's ordering classes");
   c->geoms[geom_id].mlp = mlp;
+  c->geoms[geom_id].mlp_gen++;
   return GNAV_OK;
 }
 
@@ -1093,34 +1135,64 @@ gnav_status gnav_touchable_offset(gnav_ctx* c, int32_t geom_id, int32_t* offset,
 }
 
 gnav_status gnav_locate(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
-                        int32_t* out, void* stream) {
+                        int32_t* out, int32_t precision, void* stream) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
   if (n < 0 || (n > 0 && (!pos || !out))) return fail(c, GNAV_EINVAL, "bad locate arguments");
+  if (precision < GNAV_PREC_FP64 || precision > GNAV_PREC_FP32) return fail(c, GNAV_EINVAL, "bad precision");
+  // point-in-volume decisions are FP64 in every precision form
   int tb = c->geoms[geom_id].t_base;
   HIP_TRY(c, launch_locate(c->G, tb, tb, n, pos, dir, out, (hipStream_t)stream), "locate launch");
   return GNAV_OK;
 }
 
-gnav_status gnav_compute_step(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
-                              const int32_t* touch, double* step, int32_t* lim, int32_t* next,
-                              void* stream) {
-  return gnav_compute_step_prec(c, geom_id, n, pos, dir, touch, GNAV_PREC_FP64, step, lim, next, nullptr,
-                                stream);
-}
-
-gnav_status gnav_compute_step_prec(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos,
-                                   const double* dir, const int32_t* touch, int32_t precision, double* step,
-                                   int32_t* lim, int32_t* next, double* safety, void* stream) {
+gnav_status gnav_compute_step_ex(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
+                                 const int32_t* touch, const double* max_step, int32_t precision, int32_t learned,
+                                 const gnav_step_outputs* out, void* stream) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
-  if (n < 0 || (n > 0 && (!pos || !dir || !step || !lim))) return fail(c, GNAV_EINVAL, "bad step arguments");
+  if (!out) return fail(c, GNAV_EINVAL, "null output description");
+  if (n < 0 || (n > 0 && (!pos || !dir || !out->step_dev || !out->limiter_dev)))
+    return fail(c, GNAV_EINVAL, "bad step arguments");
   if (precision < GNAV_PREC_FP64 || precision > GNAV_PREC_FP32) return fail(c, GNAV_EINVAL, "bad precision");
-  int tb = c->geoms[geom_id].t_base;
-  HIP_TRY(c, launch_step(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, dir, touch, step, lim, next, safety,
-                         precision, (hipStream_t)stream),
-          "step launch");
+  if (learned < 0 || learned > 2) return fail(c, GNAV_EINVAL, "learned must be 0, 1 or 2");
+  if (learned != 0 && precision != GNAV_PREC_FP64)
+    return fail(c, GNAV_EINVAL, "candidate orders need FP64 distances");
+  const GeomRec& gr = c->geoms[geom_id];
+  StepArgs a{};
+  a.G = c->G;
+  a.W = a.tbase = gr.t_base;
+  a.tcount = gr.n_t;
+  a.n = n;
+  a.pos = pos;
+  a.dir = dir;
+  a.touch = touch;
+  a.max_step = max_step;
+  a.step = out->step_dev;
+  a.lim = out->limiter_dev;
+  a.next = out->next_touchable_dev;
+  a.saf = out->safety_dev;
+  a.normal = out->normal_dev;
+  a.normal_valid = out->normal_valid_dev;
+  int order = learned;
+  if (learned == 2) {
+    if (!gr.mlp || !mlp_view(gr.mlp, &a.mlp) || a.mlp.n_class != gr.n_class)
+      return fail(c, GNAV_ESTATE, "no network (or a class-count mismatch) for the learned order");
+    // with no mother wide enough to order, the network would score nothing
+    if (!gr.any_wide) order = 1;
+  }
+  HIP_TRY(c, launch_step(a, precision, order, (hipStream_t)stream), "step launch");
   return GNAV_OK;
+}
+
+gnav_status gnav_compute_step(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
+                              const int32_t* touch, const double* max_step, double* step, int32_t* lim,
+                              int32_t* next, int32_t precision, int32_t learned, void* stream) {
+  gnav_step_outputs o{};
+  o.step_dev = step;
+  o.limiter_dev = lim;
+  o.next_touchable_dev = next;
+  return gnav_compute_step_ex(c, geom_id, n, pos, dir, touch, max_step, precision, learned, &o, stream);
 }
 
 gnav_status gnav_free_path(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos, const double* dir,
@@ -1138,12 +1210,14 @@ gnav_status gnav_free_path(gnav_ctx* c, int32_t geom_id, int64_t n, const double
 }
 
 gnav_status gnav_compute_safety(gnav_ctx* c, int32_t geom_id, int64_t n, const double* pos,
-                                const int32_t* touch, double* out, void* stream) {
+                                const int32_t* touch, double* out, int32_t precision, void* stream) {
   gnav_status s = check_geom(c, geom_id);
   if (s) return s;
   if (n < 0 || (n > 0 && (!pos || !out))) return fail(c, GNAV_EINVAL, "bad safety arguments");
+  if (precision < GNAV_PREC_FP64 || precision > GNAV_PREC_FP32) return fail(c, GNAV_EINVAL, "bad precision");
   int tb = c->geoms[geom_id].t_base;
-  HIP_TRY(c, launch_safety(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, touch, out, (hipStream_t)stream),
+  HIP_TRY(c, launch_safety(c->G, tb, tb, c->geoms[geom_id].n_t, n, pos, touch, out, precision,
+                           (hipStream_t)stream),
           "safety launch");
   return GNAV_OK;
 }
@@ -1160,7 +1234,8 @@ gnav_status gnav_tally_create(gnav_ctx* c, int32_t n_events, gnav_tally** out) {
   if ((e = t->edep_t.upload(nullptr, sizeof(double) * t->n_touch)) != hipSuccess ||
       (e = t->edep_ev.upload(nullptr, sizeof(double) * (size_t)n_events)) != hipSuccess ||
       (e = t->esc_ev.upload(nullptr, sizeof(double) * (size_t)n_events)) != hipSuccess ||
-      (e = t->counters.upload(nullptr, sizeof(unsigned long long) * GNAV_NCOUNTERS)) != hipSuccess) {
+      (e = t->counters.upload(nullptr, sizeof(unsigned long long) * GNAV_NCOUNTERS)) != hipSuccess ||
+      (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
     delete t;
     return hip_fail(c, e, "tally allocation");
   }
@@ -1225,6 +1300,8 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
     return fail(c, GNAV_EINVAL, "log buffers incomplete");
   if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
+  if (b->max_steps_per_track > GNAV_MAX_STEPS_PER_TRACK)
+    return fail(c, GNAV_EINVAL, "max_steps_per_track above GNAV_MAX_STEPS_PER_TRACK");
   int grid_req = b->grid, chunk_req = b->chunk, sort_req = b->sort_period, block_req = b->block;
   if (b->tuned) {
     auto it = c->tuning.find(tuning_key(b));
@@ -1265,8 +1342,10 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   // per-slot storage for the second annihilation photon of a pair conversion
   size_t pend_bytes = (size_t)grid * block * 6 * sizeof(double);
   if (c->d_pend.bytes < pend_bytes) {
+    HIP_TRY(c, hipDeviceSynchronize(), "synchronize");
+    HIP_TRY(c, c->d_pend.upload(nullptr, pend_bytes, stream), "pending-photon buffer");
     HIP_TRY(c, hipStreamSynchronize(stream), "synchronize");
-    HIP_TRY(c, c->d_pend.upload(nullptr, pend_bytes), "pending-photon buffer");
+    c->pend_gen++;
   }
   L.pend = c->d_pend.as<double>();
   L.count = b->count_work != 0;
@@ -1309,7 +1388,45 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
 struct gnav_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // what the captured kernels hold, checked before every replay
+  const gnav_ctx* ctx = nullptr;
+  uint64_t tables_gen = 0, pend_gen = 0, mlp_gen = 0;
+  int geom_id = -1;
+  bool uses_mlp = false;
 };
+
+namespace {
+
+// Order a launch of context c on `stream` after the context's previous
+// launch when that one went to another stream (launches share the work
+// queue and the pending-photon buffer), then remember this one.  A stream
+// under capture is left alone: a captured launch is ordered when the graph is
+// replayed (gnav_graph_launch applies the same rule).
+hipError_t order_before(gnav_ctx* c, hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+  if (c->launched && stream != c->last_stream) {
+    e = hipStreamWaitEvent(stream, c->last_launch, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t order_after(gnav_ctx* c, hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+  e = hipEventRecord(c->last_launch, stream);
+  if (e != hipSuccess) return e;
+  c->last_stream = stream;
+  c->launched = true;
+  return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1317,7 +1434,9 @@ gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t
   TransportLaunch L;
   gnav_status s = prepare_transport(c, b, t, (hipStream_t)stream, &L);
   if (s) return s;
+  HIP_TRY(c, order_before(c, (hipStream_t)stream), "stream ordering");
   HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");
+  HIP_TRY(c, order_after(c, (hipStream_t)stream), "stream ordering");
   return GNAV_OK;
 }
 
@@ -1366,6 +1485,7 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
   if (batch->log_dev || batch->record_dev)
     return fail(c, GNAV_EINVAL, "tune without the per-track log or the recorder");
   hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, order_before(c, st), "stream ordering");
   gnav_batch b = *batch;
   b.tuned = 0;
   // coordinate descent: block (pool size) with its default grid, then grid,
@@ -1419,6 +1539,7 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
     if ((s = consider(cand))) return s;
   }
   if ((s = gnav_tally_reset(c, t, st))) return s;
+  HIP_TRY(c, order_after(c, st), "stream ordering");
   HIP_TRY(c, hipStreamSynchronize(st), "synchronize");
   c->tuning[tuning_key(&b)] = best;
   if (out) *out = best;
@@ -1453,6 +1574,12 @@ gnav_status gnav_graph_create(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, v
         : e5 != hipSuccess ? e5 : ee;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  g->ctx = c;
+  g->tables_gen = c->tables_gen;
+  g->pend_gen = c->pend_gen;
+  g->geom_id = b->geom_id;
+  g->uses_mlp = L.order == kOrderLearned;
+  g->mlp_gen = c->geoms[b->geom_id].mlp_gen;
   (void)hipStreamDestroy(cap);
   if (e != hipSuccess) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -1466,7 +1593,17 @@ gnav_status gnav_graph_create(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, v
 
 gnav_status gnav_graph_launch(gnav_ctx* c, gnav_graph* g, void* stream) {
   if (!c || !g) return GNAV_EINVAL;
-  HIP_TRY(c, hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+  if (g->ctx != c) return fail(c, GNAV_EINVAL, "graph belongs to another context");
+  if (g->tables_gen != c->tables_gen)
+    return fail(c, GNAV_ESTATE, "geometry tables were reallocated after the capture (capture again)");
+  if (g->pend_gen != c->pend_gen)
+    return fail(c, GNAV_ESTATE, "pending-photon buffer was reallocated after the capture (capture again)");
+  if (g->uses_mlp && g->mlp_gen != c->geoms[g->geom_id].mlp_gen)
+    return fail(c, GNAV_ESTATE, "network binding changed after the capture (capture again)");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, order_before(c, st), "stream ordering");
+  HIP_TRY(c, hipGraphLaunch(g->exec, st), "graph launch");
+  HIP_TRY(c, order_after(c, st), "stream ordering");
   return GNAV_OK;
 }
 

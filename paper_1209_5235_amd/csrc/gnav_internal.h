@@ -62,14 +62,34 @@ struct TransportLaunch {
 };
 
 bool mlp_view(const gnav_mlp* m, MlpView* out);
+const gnav_ctx* mlp_owner(const gnav_mlp* m);
+// Drop every binding of `mlp` in context c (the network is being freed).
+void unbind_mlp(gnav_ctx* c, const gnav_mlp* mlp);
 
 hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const double* pos,
                          const double* dir, int* out, hipStream_t st);
-hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                       const double* dir, const int* touch, double* step, int* lim, int* next, double* saf,
-                       int prec, hipStream_t st);
+// One ComputeStep query launch (gnav_compute_step_ex): n queries of one
+// geometry whose world touchable is W (= tbase) with tcount touchables.
+struct StepArgs {
+  DevGeom G;
+  int W, tbase, tcount;
+  long n;
+  const double* pos;
+  const double* dir;
+  const int* touch;         // per-geometry touchable ids, or null: locate first
+  const double* max_step;   // or null
+  double* step;
+  int* lim;
+  int* next;                // or null
+  double* saf;              // or null
+  double* normal;           // [n][3] or null
+  int* normal_valid;        // or null
+  MlpView mlp;              // order 2 only
+};
+
+hipError_t launch_step(const StepArgs& a, int prec, int order, hipStream_t st);
 hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                         const int* touch, double* out, hipStream_t st);
+                         const int* touch, double* out, int prec, hipStream_t st);
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);
 // the transport kernel built for track pools of 64, 128 and 256 slots
 hipError_t launch_transport_pool64(const TransportLaunch& L, hipStream_t st);

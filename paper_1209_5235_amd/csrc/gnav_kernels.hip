@@ -7,6 +7,7 @@
 
 #include "gnav_device.h"
 #include "gnav_internal.h"
+#include "gnav_learned.h"
 #include "gnav_physics.h"
 
 namespace gnav {
@@ -28,44 +29,121 @@ __global__ void __launch_bounds__(256) k_locate(DevGeom G, int W, int tbase, lon
   out[i] = T < 0 ? -1 : T - tbase;
 }
 
-template <int PREC>
-__global__ void __launch_bounds__(256) k_step(DevGeom G, int W, int tbase, int tcount, long n,
-                                              const double* pos, const double* dir, const int* touch,
-                                              double* step, int* lim_out, int* next, double* saf_out) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Exit normal at the end point q (global) of a step from touchable T that
+// ended on the boundary of the mother (lim < 0) or of daughter slot lim: the
+// outward normal of the mother, or the inward normal of the entered daughter,
+// rotated to the global frame (the world->local maps are rotations, so a
+// direction returns through the transposed matrix).
+__device__ __forceinline__ int exit_normal(const DevGeom& G, int T, const TRec& tr, int lim, V3 q, V3& ng) {
+  const int S = lim >= 0 ? tr.child_base + lim : T;
+  const TRec ts = lim >= 0 ? G.t[S] : tr;
+  const LRec& L = G.lv[ts.lv];
+  V3 ql, dummy;
+  touchable_frame(G, S, trec_kind(ts), q, V3{0.0, 0.0, 1.0}, ql, dummy);
+  V3 nl;
+  const int faces = solid_normal(L.info, L.par, ql, nl);
+  if (lim >= 0) nl = V3{-nl.x, -nl.y, -nl.z};
+  if (trec_kind(ts) == 0) {
+    ng = nl;
+  } else {
+    const double* m = G.t_xf + (size_t)S * 12;
+    ng = V3{m[0] * nl.x + m[3] * nl.y + m[6] * nl.z, m[1] * nl.x + m[4] * nl.y + m[7] * nl.z,
+            m[2] * nl.x + m[5] * nl.y + m[8] * nl.z};
+  }
+  return faces > 1 ? GNAV_NORMAL_EDGE : GNAV_NORMAL_FACE;
+}
+
+// ComputeStep queries, one per thread (256 per block).  With the learned
+// order every thread first gathers its features into LDS and the block
+// scores all of them on MFMA (rows of threads without a voxelised mother
+// are scored too and ignored), so no thread may leave before that.
+template <int PREC, int ORDER>
+__global__ void __launch_bounds__(256) k_step(StepArgs a) {
+  const DevGeom& G = a.G;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < a.n;
   NavCount<false> nc;
-  V3 p{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-  V3 v{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
-  int T = touch ? ((touch[i] < 0 || touch[i] >= tcount) ? -1 : touch[i] + tbase)
-                : locate(G, W, p, true, v, nc);
+  V3 p{0.0, 0.0, 0.0}, v{0.0, 0.0, 1.0};
+  int T = -1;
+  if (act) {
+    p = V3{a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2]};
+    v = V3{a.dir[3 * i], a.dir[3 * i + 1], a.dir[3 * i + 2]};
+    if (a.touch) T = (a.touch[i] < 0 || a.touch[i] >= a.tcount) ? -1 : a.touch[i] + a.tbase;
+    else T = locate(G, a.W, p, true, v, nc);
+  }
+  TRec tr{0, -1, 0, 0};
+  V3 pl{0.0, 0.0, 0.0}, vl{0.0, 0.0, 1.0};
+  if (T >= 0) {
+    tr = G.t[T];
+    touchable_frame(G, T, trec_kind(tr), p, v, pl, vl);
+  }
+  int pred = -1;
+  if constexpr (ORDER == kOrderLearned) {
+    __shared__ uint16_t xf[256][6];
+    __shared__ uint16_t cls[256];
+    const int t = threadIdx.x;
+    bool elig = false;
+    if (T >= 0) {
+      const LRec& L = G.lv[tr.lv];
+      elig = L.lclass >= 0 && L.wide && L.dau_cnt > 0;
+    }
+    if (elig) {
+      learned_features(G.lv[tr.lv], pl, vl, a.mlp.n_class, xf[t], &cls[t]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; k++) xf[t][k] = 0;
+      cls[t] = 0;
+    }
+    if (__syncthreads_or(elig)) {
+      learned_predict<4>(a.mlp, xf, cls, 256);
+      __syncthreads();
+      if (elig) pred = cls[t];
+    }
+  }
+  if (!act) return;
   if (T < 0) {
-    step[i] = kInf;
-    lim_out[i] = kLimMother;
-    if (next) next[i] = -1;
-    if (saf_out) saf_out[i] = 0.0;
+    a.step[i] = kInf;
+    a.lim[i] = kLimMother;
+    if (a.next) a.next[i] = -1;
+    if (a.saf) a.saf[i] = 0.0;
+    if (a.normal) a.normal[3 * i] = a.normal[3 * i + 1] = a.normal[3 * i + 2] = 0.0;
+    if (a.normal_valid) a.normal_valid[i] = GNAV_NORMAL_NONE;
     return;
   }
-  TRec tr = G.t[T];
-  V3 pl, vl;
-  touchable_frame(G, T, trec_kind(tr), p, v, pl, vl);
   int lim;
   double saf;
-  double s = compute_step_p<false, kOrderPlain, PREC>(G, G.lv[tr.lv], tr.lv, pl, vl, lim, saf, nc, -1,
-                                                      nullptr);
-  step[i] = s;
-  lim_out[i] = lim;
-  if (saf_out) saf_out[i] = saf;
-  if (next) {
-    int nt = -1;
-    if (s < kInf) {
-      V3 q{p.x + s * v.x, p.y + s * v.y, p.z + s * v.z};
-      nt = relocate(G, T, tr, q, v, lim, nc);
+  double s = compute_step_p<false, ORDER, PREC>(G, G.lv[tr.lv], tr.lv, pl, vl, lim, saf, nc, pred, nullptr);
+  if (a.max_step) {
+    double ms = a.max_step[i];
+    if (ms < 0.0) ms = 0.0;
+    if (ms <= s) {  // false for NaN: no limit
+      s = ms;
+      lim = kLimMaxStep;
     }
-    next[i] = nt < 0 ? -1 : nt - tbase;
+  }
+  a.step[i] = s;
+  a.lim[i] = lim;
+  if (a.saf) a.saf[i] = saf;
+  const bool crossed = lim != kLimMaxStep && s < kInf;
+  const V3 q{p.x + s * v.x, p.y + s * v.y, p.z + s * v.z};
+  if (a.next) {
+    int nt = T;
+    if (lim != kLimMaxStep) nt = crossed ? relocate(G, T, tr, q, v, lim, nc) : -1;
+    a.next[i] = nt < 0 ? -1 : nt - a.tbase;
+  }
+  if (a.normal || a.normal_valid) {
+    V3 ng{0.0, 0.0, 0.0};
+    const int code = crossed ? exit_normal(G, T, tr, lim, q, ng) : GNAV_NORMAL_NONE;
+    if (a.normal) {
+      a.normal[3 * i] = ng.x;
+      a.normal[3 * i + 1] = ng.y;
+      a.normal[3 * i + 2] = ng.z;
+    }
+    if (a.normal_valid) a.normal_valid[i] = code;
   }
 }
 
+template <int PREC>
 __global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int tcount, long n,
                                                 const double* pos, const int* touch, double* out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,7 +163,7 @@ __global__ void __launch_bounds__(256) k_safety(DevGeom G, int W, int tbase, int
   int lim;
   double saf;
   // the safety comes from the start node of a step walk along any direction
-  compute_step(G, G.lv[tr.lv], pl, vl, lim, saf, nc);
+  compute_step_p<false, kOrderPlain, PREC>(G, G.lv[tr.lv], tr.lv, pl, vl, lim, saf, nc, -1, nullptr);
   out[i] = saf;
 }
 
@@ -165,28 +243,27 @@ hipError_t launch_locate(const DevGeom& G, int W, int tbase, long n, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_step(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                       const double* dir, const int* touch, double* step, int* lim, int* next, double* saf,
-                       int prec, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  dim3 grid(grid_for(n, 256)), block(256);
-  if (prec == kPrecScreened)
-    hipLaunchKernelGGL(k_step<kPrecScreened>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch,
-                       step, lim, next, saf);
-  else if (prec == kPrecPure)
-    hipLaunchKernelGGL(k_step<kPrecPure>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch, step,
-                       lim, next, saf);
-  else
-    hipLaunchKernelGGL(k_step<kPrecFP64>, grid, block, 0, st, G, W, tbase, tcount, n, pos, dir, touch, step,
-                       lim, next, saf);
+hipError_t launch_step(const StepArgs& a, int prec, int order, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  dim3 grid(grid_for(a.n, 256)), block(256);
+  if (prec == kPrecScreened) hipLaunchKernelGGL((k_step<kPrecScreened, kOrderPlain>), grid, block, 0, st, a);
+  else if (prec == kPrecPure) hipLaunchKernelGGL((k_step<kPrecPure, kOrderPlain>), grid, block, 0, st, a);
+  else if (order == kOrderBound) hipLaunchKernelGGL((k_step<kPrecFP64, kOrderBound>), grid, block, 0, st, a);
+  else if (order == kOrderLearned) hipLaunchKernelGGL((k_step<kPrecFP64, kOrderLearned>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_step<kPrecFP64, kOrderPlain>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_safety(const DevGeom& G, int W, int tbase, int tcount, long n, const double* pos,
-                         const int* touch, double* out, hipStream_t st) {
+                         const int* touch, double* out, int prec, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_safety, dim3(grid_for(n, 256)), dim3(256), 0, st, G, W, tbase, tcount, n, pos, touch,
-                     out);
+  dim3 grid(grid_for(n, 256)), block(256);
+  if (prec == kPrecScreened)
+    hipLaunchKernelGGL(k_safety<kPrecScreened>, grid, block, 0, st, G, W, tbase, tcount, n, pos, touch, out);
+  else if (prec == kPrecPure)
+    hipLaunchKernelGGL(k_safety<kPrecPure>, grid, block, 0, st, G, W, tbase, tcount, n, pos, touch, out);
+  else
+    hipLaunchKernelGGL(k_safety<kPrecFP64>, grid, block, 0, st, G, W, tbase, tcount, n, pos, touch, out);
   return hipGetLastError();
 }
 

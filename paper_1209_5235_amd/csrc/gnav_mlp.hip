@@ -247,6 +247,7 @@ using namespace gnav;
 // ---------------------------------------------------------------------------
 
 struct gnav_mlp {
+  gnav_ctx* owner = nullptr;  // the context that created it (its bindings live there)
   int n_class = 0, max_batch = 0;
   long n_params = 0;
   long o_w1x, o_w1m, o_b1, o_w2, o_b2, o_w3, o_b3;
@@ -276,6 +277,8 @@ struct gnav_mlp {
 };
 
 namespace gnav {
+const gnav_ctx* mlp_owner(const gnav_mlp* q) { return q ? q->owner : nullptr; }
+
 bool mlp_view(const gnav_mlp* q, MlpView* v) {
   if (!q || !v) return false;
   v->w1x = q->pb + q->o_w1x;
@@ -408,6 +411,7 @@ gnav_status gnav_mlp_create(gnav_ctx* ctx, int32_t n_class, int32_t max_batch, c
   *out = nullptr;
   gnav_mlp* q = new (std::nothrow) gnav_mlp();
   if (!q) return GNAV_ENOMEM;
+  q->owner = ctx;
   q->n_class = n_class;
   q->max_batch = max_batch;
   long o = 0;
@@ -502,6 +506,7 @@ gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* q, float* params_host) 
 gnav_status gnav_mlp_free(gnav_ctx* ctx, gnav_mlp* q) {
   if (!ctx) return GNAV_EINVAL;
   (void)hipDeviceSynchronize();
+  if (q) gnav::unbind_mlp(q->owner, q);
   delete q;
   return GNAV_OK;
 }

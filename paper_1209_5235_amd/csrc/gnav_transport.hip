@@ -20,6 +20,7 @@
 
 #include "gnav_device.h"
 #include "gnav_internal.h"
+#include "gnav_learned.h"
 #include "gnav_physics.h"
 
 #ifndef GNAV_POOL
@@ -208,131 +209,13 @@ __device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Learned order: one wave scores up to 64 queued steps with the network on
-// bf16 MFMA (v_mfma_f32_16x16x16_bf16, float accumulation), 16 queries per
-// M tile.  Per lane l: A rows m = l % 16, k = 4 (l / 16) + 0..3; B columns
-// n = l % 16, same k; D columns n = l % 16, rows 4 (l / 16) + 0..3.  Hidden
-// activations pass through a per-wave LDS tile [16][128] bf16; the logits
-// reuse it as [16][64] float.  The predicted position is the argmax.
-// ---------------------------------------------------------------------------
-
-typedef short lbf16x4 __attribute__((ext_vector_type(4)));
-typedef float lf32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t lf2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float lbf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-
+// Learned order: the block gathers the features of its eligible steps here
+// and the network (gnav_learned.h) writes each step's predicted candidate
+// position over its class.
 struct LearnScratch {
   uint16_t xf[kPool][6];  // bf16 features of the listed steps (mother-frame point, direction)
   uint16_t cls[kPool];    // their ordering classes in, the predicted candidate positions out
 };
-
-// Four consecutive bf16 values as one MFMA operand (8-byte aligned loads).
-__device__ __forceinline__ lbf16x4 load_bf16x4(const uint16_t* p) {
-  return *reinterpret_cast<const lbf16x4*>(p);
-}
-
-// Scores the n listed steps whose features are in S.xf / S.cls and writes the
-// highest-scoring candidate position over each step's class in S.cls.
-//
-// Each wave takes 16 steps at a time and computes every layer transposed,
-// H^T = W X^T: the weights are the A operand (row = output unit l % 16,
-// k = 4 (l / 16) + 0..3) and the activations the B operand (column = step
-// l % 16, same k).  The accumulator of output tile t then holds, per lane,
-// units 16 t + 4 (l / 16) + 0..3 of step l % 16, which is exactly the B
-// operand of the next layer's k-slice t: activations stay in registers.
-//
-// Kept out of line (the MFMA operands would otherwise raise the register
-// count of the whole loop); it takes the weights by value so that the
-// kernel's argument block is never addressed from the call.
-__device__ __attribute__((noinline)) void learned_predict(const MlpView M, LearnScratch& S, int n) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  for (int row0 = 16 * w; row0 < n; row0 += 16 * kWaves) {
-    const int li = row0 + r;
-    const bool valid = li < n;
-    const int cls = valid ? S.cls[li] : 0;
-    // layer 1: K = 6 inputs padded to 16; + W1m[class] + b1, ReLU
-    lbf16x4 x;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int k = 4 * q + j;
-      x[j] = (short)(k < 6 && valid ? S.xf[li][k] : 0);
-    }
-    lbf16x4 h1[8];
-#pragma unroll
-    for (int t = 0; t < 8; t++) {
-      lbf16x4 wa;
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int k = 4 * q + j;
-        wa[j] = (short)(k < 6 ? M.w1x[(16 * t + r) * 6 + k] : 0);
-      }
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, x, acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int u = 16 * t + 4 * q + j;
-        const float v = acc[j] + lbf2f(M.w1m[(long)cls * 128 + u]) + M.b1[u];
-        h1[t][j] = (short)lf2bf(v > 0.f ? v : 0.f);
-      }
-    }
-    // layer 2 + b2, ReLU (each tile's eight A operands loaded before its MFMA chain)
-    lbf16x4 h2[8];
-#pragma unroll
-    for (int t = 0; t < 8; t++) {
-      lbf16x4 wa[8];
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w2 + (16 * t + r) * 128 + 16 * kt + 4 * q);
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h1[kt], acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const float v = acc[j] + M.b2[16 * t + 4 * q + j];
-        h2[t][j] = (short)lf2bf(v > 0.f ? v : 0.f);
-      }
-    }
-    // layer 3 + b3: 64 logits; this lane holds candidates 16 t + 4 q + j
-    float best_v = 0.f;
-    int best_c = -1;
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      lbf16x4 wa[8];
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w3 + (16 * t + r) * 128 + 16 * kt + 4 * q);
-      lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h2[kt], acc, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int c = 16 * t + 4 * q + j;
-        const float v = acc[j] + M.b3[c];
-        if (best_c < 0 || v > best_v) {  // candidates arrive in increasing order
-          best_v = v;
-          best_c = c;
-        }
-      }
-    }
-    // highest logit over the four lanes of the step; the lowest position on ties
-#pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
-      const float ov = __shfl_xor(best_v, off);
-      const int oc = __shfl_xor(best_c, off);
-      if (ov > best_v || (ov == best_v && oc < best_c)) {
-        best_v = ov;
-        best_c = oc;
-      }
-    }
-    if (q == 0 && valid) S.cls[li] = (uint16_t)best_c;
-  }
-}
 
 template <bool LOG, bool COUNT, int ORDER, int PREC>
 __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
@@ -598,24 +481,13 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         if (tid < n) {
           const int s = P.list[tid];
           const int lvk = P.lvk[s];
-          const LRec& L = G.lv[lvk >> 1];
           V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
           V3 pl, vl;
           touchable_frame(G, P.T[s], lvk & 1, x, v, pl, vl);
-          const double pc[3] = {pl.x, pl.y, pl.z};
-#pragma unroll
-          for (int ax = 0; ax < 3; ax++) {
-            double half = 0.5 * L.n[ax] * L.vw[ax];
-            S.xf[tid][ax] = lf2bf((float)((pc[ax] - (L.vlo[ax] + half)) / half));
-          }
-          S.xf[tid][3] = lf2bf((float)vl.x);
-          S.xf[tid][4] = lf2bf((float)vl.y);
-          S.xf[tid][5] = lf2bf((float)vl.z);
-          const int c = L.lclass;
-          S.cls[tid] = (uint16_t)(c < 0 ? 0 : (c >= a.mlp.n_class ? a.mlp.n_class - 1 : c));
+          learned_features(G.lv[lvk >> 1], pl, vl, a.mlp.n_class, S.xf[tid], &S.cls[tid]);
         }
         __syncthreads();
-        learned_predict(a.mlp, S, n);
+        learned_predict<kWaves>(a.mlp, S.xf, S.cls, n);
         __syncthreads();
         if (tid < n) P.pred[P.list[tid]] = S.cls[tid];
       }

@@ -27,6 +27,8 @@ COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", 
             "invalid", "dist_in_f32"]
 # distance arithmetic of ComputeStep (GNAV_PREC_*)
 PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
+LIM_MOTHER, LIM_PE, LIM_COMPTON, LIM_PAIR, LIM_MAX_STEP = -1, -2, -3, -4, -5
+NORMAL_NONE, NORMAL_FACE, NORMAL_EDGE = 0, 1, 2
 NCOUNTERS = len(COUNTERS)
 LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
                       ("edep", np.float64), ("energy", np.float64)])
@@ -62,6 +64,12 @@ class gnav_batch(C.Structure):
     ]
 
 
+class gnav_step_outputs(C.Structure):
+    _fields_ = [("step_dev", C.c_void_p), ("limiter_dev", C.c_void_p),
+                ("next_touchable_dev", C.c_void_p), ("safety_dev", C.c_void_p),
+                ("normal_dev", C.c_void_p), ("normal_valid_dev", C.c_void_p)]
+
+
 class gnav_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("grid", C.c_int32), ("chunk", C.c_int32),
                 ("sort_period", C.c_int32), ("ms", C.c_float)]
@@ -77,14 +85,15 @@ def _load():
         "gnav_create": ([C.c_int32, C.POINTER(P)], C.c_int32),
         "gnav_destroy": ([P], None),
         "gnav_last_error": ([P], C.c_char_p),
-        "gnav_upload_geometry": ([P, C.POINTER(gnav_geometry_desc), _i32p, _i32p], C.c_int32),
+        "gnav_upload_geometry": ([P, C.POINTER(gnav_geometry_desc), _i32p, _i32p, P], C.c_int32),
         "gnav_touchables": ([P, C.c_int32, P, P, P, P], C.c_int32),
         "gnav_touchable_offset": ([P, C.c_int32, _i32p, _i32p], C.c_int32),
-        "gnav_locate": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
-        "gnav_compute_step": ([P, C.c_int32, C.c_int64, P, P, P, P, P, P, P], C.c_int32),
-        "gnav_compute_step_prec": ([P, C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P, P, P, P],
-                                   C.c_int32),
-        "gnav_compute_safety": ([P, C.c_int32, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_locate": ([P, C.c_int32, C.c_int64, P, P, P, C.c_int32, P], C.c_int32),
+        "gnav_compute_step": ([P, C.c_int32, C.c_int64, P, P, P, P, P, P, P, C.c_int32, C.c_int32, P],
+                              C.c_int32),
+        "gnav_compute_step_ex": ([P, C.c_int32, C.c_int64, P, P, P, P, C.c_int32, C.c_int32,
+                                  C.POINTER(gnav_step_outputs), P], C.c_int32),
+        "gnav_compute_safety": ([P, C.c_int32, C.c_int64, P, P, P, C.c_int32, P], C.c_int32),
         "gnav_free_path": ([P, C.c_int32, C.c_int64, P, P, P, C.c_double, C.c_double, P, P, P],
                            C.c_int32),
         "gnav_tally_create": ([P, C.c_int32, C.POINTER(P)], C.c_int32),
@@ -125,7 +134,7 @@ gnav_touchables = lib.gnav_touchables
 gnav_touchable_offset = lib.gnav_touchable_offset
 gnav_locate = lib.gnav_locate
 gnav_compute_step = lib.gnav_compute_step
-gnav_compute_step_prec = lib.gnav_compute_step_prec
+gnav_compute_step_ex = lib.gnav_compute_step_ex
 gnav_compute_safety = lib.gnav_compute_safety
 gnav_free_path = lib.gnav_free_path
 gnav_tally_create = lib.gnav_tally_create
@@ -197,7 +206,7 @@ class Context:
             msg = gnav_last_error(self.h).decode(errors="replace")
             raise GnavError(f"{what}: {STATUS.get(st, st)}: {msg}")
 
-    def upload_geometry(self, desc, voxel_lists=0):
+    def upload_geometry(self, desc, voxel_lists=0, stream=None):
         """Upload a workloads.GeometryDesc; returns (geom_id, n_touchables).  voxel_lists 0:
         shape-aware node lists, 1: bounding-box lists (gnav_geometry_desc.voxel_lists)."""
         arrs = dict(
@@ -225,8 +234,8 @@ class Context:
             int(desc.world_lv), int(voxel_lists))
         gid = C.c_int32()
         nt = C.c_int32()
-        self._check(gnav_upload_geometry(self.h, C.byref(d), C.byref(gid), C.byref(nt)),
-                    "gnav_upload_geometry")
+        self._check(gnav_upload_geometry(self.h, C.byref(d), C.byref(gid), C.byref(nt),
+                                         _stream(stream)), "gnav_upload_geometry")
         self.geoms.append((desc, nt.value))
         return gid.value, nt.value
 
@@ -243,37 +252,48 @@ class Context:
                     "gnav_touchable_offset")
         return off.value, tot.value
 
-    def locate(self, geom_id, pos, dirs=None, out=None, stream=None):
+    def locate(self, geom_id, pos, dirs=None, out=None, stream=None, precision=0):
         import torch
         n = pos.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=pos.device)
-        self._check(gnav_locate(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(out), _stream(stream)),
-                    "gnav_locate")
+        self._check(gnav_locate(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(out), int(precision),
+                                _stream(stream)), "gnav_locate")
         return out
 
     def compute_step(self, geom_id, pos, dirs, touch=None, with_next=True, stream=None, precision=0,
-                     with_safety=False):
-        """gnav_compute_step (FP64) or gnav_compute_step_prec; returns (step, limiter, next)
-        plus the safety when with_safety."""
+                     with_safety=False, max_step=None, learned=0, with_normal=False):
+        """gnav_compute_step, or gnav_compute_step_ex when the safety or the normal is wanted;
+        returns (step, limiter, next) followed by the safety when with_safety and by
+        (normal [n][3], normal_valid) when with_normal."""
         import torch
         n = pos.shape[0]
         step = torch.empty(n, dtype=torch.float64, device=pos.device)
         lim = torch.empty(n, dtype=torch.int32, device=pos.device)
         nxt = torch.empty(n, dtype=torch.int32, device=pos.device) if with_next else None
         saf = torch.empty(n, dtype=torch.float64, device=pos.device) if with_safety else None
-        if precision == PREC_FP64 and not with_safety:
+        nrm = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if with_normal else None
+        nval = torch.empty(n, dtype=torch.int32, device=pos.device) if with_normal else None
+        if not with_safety and not with_normal:
             self._check(gnav_compute_step(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
-                                          _ptr(step), _ptr(lim), _ptr(nxt), _stream(stream)),
+                                          _ptr(max_step), _ptr(step), _ptr(lim), _ptr(nxt),
+                                          int(precision), int(learned), _stream(stream)),
                         "gnav_compute_step")
         else:
-            self._check(gnav_compute_step_prec(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
-                                               int(precision), _ptr(step), _ptr(lim), _ptr(nxt),
-                                               _ptr(saf), _stream(stream)),
-                        "gnav_compute_step_prec")
+            out = gnav_step_outputs(step.data_ptr(), lim.data_ptr(),
+                                    nxt.data_ptr() if nxt is not None else None,
+                                    saf.data_ptr() if saf is not None else None,
+                                    nrm.data_ptr() if nrm is not None else None,
+                                    nval.data_ptr() if nval is not None else None)
+            self._check(gnav_compute_step_ex(self.h, geom_id, n, _ptr(pos), _ptr(dirs), _ptr(touch),
+                                             _ptr(max_step), int(precision), int(learned),
+                                             C.byref(out), _stream(stream)), "gnav_compute_step_ex")
+        res = (step, lim, nxt)
         if with_safety:
-            return step, lim, nxt, saf
-        return step, lim, nxt
+            res = res + (saf,)
+        if with_normal:
+            res = res + (nrm, nval)
+        return res
 
     def free_path(self, geom_id, pos, dirs, life, energy=1.0, mu_mass=0.0, stream=None):
         """gnav_free_path: first interaction distances T and boundaries crossed."""
@@ -285,12 +305,12 @@ class Context:
                                    float(mu_mass), _ptr(t), _ptr(nb), _stream(stream)), "gnav_free_path")
         return t, nb
 
-    def compute_safety(self, geom_id, pos, touch=None, stream=None):
+    def compute_safety(self, geom_id, pos, touch=None, stream=None, precision=0):
         import torch
         n = pos.shape[0]
         out = torch.empty(n, dtype=torch.float64, device=pos.device)
         self._check(gnav_compute_safety(self.h, geom_id, n, _ptr(pos), _ptr(touch), _ptr(out),
-                                        _stream(stream)), "gnav_compute_safety")
+                                        int(precision), _stream(stream)), "gnav_compute_safety")
         return out
 
     def tally_create(self, n_events):

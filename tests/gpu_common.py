@@ -35,16 +35,17 @@ GEOMS = {
     "barrel_v103": lambda: W.geometry.barrel_variant(103),
 }
 
-_cache = {}
-
-
 def geom(ctx, name, oracle_lib):
-    key = (id(ctx), name)
-    if key not in _cache:
+    """(desc, geometry id, touchables, oracle geometry) of a named geometry uploaded to ctx.
+
+    The cache lives on the context object, so a context created later at a reused
+    address never sees ids of geometries it does not hold."""
+    cache = ctx.__dict__.setdefault("_test_geoms", {})
+    if name not in cache:
         desc = GEOMS[name]()
         gid, nt = ctx.upload_geometry(desc)
-        _cache[key] = (desc, gid, nt, oracle_lib.Geometry(desc))
-    return _cache[key]
+        cache[name] = (desc, gid, nt, oracle_lib.Geometry(desc))
+    return cache[name]
 
 
 def sample_points(desc, rng, n):

@@ -1,0 +1,212 @@
+"""GPU: the C-ABI boundary's state rules and query arguments.
+
+* graphs refuse to replay (GNAV_ESTATE, no device work) once a table, the
+  pending-photon buffer or the bound network they captured is gone;
+* max_steps_per_track above the packed counter range is rejected, and
+  truncation itself matches the oracle;
+* gnav_compute_step's max_step limit, candidate orders and precision
+  argument, and the precision argument of locate and safety;
+* launches of one context on two streams are ordered by the library.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import ATOL, RTOL, compare_logs, ctx, geom, print_case, run_transport, torch_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def test_graph_is_stale_after_upload_and_larger_grid(torch_dev, oracle_lib):
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav
+    print_case("graph_stale")
+    geoms, prim, _ = W.tiny(n=2000)
+    c = gnav.Context(0)
+    gid, _ = c.upload_geometry(geoms[0])
+    dev = gnav.primaries_to_device(prim, "cuda")
+    t = c.tally_create(prim.n_events)
+    g = c.graph_create(gid, dev, t)
+    c.graph_launch(g)
+    torch.cuda.synchronize()
+    first = t.read()
+    assert first["counters"]["tracks"] >= prim.n
+    # a batch needing a larger grid than any before reallocates the pending buffer
+    big = gnav.primaries_to_device(W.tiny(n=300_000)[1], "cuda")
+    t2 = c.tally_create(prim.n_events)
+    c.transport_batch(gid, big, t2, grid=8000)
+    torch.cuda.synchronize()
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.graph_launch(g)
+    c.graph_free(g)
+    t2.free()
+    # recapture works; a geometry upload then makes it stale again
+    g = c.graph_create(gid, dev, t)
+    c.graph_launch(g)
+    torch.cuda.synchronize()
+    again = t.read()
+    assert again["counters"] == first["counters"]
+    c.upload_geometry(W.geometry.slab())
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.graph_launch(g)
+    c.graph_free(g)
+    t.free()
+    c.close()
+
+
+def test_graph_is_stale_after_network_freed(torch_dev):
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav, learned
+    print_case("graph_stale_mlp")
+    c = gnav.Context(0)
+    desc = W.geometry.barrel()
+    gid, _ = c.upload_geometry(desc, voxel_lists=1)  # bounding-box lists: wide mothers
+    net = gnav.MLP(c, c.ordering_classes(gid), learned.init_params(c.ordering_classes(gid)))
+    c.set_mlp(gid, net)
+    _, prim, _ = W.barrel(n=2000)
+    dev = gnav.primaries_to_device(prim, "cuda")
+    t = c.tally_create(prim.n_events)
+    g = c.graph_create(gid, dev, t, order=2)
+    c.graph_launch(g)
+    torch.cuda.synchronize()
+    net.free()  # drops the binding
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.graph_launch(g)
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.transport_batch(gid, dev, t, order=2)
+    c.graph_free(g)
+    t.free()
+    c.close()
+
+
+def test_max_steps_range_and_truncation_parity(ctx, torch_dev, oracle_lib):
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    _, prim, _ = W.calorimeter(n=3000)
+    dev = gnav.primaries_to_device(prim, "cuda")
+    t = ctx.tally_create(prim.n_events)
+    with pytest.raises(gnav.GnavError, match="EINVAL"):
+        ctx.transport_batch(gid, dev, t, max_steps=(1 << 23))
+    t.free()
+    for ms in (1, 3, 7):
+        print_case("truncation", ms)
+        got = run_transport(ctx, torch, gid, prim, 16, max_steps=ms)
+        ref = og.transport(prim, seed=0, max_steps=ms, log_cap=16)
+        assert ref["counters"]["truncated"] > 0
+        for k in ("steps", "truncated", "pe", "compton", "pair", "crossings", "escaped", "tracks"):
+            assert got["counters"][k] == ref["counters"][k], (ms, k)
+        assert not compare_logs(got["log"], got["log_n"], got["log_fate"], ref, 16)
+
+
+@pytest.mark.parametrize("name", ["tiny_rot", "zoo", "barrel"])
+def test_compute_step_max_step_limit(ctx, torch_dev, oracle_lib, name):
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("max_step", name)
+    rng = np.random.default_rng(21)
+    from tests.gpu_common import sample_points
+    pts = sample_points(desc, rng, 20000)
+    dirs = W.primaries.isotropic(rng, len(pts))
+    T = og.locate(pts, dirs)
+    ok = T >= 0
+    pts, dirs, T = pts[ok], dirs[ok], T[ok]
+    s_ref, l_ref, n_ref = og.compute_step(pts, dirs, T)
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (gid, tt(pts), tt(dirs), tt(T.astype(np.int32)))
+    s0 = ctx.compute_step(*args)[0].cpu().numpy()
+    # a limit strictly below the step for half of the queries, exactly the step (a tie,
+    # which the limit wins) for a quarter, none (NaN) for the rest
+    u = rng.random(len(pts))
+    ms = np.where(u < 0.5, s0 * rng.uniform(0.0, 0.999, len(pts)), np.nan)
+    ms[(u >= 0.5) & (u < 0.75)] = s0[(u >= 0.5) & (u < 0.75)]
+    s, l, nx = (a.cpu().numpy() for a in ctx.compute_step(*args, max_step=tt(ms)))
+    limited = u < 0.75
+    assert np.array_equal(l[limited], np.full(limited.sum(), -5))
+    assert np.array_equal(s[limited], ms[limited])
+    assert np.array_equal(nx[limited], T[limited])
+    free = ~limited
+    assert np.array_equal(l[free], l_ref[free])
+    assert np.array_equal(nx[free], n_ref[free])
+    assert np.array_equal(s[free], s0[free])
+    fin = free & np.isfinite(s_ref)
+    assert np.allclose(s[fin], s_ref[fin], rtol=RTOL, atol=ATOL)
+
+
+def test_compute_step_orders_and_precision_arguments(torch_dev, oracle_lib):
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav, learned
+    print_case("step_orders")
+    c = gnav.Context(0)
+    desc = W.geometry.barrel()
+    gid, _ = c.upload_geometry(desc, voxel_lists=1)
+    og = oracle_lib.Geometry(desc)
+    # an untrained network: its predictions are arbitrary, the results may not change
+    net = gnav.MLP(c, c.ordering_classes(gid), learned.init_params(c.ordering_classes(gid), seed=11))
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.compute_step(gid, torch.zeros((1, 3), dtype=torch.float64, device="cuda"),
+                       torch.ones((1, 3), dtype=torch.float64, device="cuda") / np.sqrt(3), learned=2)
+    c.set_mlp(gid, net)
+    # photons from the axis, and points spread over the whole world
+    from tests.gpu_common import sample_points
+    _, prim, _ = W.barrel(n=30000, seed=3)
+    rng = np.random.default_rng(5)
+    P = np.concatenate([prim.pos, sample_points(desc, rng, 60000)])
+    D = np.concatenate([prim.dir, W.primaries.isotropic(rng, 60000)])
+    pts = torch.from_numpy(P).cuda()
+    dirs = torch.from_numpy(D).cuda()
+    runs = [[a.cpu().numpy() for a in c.compute_step(gid, pts, dirs, learned=k, with_safety=True)]
+            for k in (0, 1, 2)]
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
+    s_ref, l_ref, n_ref = og.compute_step(P, D)
+    assert np.array_equal(runs[0][1], l_ref) and np.array_equal(runs[0][2], n_ref)
+    fin = np.isfinite(s_ref)
+    assert np.array_equal(np.isfinite(runs[0][0]), fin)
+    assert np.allclose(runs[0][0][fin], s_ref[fin], rtol=RTOL, atol=ATOL)
+    # locate: every precision gives the FP64 answer
+    loc = [c.locate(gid, pts, dirs, precision=p).cpu().numpy() for p in (0, 1, 2)]
+    assert np.array_equal(loc[0], loc[1]) and np.array_equal(loc[0], loc[2])
+    assert np.array_equal(loc[0], og.locate(P, D))
+    # safety: the screened form lowers FP32 safeties rigorously, so it never exceeds FP64's
+    saf64 = c.compute_safety(gid, pts, precision=0).cpu().numpy()
+    saf_scr = c.compute_safety(gid, pts, precision=1).cpu().numpy()
+    saf32 = c.compute_safety(gid, pts, precision=2).cpu().numpy()
+    assert np.all(saf_scr >= 0) and np.all(saf_scr <= saf64)
+    assert np.allclose(saf32, saf64, rtol=1e-4, atol=2e-3)
+    c.set_mlp(gid, None)
+    net.free()
+    c.close()
+
+
+def test_launches_on_two_streams_are_ordered(ctx, torch_dev, oracle_lib):
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav
+    desc, gid, nt, og = geom(ctx, "calorimeter", oracle_lib)
+    print_case("two_streams")
+    _, pa, _ = W.calorimeter(n=50000, seed=0)
+    _, pb, _ = W.calorimeter(n=50000, seed=1)
+    da, db = gnav.primaries_to_device(pa, "cuda"), gnav.primaries_to_device(pb, "cuda")
+    ref = []
+    for d, p in ((da, pa), (db, pb)):
+        t = ctx.tally_create(p.n_events)
+        ctx.transport_batch(gid, d, t)
+        torch.cuda.synchronize()
+        ref.append(t.read())
+        t.free()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ta, tb = ctx.tally_create(pa.n_events), ctx.tally_create(pb.n_events)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        ta.reset(stream=s1)
+        tb.reset(stream=s2)
+        ctx.transport_batch(gid, da, ta, stream=s1)
+        ctx.transport_batch(gid, db, tb, stream=s2)
+        torch.cuda.synchronize()
+        for t, r in ((ta, ref[0]), (tb, ref[1])):
+            got = t.read()
+            assert got["counters"] == r["counters"]
+            assert np.allclose(got["edep_event"], r["edep_event"], rtol=RTOL, atol=1e-15)
+    ta.free()
+    tb.free()

@@ -79,29 +79,38 @@ def test_compute_step_parity(ctx, torch_dev, oracle_lib, name):
     assert np.array_equal(l2.cpu().numpy(), l_ref)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("name", ["tiny_rot", "zoo", "calorimeter", "barrel"])
-def test_safety_is_lower_bound(ctx, torch_dev, oracle_lib, name):
+def test_safety_is_lower_bound(ctx, torch_dev, oracle_lib, name, precision):
+    """Every point strictly inside the sphere of the GPU safety lies in the same
+    touchable (brute-force oracle locate), for 2000 points and 64 directions
+    each.  (The voxel safety is not compared with the oracle's brute-force
+    safety: both are lower bounds of the true distance and neither bounds the
+    other, since an isotropic solid safety can fall below the distance to a
+    voxel node face.)"""
     torch = torch_dev
     desc, gid, nt, og = geom(ctx, name, oracle_lib)
-    print_case("safety", name)
+    print_case("safety", name, precision)
     rng = np.random.Generator(np.random.Philox(key=1003))
-    pts = sample_points(desc, rng, 400)
+    pts = sample_points(desc, rng, 3000)
     T = og.locate(pts)
     ok = T >= 0
-    pts, T = pts[ok], T[ok]
-    saf = ctx.compute_safety(gid, torch.from_numpy(pts).cuda()).cpu().numpy()
-    ref = og.compute_safety(pts, T)
+    pts, T = pts[ok][:2000], T[ok][:2000]
+    saf = ctx.compute_safety(gid, torch.from_numpy(pts).cuda(), precision=precision).cpu().numpy()
+    same = ctx.compute_safety(gid, torch.from_numpy(pts).cuda(), torch.from_numpy(T.astype(np.int32)).cuda(),
+                              precision=precision).cpu().numpy()
+    assert np.array_equal(saf, same)
     assert np.all(saf >= 0)
-    sph = W.primaries.isotropic(rng, 128)
-    for p, t, s in zip(pts, T, saf):
-        if s <= 1e-6:
-            continue
-        q = p + s * (1 - 1e-9) * sph
-        loc = og.locate(q)
-        # every point strictly within the safety is in the same touchable
-        d = og.compute_safety(q, loc)
-        assert np.all((loc == t) | (d < 1e-6))
-    assert np.mean(saf > 0) > 0.5 * np.mean(ref > 0)
+    sph = W.primaries.isotropic(rng, 64)
+    q = (pts[:, None, :] + (saf * (1 - 1e-9))[:, None, None] * sph[None, :, :]).reshape(-1, 3)
+    loc = og.locate(q).reshape(len(pts), 64)
+    d = og.compute_safety(q, loc.reshape(-1)).reshape(len(pts), 64)
+    # a sphere point may only leave the touchable within the surface band of
+    # a boundary it just touches
+    bad = (loc != T[:, None]) & (d > 1e-6)
+    assert not bad.any(), np.argwhere(bad)[:5]
+    # the safety is positive away from boundaries for most points
+    assert np.mean(saf > 0) > 0.9
 
 
 @pytest.mark.parametrize("name,n,cap", [("tiny", 10000, 64), ("calorimeter", 4000, 400),
