@@ -72,6 +72,9 @@ def lib():
         L.og_locate.argtypes = [P, C.c_int, f64p, P, i32p]
         L.og_compute_step.argtypes = [P, C.c_int, f64p, f64p, P, f64p, i32p, P]
         L.og_compute_safety.argtypes = [P, C.c_int, f64p, P, f64p]
+        L.og_compute_step_normal.argtypes = [P, C.c_int, f64p, f64p, P, f64p, i32p, P, f64p, i32p]
+        L.og_solid_normal_n.argtypes = [C.c_int, f64p, C.c_int, f64p, f64p, i32p]
+        L.og_solid_normal_n.restype = C.c_int
         L.og_solid_eval.argtypes = [C.c_int, f64p, C.c_int, C.c_int, f64p, P, f64p]
         L.og_solid_eval.restype = C.c_int
         L.og_free_path.argtypes = [P, f64p, f64p, C.c_double, C.c_double, C.POINTER(C.c_int)]
@@ -80,7 +83,7 @@ def lib():
         L.og_rotate.argtypes = [C.c_int, f64p, f64p, f64p]
         L.og_transport.argtypes = [P, C.c_int64, i32p, i32p, f64p, f64p, f64p, C.c_uint64,
                                    C.c_double, C.c_int64, f64p, f64p, f64p, u64p, P, C.c_int64,
-                                   P, P]
+                                   P, P, P]
         L.og_transport.restype = C.c_int
         _lib = L
     return _lib
@@ -128,6 +131,19 @@ def solid_eval(stype, par, op, p, v=None):
     if rc != 0:
         raise ValueError("invalid solid parameters")
     return out
+
+
+def solid_normal(stype, par, p):
+    """Outward unit normals of a solid at points p [n][3] and the number of faces
+    within the tolerance of the defining one (1 face, 2+ edge or corner)."""
+    par8 = np.zeros(8)
+    par8[: len(par)] = par
+    p = _c(np.atleast_2d(p), np.float64)
+    out = np.zeros_like(p)
+    faces = np.zeros(p.shape[0], np.int32)
+    if lib().og_solid_normal_n(int(stype), par8, p.shape[0], p, out, faces) != 0:
+        raise ValueError("invalid solid parameters")
+    return out, faces
 
 
 def compton_sample(E, n, seed=0):
@@ -223,6 +239,22 @@ class Geometry:
         lib().og_compute_step(self.h, n, pos, dirs, _ptr(t), step, lim, _ptr(nxt))
         return step, lim, nxt
 
+    def compute_step_normal(self, pos, dirs, touchable=None):
+        """ComputeStep plus the exit normal of the crossed boundary (global frame) and its
+        validity (0 none, 1 face, 2 edge or corner)."""
+        pos = _c(pos, np.float64)
+        dirs = _c(dirs, np.float64)
+        n = pos.shape[0]
+        t = None if touchable is None else _c(touchable, np.int32)
+        step = np.zeros(n)
+        lim = np.zeros(n, np.int32)
+        nxt = np.zeros(n, np.int32)
+        nrm = np.zeros((n, 3))
+        val = np.zeros(n, np.int32)
+        lib().og_compute_step_normal(self.h, n, pos, dirs, _ptr(t), step, lim, nxt.ctypes.data_as(C.c_void_p),
+                                     nrm, val)
+        return step, lim, nxt, nrm, val
+
     def compute_safety(self, pos, touchable=None):
         pos = _c(pos, np.float64)
         n = pos.shape[0]
@@ -237,8 +269,11 @@ class Geometry:
                                float(Y), C.byref(nb))
         return T, nb.value
 
-    def transport(self, prim, seed=0, ecut=1e-3, max_steps=1_000_000, log_cap=0, n_events=None):
-        """Run the gamma loop; returns a dict of tallies, counters and optional logs."""
+    def transport(self, prim, seed=0, ecut=1e-3, max_steps=1_000_000, log_cap=0, n_events=None,
+                  want_start=False):
+        """Run the gamma loop; returns a dict of tallies, counters and optional logs (and,
+        with want_start, the start state [3 n][7] = position, direction, energy of every
+        track slot: 3 i the primary, 3 i + 1 and 3 i + 2 its annihilation photons)."""
         n = prim.n
         ne = prim.n_events if n_events is None else n_events
         edep_t = np.zeros(self.n_touchables)
@@ -250,13 +285,16 @@ class Geometry:
             log = np.zeros((3 * n, log_cap), dtype=LOG_DTYPE)
             logn = np.zeros(3 * n, np.int32)
             fate = np.zeros(3 * n, np.int32)
+        start = np.full((3 * n, 7), np.nan) if want_start else None
         lib().og_transport(self.h, n, _c(prim.event, np.int32), _c(prim.prim_id, np.int32),
                            _c(prim.pos, np.float64), _c(prim.dir, np.float64),
                            _c(prim.energy, np.float64), int(seed), float(ecut), int(max_steps),
                            edep_t, edep_ev, esc_ev, counters, _ptr(log), int(log_cap), _ptr(logn),
-                           _ptr(fate))
+                           _ptr(fate), _ptr(start))
         out = dict(edep_touchable=edep_t, edep_event=edep_ev, escaped_event=esc_ev,
                    counters=dict(zip(COUNTERS, (int(c) for c in counters))))
         if log_cap > 0:
             out.update(log=log, log_n=logn, log_fate=fate)
+        if want_start:
+            out["start"] = start
         return out

@@ -338,6 +338,65 @@ double og_solid_safety_out(const og_solid* s, const double* p) {
   return d < 0 ? -d : 0.0;
 }
 
+/* Outward normal of the solid at p (Sec. 3.2: the normal of the boundary
+ * surface at the crossing point).  The solid's value is the largest of its
+ * face values, so the face that defines the surface at p is the one with the
+ * largest value (the first in face order on a tie: box x, y, z; radial
+ * outer, inner, z, start phi, end phi), and the normal is that face value's
+ * gradient, written out per face below.  Returns the number of faces whose
+ * value is within the tolerance of the largest (1 on a face, 2 or more on an
+ * edge or corner). */
+int og_solid_normal(const og_solid* s, const double* p, double n[3]) {
+  double val[K_N];
+  double grad[K_N][3];
+  int nf;
+  memset(grad, 0, sizeof(grad));
+  if (s->type == OG_BOX) {
+    nf = 3;
+    for (int i = 0; i < 3; i++) {
+      val[i] = fabs(p[i]) - s->par[i];
+      grad[i][i] = p[i] < 0 ? -1.0 : 1.0; /* d|p_i|/dp_i */
+    }
+  } else if (s->type == OG_ORB) {
+    double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    nf = 1;
+    val[0] = r - s->par[0];
+    if (r > 0) {
+      for (int i = 0; i < 3; i++) grad[0][i] = p[i] / r;
+    } else {
+      grad[0][2] = 1.0;
+    }
+  } else {
+    nf = K_N;
+    rad_comps(s, p, val);
+    double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
+    double ex = rho > 0 ? p[0] / rho : 1.0, ey = rho > 0 ? p[1] / rho : 0.0; /* grad rho */
+    /* (rho - (Ao + Bo z)) co */
+    grad[K_RO][0] = s->co * ex;
+    grad[K_RO][1] = s->co * ey;
+    grad[K_RO][2] = -s->co * s->Bo;
+    /* ((Ai + Bi z) - rho) ci */
+    grad[K_RI][0] = -s->ci * ex;
+    grad[K_RI][1] = -s->ci * ey;
+    grad[K_RI][2] = s->ci * s->Bi;
+    /* |z| - dz */
+    grad[K_Z][2] = p[2] < 0 ? -1.0 : 1.0;
+    /* p . ns and p . ne */
+    grad[K_PA][0] = s->ns[0];
+    grad[K_PA][1] = s->ns[1];
+    grad[K_PB][0] = s->ne[0];
+    grad[K_PB][1] = s->ne[1];
+  }
+  int best = 0;
+  for (int i = 1; i < nf; i++)
+    if (val[i] > val[best]) best = i;
+  int faces = 0;
+  for (int i = 0; i < nf; i++)
+    if (val[i] >= val[best] - kTol) faces++;
+  for (int i = 0; i < 3; i++) n[i] = grad[best][i];
+  return faces;
+}
+
 /* Real roots of a t^2 + 2 b t + c, ascending; the numerically stable pair
  * q = -(b + sign(b) sqrt(b^2 - a c)), roots q/a and c/q. */
 static int quad_roots(double a, double b, double c, double t[2]) {
@@ -1263,12 +1322,62 @@ void og_compute_step(const og_geom* g, int n, const double* pos, const double* d
   }
 }
 
+/* A direction in the frame of touchable T back to the global frame: the
+ * placement rotations applied level by level from T up to the world. */
+static void dir_to_global(const og_geom* g, int T, const double* vl, double* vg) {
+  double v[3] = {vl[0], vl[1], vl[2]};
+  for (int u = T; u > 0; u = g->t_parent[u]) {
+    const double* R = g->pv_rot + 9 * g->t_pv[u];
+    double w[3];
+    for (int i = 0; i < 3; i++) w[i] = R[3 * i] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
+    memcpy(v, w, sizeof(w));
+  }
+  memcpy(vg, v, sizeof(v));
+}
+
+/* ComputeStep with the exit normal at the end point: the outward normal of
+ * the mother when the mother limits the step, the inward normal of the
+ * entered daughter otherwise (both point along the direction of travel), in
+ * the global frame.  valid: 0 no boundary reached, 1 a face, 2 an edge or a
+ * corner (two or more faces within the tolerance). */
+void og_compute_step_normal(const og_geom* g, int n, const double* pos, const double* dir, const int* touch,
+                            double* step, int* lim, int* next, double* normal, int* valid) {
+  og_compute_step(g, n, pos, dir, touch, step, lim, next);
+  for (int i = 0; i < n; i++) {
+    const double* p = pos + 3 * i;
+    const double* v = dir + 3 * i;
+    double* nv = normal + 3 * i;
+    nv[0] = nv[1] = nv[2] = 0.0;
+    valid[i] = 0;
+    if (!(step[i] < kInf)) continue;
+    int T = touch ? touch[i] : locate(g, p, v);
+    if (T < 0) continue;
+    int S = lim[i] >= 0 ? g->t_child_base[T] + lim[i] : T;
+    double q[3] = {p[0] + step[i] * v[0], p[1] + step[i] * v[1], p[2] + step[i] * v[2]};
+    double ql[3], nl[3];
+    frame_of(g, S, q, NULL, ql, NULL);
+    int faces = og_solid_normal(lv_solid_of(g, g->t_lv[S]), ql, nl);
+    if (lim[i] >= 0)
+      for (int k = 0; k < 3; k++) nl[k] = -nl[k];
+    dir_to_global(g, S, nl, nv);
+    valid[i] = faces > 1 ? 2 : 1;
+  }
+}
+
 void og_compute_safety(const og_geom* g, int n, const double* pos, const int* touch, double* out) {
   for (int i = 0; i < n; i++) {
     const double* p = pos + 3 * i;
     int T = touch ? touch[i] : locate(g, p, NULL);
     out[i] = T < 0 ? 0.0 : compute_safety(g, T, p);
   }
+}
+
+/* Outward normals of one solid at n points (face counts in faces). */
+int og_solid_normal_n(int type, const double* par, int n, const double* p, double* normals, int* faces) {
+  og_solid s;
+  if (solid_init(&s, type, par) != 0) return -1;
+  for (int i = 0; i < n; i++) faces[i] = og_solid_normal(&s, p + 3 * i, normals + 3 * i);
+  return 0;
 }
 
 /* Per-solid entry points for unit tests: op 0 d, 1 inside(p[,v]), 2 dist_in,
@@ -1421,6 +1530,7 @@ typedef struct {
   int64_t log_cap;
   int32_t* log_n;
   int32_t* log_fate;
+  double* start; /* optional [3 n][7]: position, direction and energy at each track's start */
 } og_run;
 
 static void log_step(og_run* r, int64_t slot, int64_t* nrec, int T, int code, double step, double edep,
@@ -1445,6 +1555,14 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
   int64_t nrec = 0;
   int fate;
   r->counters[OG_C_TRACKS]++;
+  if (r->start) {
+    double* q = r->start + 7 * slot;
+    for (int i = 0; i < 3; i++) {
+      q[i] = x[i];
+      q[3 + i] = v[i];
+    }
+    q[6] = E;
+  }
   int T = locate(g, x, v);
   if (T < 0) {
     r->esc_ev[event] += E;
@@ -1560,8 +1678,8 @@ done:
 int og_transport(const og_geom* g, int64_t n, const int32_t* event, const int32_t* prim_id,
                  const double* pos, const double* dir, const double* energy, uint64_t seed, double ecut,
                  int64_t max_steps, double* edep_t, double* edep_ev, double* esc_ev, uint64_t* counters,
-                 og_logrec* log, int64_t log_cap, int32_t* log_n, int32_t* log_fate) {
-  og_run r = {g, seed, ecut, max_steps, edep_t, edep_ev, esc_ev, counters, log, log_cap, log_n, log_fate};
+                 og_logrec* log, int64_t log_cap, int32_t* log_n, int32_t* log_fate, double* start) {
+  og_run r = {g, seed, ecut, max_steps, edep_t, edep_ev, esc_ev, counters, log, log_cap, log_n, log_fate, start};
   for (int64_t i = 0; i < n; i++) {
     double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
     double v[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};

@@ -332,6 +332,25 @@ def slab(material="water", thickness=50.0, half_xy=500.0):
     return b.build(world)
 
 
+def foil_stack(n_foils=400, half_thickness=4.5e-10, half_xy=10.0, material="vacuum"):
+    """Vacuum foils thinner than the surface tolerance (1e-9 mm), stacked
+    along z without gaps and centred on the origin, in a vacuum world.
+
+    Every step through such a foil is shorter than the tolerance, so tracks
+    crossing the stack take runs of zero-length steps: the case of the
+    zero-step push and kill rule.
+    """
+    b = Builder("foil_stack")
+    s_world = b.solid(BOX, 100.0, 100.0, 100.0)
+    s_foil = b.solid(BOX, half_xy, half_xy, half_thickness)
+    world = b.lv(s_world, "vacuum", "world")
+    foil = b.lv(s_foil, material, "foil")
+    z0 = -n_foils * half_thickness
+    for k in range(n_foils):
+        b.place(world, foil, t=(0.0, 0.0, z0 + (2 * k + 1) * half_thickness))
+    return b.build(world)
+
+
 def solids_zoo(seed=5):
     """One daughter of every solid family (rotated and translated) in a box world.
 
