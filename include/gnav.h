@@ -114,6 +114,20 @@ typedef struct {
   double energy;     /* photon energy after the step, MeV (0 when absorbed) */
 } gnav_logrec;
 
+/* Summary of one track for comparisons at full size (32 bytes): what the
+ * per-track log would hold, folded.  hash is 64-bit FNV-1a (offset basis
+ * 14695981039346656037, prime 1099511628211) over the bytes of every step
+ * record's touchable and code, each as a little-endian int32, in record
+ * order; the sums add the records' step lengths and deposits in record
+ * order. */
+typedef struct {
+  uint64_t hash;
+  int32_t n;        /* step records */
+  int32_t fate;     /* GNAV_FATE_* (0: slot unused) */
+  double sum_step;  /* mm */
+  double sum_edep;  /* MeV, logged deposits (an energy cut's or a kill's deposit is not logged) */
+} gnav_digest;
+
 /* Flat description of a placement hierarchy (Sec. 3.2: volumes nested in a
  * hierarchy).  All arrays are host memory owned by the caller and copied
  * before gnav_upload_geometry returns. */
@@ -324,14 +338,17 @@ typedef struct {
   uint64_t* record_count_dev; /* crossings seen (may exceed the capacity; extra ones dropped) */
   gnav_logrec* log_dev;       /* optional per-track log: 3 slots per primary (primary and */
   int64_t log_capacity;       /*   its two annihilation photons), log_capacity records each */
-  int32_t* log_n_dev;         /*   [3 n] records written per slot (may exceed the capacity) */
-  int32_t* log_fate_dev;      /*   [3 n] GNAV_FATE_* per slot (0 = slot unused) */
+  int32_t* log_n_dev;         /*   [3 n] records written per slot (may exceed the capacity), */
+  int32_t* log_fate_dev;      /*   [3 n] GNAV_FATE_* per slot (0 = slot unused); both required
+                                   with log_dev */
   int32_t chunk;              /* primaries a block claims from the device queue at once; 0: each
                                  wave claims exactly what its idle lanes need (one atomic) */
   int32_t sort_period;        /* every sort_period-th round the step phase groups tracks by their
                                  current logical volume instead of solid family; 0: never */
   int32_t tuned;              /* 1: take block, grid, chunk and sort_period from gnav_autotune's cache
                                  for this geometry, precision and order when present */
+  gnav_digest* digest_dev;    /* optional [3 n] per-track digests (slots as for the log); the
+                                 caller zeroes them; log_dev may then be NULL */
 } gnav_batch;
 
 /* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase

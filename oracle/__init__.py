@@ -24,6 +24,8 @@ ME = 0.51099895
 
 LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
                       ("edep", np.float64), ("energy", np.float64)])
+DIGEST_DTYPE = np.dtype([("hash", np.uint64), ("n", np.int32), ("fate", np.int32),
+                         ("sum_step", np.float64), ("sum_edep", np.float64)])
 
 
 def build(force=False):
@@ -83,7 +85,7 @@ def lib():
         L.og_rotate.argtypes = [C.c_int, f64p, f64p, f64p]
         L.og_transport.argtypes = [P, C.c_int64, i32p, i32p, f64p, f64p, f64p, C.c_uint64,
                                    C.c_double, C.c_int64, f64p, f64p, f64p, u64p, P, C.c_int64,
-                                   P, P, P]
+                                   P, P, P, P, P, P]
         L.og_transport.restype = C.c_int
         _lib = L
     return _lib
@@ -270,10 +272,13 @@ class Geometry:
         return T, nb.value
 
     def transport(self, prim, seed=0, ecut=1e-3, max_steps=1_000_000, log_cap=0, n_events=None,
-                  want_start=False):
+                  want_start=False, want_digest=False, want_margins=False):
         """Run the gamma loop; returns a dict of tallies, counters and optional logs (and,
         with want_start, the start state [3 n][7] = position, direction, energy of every
-        track slot: 3 i the primary, 3 i + 1 and 3 i + 2 its annihilation photons)."""
+        track slot: 3 i the primary, 3 i + 1 and 3 i + 2 its annihilation photons); with
+        want_digest the per-track digests [3 n]; with want_margins (needs log_cap) the
+        smallest decision margin behind each log record [3 n][log_cap] and after the last
+        record [3 n] (|a - b| / scale of the closest comparison)."""
         n = prim.n
         ne = prim.n_events if n_events is None else n_events
         edep_t = np.zeros(self.n_touchables)
@@ -286,15 +291,23 @@ class Geometry:
             logn = np.zeros(3 * n, np.int32)
             fate = np.zeros(3 * n, np.int32)
         start = np.full((3 * n, 7), np.nan) if want_start else None
+        digest = np.zeros(3 * n, DIGEST_DTYPE) if want_digest else None
+        margin = np.full((3 * n, max(log_cap, 1)), np.inf, np.float32) if want_margins else None
+        tail = np.full(3 * n, np.inf, np.float32) if want_margins else None
         lib().og_transport(self.h, n, _c(prim.event, np.int32), _c(prim.prim_id, np.int32),
                            _c(prim.pos, np.float64), _c(prim.dir, np.float64),
                            _c(prim.energy, np.float64), int(seed), float(ecut), int(max_steps),
                            edep_t, edep_ev, esc_ev, counters, _ptr(log), int(log_cap), _ptr(logn),
-                           _ptr(fate), _ptr(start))
+                           _ptr(fate), _ptr(start), _ptr(digest), _ptr(margin), _ptr(tail))
         out = dict(edep_touchable=edep_t, edep_event=edep_ev, escaped_event=esc_ev,
                    counters=dict(zip(COUNTERS, (int(c) for c in counters))))
         if log_cap > 0:
             out.update(log=log, log_n=logn, log_fate=fate)
         if want_start:
             out["start"] = start
+        if want_digest:
+            out["digest"] = digest
+        if want_margins:
+            out["margin"] = margin[:, :log_cap] if log_cap else margin[:, :0]
+            out["tail_margin"] = tail
         return out

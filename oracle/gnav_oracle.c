@@ -247,6 +247,30 @@ static int solid_init(og_solid* s, int type, const double* par) {
 static double max2(double a, double b) { return a > b ? a : b; }
 static double min2(double a, double b) { return a < b ? a : b; }
 
+/* Decision margins (for telling a rounding-edge flip from a real difference
+ * when a track's history differs from another implementation's).  Each
+ * decision taken while transporting a track -- a comparison of a with b --
+ * notes |a - b| / scale; the smallest since the track's previous step record
+ * is stored with the next record.  scale is the magnitude that sets the
+ * rounding of the compared values: the geometry's coordinate extent for
+ * lengths (og_scale), 1 for directions and uniform numbers, the operand
+ * itself for attenuations and energies.  Off unless margins are requested. */
+static int og_margin_on = 0;
+static double og_margin = INFINITY;
+static double og_scale = 1.0;
+
+/* Comparisons that cannot change a result are not noted: a direction
+ * component against zero (a slab or plane parallel to the ray gives the same
+ * distances as a nearly parallel one) and the branch of the quadratic formula
+ * (both branches give the same roots). */
+static void note(double a, double b, double scale) {
+  if (!og_margin_on) return;
+  double m = fabs(a - b) / scale;
+  if (a == b) m = 0.0; /* also inf == inf */
+  if (m < og_margin) og_margin = m;
+}
+#define NOTE_LEN(a, b) note((a), (b), og_scale)
+
 /* Component values of a radial solid (tubs or cons) at p. */
 static void rad_comps(const og_solid* s, const double* p, double k[K_N]) {
   double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
@@ -286,19 +310,26 @@ double og_solid_d(const og_solid* s, const double* p) {
 static int rad_moving_in(const og_solid* s, const double* p, const double* v, const double k[K_N]) {
   double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
   double rv = rho > 0 ? (p[0] * v[0] + p[1] * v[1]) / rho : 0.0;
+  for (int i = 0; i < K_N; i++)
+    if (k[i] > -kInf) NOTE_LEN(fabs(k[i]), kHalf);
   if (fabs(k[K_RO]) <= kHalf) {
     double vn = rv - s->Bo * v[2];
+    note(vn, 0.0, 1.0);
     if (vn >= 0) return 0;
   }
   if (s->has_inner && fabs(k[K_RI]) <= kHalf) {
     double vn = -rv + s->Bi * v[2];
+    note(vn, 0.0, 1.0);
     if (vn >= 0) return 0;
   }
   if (fabs(k[K_Z]) <= kHalf) {
+    NOTE_LEN(p[2] * v[2], 0.0);
     if (p[2] * v[2] >= 0) return 0;
   }
   if (s->has_phi) {
+    if (fabs(k[K_PA]) <= kHalf) note(v[0] * s->ns[0] + v[1] * s->ns[1], 0.0, 1.0);
     if (fabs(k[K_PA]) <= kHalf && (v[0] * s->ns[0] + v[1] * s->ns[1]) >= 0) return 0;
+    if (fabs(k[K_PB]) <= kHalf) note(v[0] * s->ne[0] + v[1] * s->ne[1], 0.0, 1.0);
     if (fabs(k[K_PB]) <= kHalf && (v[0] * s->ne[0] + v[1] * s->ne[1]) >= 0) return 0;
   }
   return 1;
@@ -307,18 +338,22 @@ static int rad_moving_in(const og_solid* s, const double* p, const double* v, co
 /* Classify p (with optional direction v) against the solid. */
 int og_solid_inside(const og_solid* s, const double* p, const double* v) {
   double d = og_solid_d(s, p);
+  NOTE_LEN(d, d < 0 ? -kHalf : kHalf);
   if (d < -kHalf) return OG_IN;
   if (d > kHalf) return OG_OUT;
   if (!v) return OG_IN;
   if (s->type == OG_BOX) {
     for (int i = 0; i < 3; i++) {
       double si = fabs(p[i]) - s->par[i];
+      NOTE_LEN(fabs(si), kHalf);
+      if (fabs(si) <= kHalf) NOTE_LEN(p[i] * v[i], 0.0);
       if (fabs(si) <= kHalf && p[i] * v[i] >= 0) return OG_OUT;
     }
     return OG_IN;
   }
   if (s->type == OG_ORB) {
     double b = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+    NOTE_LEN(b, 0.0);
     return b < 0 ? OG_IN : OG_OUT;
   }
   double k[K_N];
@@ -406,6 +441,7 @@ static int quad_roots(double a, double b, double c, double t[2]) {
     return 1;
   }
   double disc = b * b - a * c;
+  note(disc, 0.0, og_scale * og_scale);
   if (disc < 0.0) return 0;
   double sq = sqrt(disc);
   double q = (b >= 0.0) ? -(b + sq) : (sq - b);
@@ -441,8 +477,11 @@ static double radial_root(double A, double B, const double* p, const double* v, 
   double best = kInf;
   for (int i = 0; i < n; i++) {
     double slope = a * t[i] + b;
+    NOTE_LEN(slope, 0.0);
     if (sign > 0 ? !(slope > 0) : !(slope < 0)) continue;
+    NOTE_LEN(R0 + Rv * t[i], 0.0);
     if (R0 + Rv * t[i] < 0) continue;
+    NOTE_LEN(t[i], 0.0);
     if (t[i] < best && t[i] >= 0) best = t[i];
   }
   return best;
@@ -456,7 +495,9 @@ static double radial_entry(double A, double B, const double* p, const double* v)
   int n = quad_roots(a, b, c, t);
   for (int i = 0; i < n; i++) {
     double slope = a * t[i] + b;
+    NOTE_LEN(slope, 0.0);
     if (!(slope < 0)) continue;
+    NOTE_LEN(R0 + Rv * t[i], 0.0);
     if (R0 + Rv * t[i] < 0) continue;
     return t[i];
   }
@@ -470,6 +511,7 @@ static int rad_ok_except(const og_solid* s, const double* p, const double* v, do
   rad_comps(s, q, k);
   for (int i = 0; i < K_N; i++) {
     if (i == skip) continue;
+    if (k[i] > -kInf) NOTE_LEN(k[i], kHalf);
     if (k[i] > kHalf) return 0;
   }
   return 1;
@@ -478,6 +520,8 @@ static int rad_ok_except(const og_solid* s, const double* p, const double* v, do
 static double box_dist_in(const og_solid* s, const double* p, const double* v) {
   for (int i = 0; i < 3; i++) {
     double si = fabs(p[i]) - s->par[i];
+    NOTE_LEN(si, -kHalf);
+    if (si >= -kHalf) NOTE_LEN(p[i] * v[i], 0.0);
     if (si >= -kHalf && p[i] * v[i] >= 0) return kInf;
   }
   double te = -kInf, tx = kInf;
@@ -489,7 +533,9 @@ static double box_dist_in(const og_solid* s, const double* p, const double* v) {
     te = max2(te, lo);
     tx = min2(tx, hi);
   }
+  if (te > -kInf && tx < kInf) NOTE_LEN(te, tx - kHalf);
   if (te >= tx - kHalf) return kInf;
+  NOTE_LEN(te, kHalf);
   return te < kHalf ? 0.0 : te;
 }
 
@@ -500,6 +546,7 @@ static double box_dist_out(const og_solid* s, const double* p, const double* v) 
     if (v[i] > 0) sd = s->par[i] - p[i];
     else if (v[i] < 0) sd = s->par[i] + p[i];
     else continue;
+    NOTE_LEN(sd, kHalf);
     if (sd <= kHalf) return 0.0;
     t = min2(t, sd / fabs(v[i]));
   }
@@ -511,15 +558,20 @@ static double orb_dist_in(const og_solid* s, const double* p, const double* v) {
   double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   double sd = sqrt(rr) - R;
   double b = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+  NOTE_LEN(sd, -kHalf);
   if (sd < -kHalf) return 0.0;
+  NOTE_LEN(b, 0.0);
   if (b >= 0) return kInf;
   double c = rr - R * R;
   double disc = b * b - c;
+  note(disc, 0.0, og_scale * og_scale);
   if (disc <= 0) return kInf;
   double sq = sqrt(disc);
   double te = c / (sq - b);
   double tx = sq - b;
+  NOTE_LEN(te, tx - kHalf);
   if (te >= tx - kHalf) return kInf;
+  NOTE_LEN(te, kHalf);
   return te < kHalf ? 0.0 : te;
 }
 
@@ -528,6 +580,8 @@ static double orb_dist_out(const og_solid* s, const double* p, const double* v) 
   double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   double sd = sqrt(rr) - R;
   double b = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+  NOTE_LEN(sd, -kHalf);
+  if (sd >= -kHalf) NOTE_LEN(b, 0.0);
   if (sd >= -kHalf && b >= 0) return 0.0;
   double c = rr - R * R;
   double disc = b * b - c;
@@ -545,12 +599,16 @@ static double rad_dist_in(const og_solid* s, const double* p, const double* v) {
   rad_comps(s, p, k);
   double d = k[0];
   for (int i = 1; i < K_N; i++) d = max2(d, k[i]);
+  NOTE_LEN(d, -kHalf);
   if (d < -kHalf) return 0.0;
   double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
   double rv = rho > 0 ? (p[0] * v[0] + p[1] * v[1]) / rho : 0.0;
   double best = kInf;
+  for (int i = 0; i < K_N; i++)
+    if (k[i] > -kInf) NOTE_LEN(k[i], -kHalf);
   /* z planes */
   if (k[K_Z] >= -kHalf) {
+    NOTE_LEN(p[2] * v[2], 0.0);
     if (p[2] * v[2] >= 0) return kInf;
     double t = k[K_Z] / fabs(v[2]);
     if (t < 0) t = 0;
@@ -559,6 +617,7 @@ static double rad_dist_in(const og_solid* s, const double* p, const double* v) {
   /* outer radial surface (convex region) */
   if (k[K_RO] >= -kHalf) {
     double vn = rv - s->Bo * v[2];
+    note(vn, 0.0, 1.0);
     if (vn >= 0) return kInf;
     double t = radial_entry(s->Ao, s->Bo, p, v);
     if (t == kInf) return kInf;
@@ -568,8 +627,10 @@ static double rad_dist_in(const og_solid* s, const double* p, const double* v) {
   /* inner radial surface: entering the section from its bore */
   if (s->has_inner) {
     double t = -1.0;
+    NOTE_LEN(fabs(k[K_RI]), kHalf);
     if (fabs(k[K_RI]) <= kHalf) {
       double vn = -rv + s->Bi * v[2];
+      note(vn, 0.0, 1.0);
       if (vn < 0) t = 0.0;
       else if (vn > 0) t = radial_root(s->Ai, s->Bi, p, v, +1);
     } else {
@@ -584,6 +645,7 @@ static double rad_dist_in(const og_solid* s, const double* p, const double* v) {
       double dp = q == 0 ? k[K_PA] : k[K_PB];
       if (dp >= -kHalf) {
         double dv = v[0] * n[0] + v[1] * n[1];
+        note(dv, 0.0, 1.0);
         if (dv >= 0) return kInf;
         double t = dp / (-dv);
         if (t < 0) t = 0;
@@ -591,6 +653,7 @@ static double rad_dist_in(const og_solid* s, const double* p, const double* v) {
       }
     }
   }
+  if (best < kInf) NOTE_LEN(best, kHalf);
   return best < kHalf ? 0.0 : best;
 }
 
@@ -604,12 +667,17 @@ static double rad_dist_out(const og_solid* s, const double* p, const double* v) 
   double t = kInf;
   if (v[2] != 0) {
     double sd = v[2] > 0 ? s->dz - p[2] : s->dz + p[2];
+    NOTE_LEN(sd, kHalf);
     if (sd <= kHalf) return 0.0;
     t = min2(t, sd / fabs(v[2]));
   }
+  NOTE_LEN(k[K_RO], -kHalf);
+  if (k[K_RO] >= -kHalf) note(rv - s->Bo * v[2], 0.0, 1.0);
   if (k[K_RO] >= -kHalf && rv - s->Bo * v[2] >= 0) return 0.0;
   t = min2(t, radial_root(s->Ao, s->Bo, p, v, +1));
   if (s->has_inner) {
+    NOTE_LEN(k[K_RI], -kHalf);
+    if (k[K_RI] >= -kHalf) note(-rv + s->Bi * v[2], 0.0, 1.0);
     if (k[K_RI] >= -kHalf && -rv + s->Bi * v[2] >= 0) return 0.0;
     t = min2(t, radial_root(s->Ai, s->Bi, p, v, -1));
   }
@@ -618,6 +686,8 @@ static double rad_dist_out(const og_solid* s, const double* p, const double* v) 
       const double* n = q == 0 ? s->ns : s->ne;
       double dp = q == 0 ? k[K_PA] : k[K_PB];
       double dv = v[0] * n[0] + v[1] * n[1];
+      NOTE_LEN(dp, -kHalf);
+      note(dv, 0.0, 1.0);
       if (dp >= -kHalf && dv >= 0) return 0.0;
       if (dv > 0) {
         double tp = -dp / dv;
@@ -1181,6 +1251,7 @@ static double compute_step(const og_geom* g, int T, const double* pg, const doub
   const og_vgrid* G = grid_of(g, lv);
   if (G) return compute_step_voxels(g, G, lv, pl, vl, lim);
   double s = og_solid_dist_out(lv_solid_of(g, lv), pl, vl);
+  double second = kInf; /* next smallest distance, for the selection's margin */
   *lim = OG_LIM_MOTHER;
   for (int k = 0; k < g->lv_dau_cnt[lv]; k++) {
     int pv = g->lv_dau_off[lv] + k;
@@ -1189,10 +1260,14 @@ static double compute_step(const og_geom* g, int T, const double* pg, const doub
     dir_to_local(g->pv_rot + 9 * pv, vl, vd);
     double t = og_solid_dist_in(lv_solid_of(g, g->pv_lv[pv]), pd, vd);
     if (t < s) {
+      second = s;
       s = t;
       *lim = k;
+    } else if (t < second) {
+      second = t;
     }
   }
+  if (second < kInf) NOTE_LEN(s, second);
   return s;
 }
 
@@ -1456,6 +1531,7 @@ static void compton_sample(double E, og_stream* rs, double* eps_out, double* cos
   for (int trial = 0; trial < OG_MAX_COMPTON_TRIALS; trial++) {
     double r1 = og_next(rs), r2 = og_next(rs), r3 = og_next(rs);
     double epssq;
+    note(r1 * (a1 + a2), a1, a1 + a2);
     if (r1 * (a1 + a2) < a1) {
       eps = exp(-a1 * r2);
       epssq = eps * eps;
@@ -1466,6 +1542,7 @@ static void compton_sample(double E, og_stream* rs, double* eps_out, double* cos
     onecost = (1.0 - eps) / (eps * k);
     sint2 = onecost * (2.0 - onecost);
     double g = 1.0 - eps * sint2 / (1.0 + epssq);
+    note(r3, g, 1.0);
     if (r3 <= g) break;
   }
   *eps_out = eps;
@@ -1479,6 +1556,7 @@ static void rotate_dir(double* v, double cost, double sint, double phi) {
   double cp = cos(phi), sp = sin(phi);
   double rp = sqrt(a * a + b * b);
   double n[3];
+  note(rp, 1e-12, 1.0);
   if (rp < 1e-12) {
     n[0] = sint * cp;
     n[1] = sint * sp;
@@ -1517,6 +1595,24 @@ typedef struct {
   double step, edep, energy;
 } og_logrec; /* 32 bytes */
 
+/* Per-track summary: 64-bit FNV-1a (Fowler, Noll, Vo) over the touchable and
+ * code of every record, each as four little-endian bytes, in record order;
+ * the record count and fate; the sums of the records' steps and deposits. */
+typedef struct {
+  uint64_t hash;
+  int32_t n, fate;
+  double sum_step, sum_edep;
+} og_digest; /* 32 bytes */
+
+static uint64_t fnv1a_int32(uint64_t h, int32_t x) {
+  uint32_t u = (uint32_t)x;
+  for (int b = 0; b < 4; b++) {
+    h ^= (u >> (8 * b)) & 0xffu;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
 typedef struct {
   const og_geom* g;
   uint64_t seed;
@@ -1531,10 +1627,21 @@ typedef struct {
   int32_t* log_n;
   int32_t* log_fate;
   double* start; /* optional [3 n][7]: position, direction and energy at each track's start */
+  og_digest* digest; /* optional [3 n] */
+  float* margin;     /* optional [3 n][log_cap]: smallest decision margin behind each record */
+  float* tail;       /* optional [3 n]: smallest margin after the last record */
 } og_run;
 
 static void log_step(og_run* r, int64_t slot, int64_t* nrec, int T, int code, double step, double edep,
                      double energy) {
+  if (r->digest) {
+    og_digest* d = r->digest + slot;
+    d->hash = fnv1a_int32(fnv1a_int32(d->hash, T), code);
+    d->sum_step += step;
+    d->sum_edep += edep;
+  }
+  if (r->margin && *nrec < r->log_cap) r->margin[slot * r->log_cap + *nrec] = (float)og_margin;
+  og_margin = INFINITY;
   if (r->log && *nrec < r->log_cap) {
     og_logrec* q = r->log + slot * r->log_cap + *nrec;
     q->touchable = T;
@@ -1555,6 +1662,15 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
   int64_t nrec = 0;
   int fate;
   r->counters[OG_C_TRACKS]++;
+  og_margin = INFINITY;
+  if (r->digest) {
+    og_digest* d = r->digest + slot;
+    d->hash = 14695981039346656037ull;
+    d->n = 0;
+    d->fate = 0;
+    d->sum_step = 0.0;
+    d->sum_edep = 0.0;
+  }
   if (r->start) {
     double* q = r->start + 7 * slot;
     for (int i = 0; i < 3; i++) {
@@ -1574,6 +1690,7 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
   int zero = 0;
   int64_t steps = 0;
   for (;;) {
+    note(E, r->ecut, E);
     if (E < r->ecut) {
       r->edep_t[T] += E;
       r->edep_ev[event] += E;
@@ -1594,11 +1711,14 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
     double s_geo = compute_step(g, T, x, v, &lim);
     steps++;
     r->counters[OG_C_STEPS]++;
+    if (s_phys < kInf) note(s_phys, s_geo, max2(og_scale, max2(s_phys, s_geo)));
     if (s_phys <= s_geo) {
       /* the interaction point of Alg. 1: T = t_{j-1} + (Y - S_{j-1}) / mu_j */
       for (int i = 0; i < 3; i++) x[i] = x[i] + s_phys * v[i];
       zero = 0;
       double u = og_next(&rs) * mu;
+      note(u, mu3[0], mu);
+      note(u, mu3[0] + mu3[1], mu);
       if (u < mu3[0]) {
         r->edep_t[T] += E;
         r->edep_ev[event] += E;
@@ -1644,6 +1764,7 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
       }
       log_step(r, slot, &nrec, T, lim, s_geo, 0.0, E);
       r->counters[OG_C_CROSSINGS]++;
+      NOTE_LEN(s_geo, kTol);
       if (s_geo < kTol) zero++;
       else zero = 0;
       if (zero >= OG_ZERO_KILL) {
@@ -1669,6 +1790,11 @@ static int track(og_run* r, uint32_t event, uint32_t key, int64_t slot, double* 
 done:
   if (r->log_n) r->log_n[slot] = (int32_t)(nrec > 0x7fffffff ? 0x7fffffff : nrec);
   if (r->log_fate) r->log_fate[slot] = fate;
+  if (r->digest) {
+    r->digest[slot].n = (int32_t)(nrec > 0x7fffffff ? 0x7fffffff : nrec);
+    r->digest[slot].fate = fate;
+  }
+  if (r->tail) r->tail[slot] = (float)og_margin;
   return fate;
 }
 
@@ -1678,8 +1804,19 @@ done:
 int og_transport(const og_geom* g, int64_t n, const int32_t* event, const int32_t* prim_id,
                  const double* pos, const double* dir, const double* energy, uint64_t seed, double ecut,
                  int64_t max_steps, double* edep_t, double* edep_ev, double* esc_ev, uint64_t* counters,
-                 og_logrec* log, int64_t log_cap, int32_t* log_n, int32_t* log_fate, double* start) {
-  og_run r = {g, seed, ecut, max_steps, edep_t, edep_ev, esc_ev, counters, log, log_cap, log_n, log_fate, start};
+                 og_logrec* log, int64_t log_cap, int32_t* log_n, int32_t* log_fate, double* start,
+                 og_digest* digest, float* margin, float* tail) {
+  og_run r = {g,       seed,     ecut,  max_steps, edep_t, edep_ev, esc_ev, counters, log, log_cap,
+              log_n,   log_fate, start, digest,    margin, tail};
+  /* coordinate scale of the margins: the world's largest extent */
+  {
+    const og_solid* w = lv_solid_of(g, g->world_lv);
+    double e = w->par[0];
+    if (w->type == OG_BOX) e = max2(w->par[0], max2(w->par[1], w->par[2]));
+    else if (w->type != OG_ORB) e = max2(w->Ao + fabs(w->Bo) * w->dz, w->dz);
+    og_scale = max2(1.0, e);
+  }
+  og_margin_on = (margin || tail) ? 1 : 0;
   for (int64_t i = 0; i < n; i++) {
     double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
     double v[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
@@ -1695,5 +1832,6 @@ int og_transport(const og_geom* g, int64_t n, const int32_t* event, const int32_
       track(&r, (uint32_t)event[i], key | 2u, 3 * i + 2, x2, w2, kMe, dx, dw);
     }
   }
+  og_margin_on = 0;
   return 0;
 }

@@ -1299,6 +1299,8 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
     return fail(c, GNAV_EINVAL, "candidate orders and the crossing recorder need FP64 distances");
   if (b->log_dev && (b->log_capacity <= 0 || !b->log_n_dev || !b->log_fate_dev))
     return fail(c, GNAV_EINVAL, "log buffers incomplete");
+  if (!b->log_dev && !b->digest_dev && (b->log_n_dev || b->log_fate_dev))
+    return fail(c, GNAV_EINVAL, "log counts without a log or digests");
   if (!(b->e_cut >= 0)) return fail(c, GNAV_EINVAL, "bad energy cut");
   if (b->max_steps_per_track > GNAV_MAX_STEPS_PER_TRACK)
     return fail(c, GNAV_EINVAL, "max_steps_per_track above GNAV_MAX_STEPS_PER_TRACK");
@@ -1371,7 +1373,8 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.rec_cap = b->record_dev ? b->record_capacity : 0;
   L.rec_count = reinterpret_cast<unsigned long long*>(b->record_count_dev);
   L.log = b->log_dev;
-  L.log_cap = b->log_capacity;
+  L.digest = b->digest_dev;
+  L.log_cap = b->log_dev ? b->log_capacity : 0;
   L.log_n = b->log_n_dev;
   L.log_fate = b->log_fate_dev;
   L.block = block;
@@ -1482,7 +1485,7 @@ gnav_status gnav_autotune(gnav_ctx* c, const gnav_batch* batch, gnav_tally* t, i
                           gnav_tuning* out) {
   if (!c || !batch || !t) return GNAV_EINVAL;
   if (trials < 1 || trials > 100) return fail(c, GNAV_EINVAL, "trials must be 1..100");
-  if (batch->log_dev || batch->record_dev)
+  if (batch->log_dev || batch->digest_dev || batch->record_dev)
     return fail(c, GNAV_EINVAL, "tune without the per-track log or the recorder");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, order_before(c, st), "stream ordering");

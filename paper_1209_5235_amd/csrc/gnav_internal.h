@@ -46,6 +46,7 @@ struct TransportLaunch {
   long log_cap;
   int* log_n;
   int* log_fate;
+  gnav_digest* digest;
   int block;
   int grid;
   bool axis_boxes;  // every solid the batch can reach is a box placed without rotation

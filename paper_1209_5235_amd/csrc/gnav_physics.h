@@ -106,8 +106,9 @@ struct TransportArgs {
   double* pend;               // [lanes][6]: pending annihilation photon position and direction
   gnav_logrec* log;
   long log_cap;
-  int* log_n;
-  int* log_fate;
+  int* log_n;                 // [3 n] or null
+  int* log_fate;              // [3 n] or null
+  gnav_digest* digest;        // [3 n] per-track digests, or null
   gnav_crossing* rec;         // optional crossing recorder
   long rec_cap;
   unsigned long long* rec_count;

@@ -190,9 +190,40 @@ __device__ __forceinline__ void end_track(Pool& P, const TransportArgs& a, int s
   if (cb & 0xFFFFFF) atomicAdd(&P.cnt[GNAV_C_CROSSINGS], (unsigned long long)(cb & 0xFFFFFF));
   if (cb >> 24) atomicAdd(&P.cnt[GNAV_C_PUSHES], (unsigned long long)(cb >> 24));
   if (LOG) {
-    int sub = P.sub_pend[s] & 15;
-    a.log_n[3 * P.prim[s] + sub] = P.nrec[s];
-    a.log_fate[3 * P.prim[s] + sub] = fate;
+    const long slot3 = 3L * P.prim[s] + (P.sub_pend[s] & 15);
+    if (a.log_n) a.log_n[slot3] = P.nrec[s];
+    if (a.log_fate) a.log_fate[slot3] = fate;
+    if (a.digest) {
+      a.digest[slot3].n = P.nrec[s];
+      a.digest[slot3].fate = fate;
+    }
+  }
+}
+
+// 64-bit FNV-1a over the touchable and the code of one step record, each as
+// four little-endian bytes (the per-track digest's hash).
+__device__ __forceinline__ uint64_t fnv1a_record(uint64_t h, int touchable, int code) {
+  const uint32_t w[2] = {(uint32_t)touchable, (uint32_t)code};
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      h ^= (w[k] >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  }
+  return h;
+}
+
+template <bool LOG>
+__device__ __forceinline__ void digest_start(Pool& P, const TransportArgs& a, int s) {
+  if (LOG && a.digest) {
+    gnav_digest& d = a.digest[3L * P.prim[s] + (P.sub_pend[s] & 15)];
+    d.hash = 14695981039346656037ull;
+    d.n = 0;
+    d.fate = 0;
+    d.sum_step = 0.0;
+    d.sum_edep = 0.0;
   }
 }
 
@@ -201,9 +232,13 @@ __device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, 
                                         double edep, double energy) {
   if (LOG) {
     int n = P.nrec[s];
-    if (n < a.log_cap) {
-      int sub = P.sub_pend[s] & 15;
-      a.log[(long)(3 * P.prim[s] + sub) * a.log_cap + n] = gnav_logrec{T - P.tbase[s], code, step, edep, energy};
+    const long slot3 = 3L * P.prim[s] + (P.sub_pend[s] & 15);
+    if (n < a.log_cap) a.log[slot3 * a.log_cap + n] = gnav_logrec{T - P.tbase[s], code, step, edep, energy};
+    if (a.digest) {
+      gnav_digest& d = a.digest[slot3];
+      d.hash = fnv1a_record(d.hash, T - P.tbase[s], code);
+      d.sum_step += step;
+      d.sum_edep += edep;
     }
     P.nrec[s] = n + 1;
   }
@@ -426,6 +461,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         const int lim = P.aux[s] >> 2;
         V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
         if (mode == kNavStart) {
+          digest_start<LOG>(P, a, s);
           atomicAdd(&P.cnt[GNAV_C_TRACKS], 1ull);
           P.draw[s] = 0;
           P.dep[s] = 0.0;
@@ -784,6 +820,7 @@ hipError_t launch(const TransportLaunch& L, hipStream_t st) {
   a.log_cap = L.log_cap;
   a.log_n = L.log_n;
   a.log_fate = L.log_fate;
+  a.digest = L.digest;
   a.rec = L.rec;
   a.rec_cap = L.rec_cap;
   a.rec_count = L.rec_count;
@@ -802,7 +839,7 @@ hipError_t launch(const TransportLaunch& L, hipStream_t st) {
     else if (L.order == kOrderLearned) GNAV_LAUNCH(LOGV, CNTV, kOrderLearned, kPrecFP64); \
     else GNAV_LAUNCH(LOGV, CNTV, kOrderPlain, kPrecFP64);                                \
   } while (0)
-  if (L.log) {
+  if (L.log || L.digest) {
     if (L.count) GNAV_LAUNCH_ORDER(true, true);
     else GNAV_LAUNCH_ORDER(true, false);
   } else {

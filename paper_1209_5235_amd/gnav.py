@@ -32,6 +32,8 @@ NORMAL_NONE, NORMAL_FACE, NORMAL_EDGE = 0, 1, 2
 NCOUNTERS = len(COUNTERS)
 LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
                       ("edep", np.float64), ("energy", np.float64)])
+DIGEST_DTYPE = np.dtype([("hash", np.uint64), ("n", np.int32), ("fate", np.int32),
+                         ("sum_step", np.float64), ("sum_edep", np.float64)])
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -61,6 +63,7 @@ class gnav_batch(C.Structure):
         ("record_count_dev", C.c_void_p), ("log_dev", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_n_dev", C.c_void_p), ("log_fate_dev", C.c_void_p),
         ("chunk", C.c_int32), ("sort_period", C.c_int32), ("tuned", C.c_int32),
+        ("digest_dev", C.c_void_p),
     ]
 
 
@@ -329,7 +332,7 @@ class Context:
 
     def _batch(self, geom_id, prim, seed=0, e_cut=1e-3, max_steps=0, precision=0, block=0, grid=0,
                log=None, event_geom=None, count_work=False, order=0, record=None, chunk=0,
-               sort_period=0, tuned=False):
+               sort_period=0, tuned=False, digest=None):
         b = gnav_batch()
         b.n_primaries = prim["energy"].shape[0]
         b.event_dev = prim["event"].data_ptr()
@@ -354,6 +357,8 @@ class Context:
             b.record_dev = record["rec"].data_ptr()
             b.record_capacity = record["cap"]
             b.record_count_dev = record["count"].data_ptr()
+        if digest is not None:
+            b.digest_dev = digest.data_ptr()
         if log is not None:
             b.log_dev = log["rec"].data_ptr()
             b.log_capacity = log["cap"]
@@ -504,6 +509,16 @@ def make_log(n_primaries, cap, device="cuda"):
     return dict(rec=torch.zeros((3 * n_primaries, cap, 4), dtype=torch.float64, device=device),
                 cap=cap, n=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device),
                 fate=torch.zeros(3 * n_primaries, dtype=torch.int32, device=device))
+
+
+def make_digests(n_primaries, device="cuda"):
+    """Zeroed per-track digests (3 slots per primary, 32 bytes each)."""
+    import torch
+    return torch.zeros((3 * n_primaries, 4), dtype=torch.float64, device=device)
+
+
+def digests_to_numpy(d):
+    return d.cpu().numpy().view(DIGEST_DTYPE).reshape(d.shape[0])
 
 
 def make_recorder(capacity, device="cuda"):
