@@ -359,6 +359,24 @@ typedef struct {
 gnav_status gnav_transport_batch(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally,
                                  void* stream);
 
+/* gnav_transport_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results; it calls no allocator (no
+ * hipMalloc or hipFree, no allocating library routine).  The transport's
+ * scratch -- the work-queue counter and one pending annihilation photon (48
+ * bytes) per track-pool slot -- lives in a fixed array of the library on each
+ * device, 256 + 48 * GNAV_NOALLOC_MAX_SLOTS bytes (9 MiB), held until the
+ * process ends, instead of the context's buffers.  grid * block (the default
+ * grid when grid is 0: 3 * 256 slots per compute unit) above
+ * GNAV_NOALLOC_MAX_SLOTS returns GNAV_EINVAL.  Each call resets the counter
+ * with a kernel and writes a pending entry before reading it, so nothing
+ * carries over from the last call; but every call on one device shares the
+ * array, so calls that can run at the same time on one GPU (on other streams,
+ * contexts or host threads) race on it and give wrong results. */
+#define GNAV_NOALLOC_MAX_SLOTS 196608
+gnav_status gnav_transport_batch_noalloc(gnav_ctx* ctx, const gnav_batch* batch, gnav_tally* tally,
+                                         void* stream);
+
 /* Launch settings of gnav_transport_batch chosen by gnav_autotune. */
 typedef struct {
   int32_t block;              /* track-pool slots (threads) per block */

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,16 @@
 using namespace gnav;
 
 static constexpr int kSolidStride = 16;  // host-side staging of solid parameters
+
+// Scratch of gnav_transport_batch_noalloc, one copy per device for the life of
+// the process: the work-queue counter in the first kNoallocQueueBytes, then
+// one pending-photon entry (6 doubles) per track-pool slot.  On the host this
+// name is not a device address; host code uses only the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static constexpr size_t kNoallocQueueBytes = 256;
+static constexpr size_t kNoallocBytes =
+    kNoallocQueueBytes + (size_t)GNAV_NOALLOC_MAX_SLOTS * 6 * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 namespace {
 
@@ -599,6 +610,8 @@ struct gnav_ctx {
   bool launched = false;
   // autotuned launch settings by (geometry, precision, order, log2 of the batch size)
   std::map<std::array<int, 4>, gnav_tuning> tuning;
+  // this device's copy of the no-allocation scratch array
+  void* scratch = nullptr;
 };
 
 struct gnav_tally {
@@ -617,6 +630,24 @@ gnav_status fail(gnav_ctx* c, gnav_status s, const std::string& msg) {
 gnav_status hip_fail(gnav_ctx* c, hipError_t e, const char* what) {
   return fail(c, e == hipErrorOutOfMemory ? GNAV_ENOMEM : GNAV_EHIP,
               std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device and kept for the process.
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    it = addr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
 }
 
 #define HIP_TRY(ctx, expr, what)                     \
@@ -749,6 +780,11 @@ gnav_status gnav_create(int32_t device, gnav_ctx** out) {
     return GNAV_ENOMEM;
   }
   if (hipEventCreateWithFlags(&c->last_launch, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return GNAV_EHIP;
+  }
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
+    (void)hipEventDestroy(c->last_launch);
     delete c;
     return GNAV_EHIP;
   }
@@ -1283,8 +1319,10 @@ std::array<int, 4> tuning_key(const gnav_batch* b) {
   return {b->geom_id, b->precision, b->order, lg};
 }
 
+// With `noalloc` the queue counter and pending photons live in the device's
+// scratch array instead of the context's buffers, and nothing is allocated.
 gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, hipStream_t stream,
-                              TransportLaunch* out) {
+                              TransportLaunch* out, bool noalloc = false) {
   if (!c || !b || !t) return GNAV_EINVAL;
   gnav_status s = check_geom(c, b->geom_id);
   if (s) return s;
@@ -1340,16 +1378,26 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.edep_ev = t->edep_ev.as<double>();
   L.esc_ev = t->esc_ev.as<double>();
   L.counters = t->counters.as<unsigned long long>();
-  L.queue = c->d_queue.as<unsigned long long>();
-  // per-slot storage for the second annihilation photon of a pair conversion
-  size_t pend_bytes = (size_t)grid * block * 6 * sizeof(double);
-  if (c->d_pend.bytes < pend_bytes) {
-    HIP_TRY(c, hipDeviceSynchronize(), "synchronize");
-    HIP_TRY(c, c->d_pend.upload(nullptr, pend_bytes, stream), "pending-photon buffer");
-    HIP_TRY(c, hipStreamSynchronize(stream), "synchronize");
-    c->pend_gen++;
+  if (noalloc) {
+    if ((long)grid * block > GNAV_NOALLOC_MAX_SLOTS)
+      return fail(c, GNAV_EINVAL, "grid * block = " + std::to_string((long)grid * block) +
+                                      " track slots, above GNAV_NOALLOC_MAX_SLOTS = " +
+                                      std::to_string(GNAV_NOALLOC_MAX_SLOTS) + " (pass a smaller grid)");
+    if (!c->scratch) return fail(c, GNAV_ESTATE, "no scratch address for this device");
+    L.queue = reinterpret_cast<unsigned long long*>(c->scratch);
+    L.pend = reinterpret_cast<double*>(static_cast<char*>(c->scratch) + kNoallocQueueBytes);
+  } else {
+    L.queue = c->d_queue.as<unsigned long long>();
+    // per-slot storage for the second annihilation photon of a pair conversion
+    size_t pend_bytes = (size_t)grid * block * 6 * sizeof(double);
+    if (c->d_pend.bytes < pend_bytes) {
+      HIP_TRY(c, hipDeviceSynchronize(), "synchronize");
+      HIP_TRY(c, c->d_pend.upload(nullptr, pend_bytes, stream), "pending-photon buffer");
+      HIP_TRY(c, hipStreamSynchronize(stream), "synchronize");
+      c->pend_gen++;
+    }
+    L.pend = c->d_pend.as<double>();
   }
-  L.pend = c->d_pend.as<double>();
   L.count = b->count_work != 0;
   if (b->order < 0 || b->order > 2) return fail(c, GNAV_EINVAL, "order must be 0, 1 or 2");
   // With no mother wide enough for ordered walks the learned order scores
@@ -1436,6 +1484,16 @@ extern "C" {
 gnav_status gnav_transport_batch(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream) {
   TransportLaunch L;
   gnav_status s = prepare_transport(c, b, t, (hipStream_t)stream, &L);
+  if (s) return s;
+  HIP_TRY(c, order_before(c, (hipStream_t)stream), "stream ordering");
+  HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");
+  HIP_TRY(c, order_after(c, (hipStream_t)stream), "stream ordering");
+  return GNAV_OK;
+}
+
+gnav_status gnav_transport_batch_noalloc(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, void* stream) {
+  TransportLaunch L;
+  gnav_status s = prepare_transport(c, b, t, (hipStream_t)stream, &L, true);
   if (s) return s;
   HIP_TRY(c, order_before(c, (hipStream_t)stream), "stream ordering");
   HIP_TRY(c, launch_transport(L, (hipStream_t)stream), "transport launch");

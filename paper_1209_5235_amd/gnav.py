@@ -30,6 +30,7 @@ PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
 LIM_MOTHER, LIM_PE, LIM_COMPTON, LIM_PAIR, LIM_MAX_STEP = -1, -2, -3, -4, -5
 NORMAL_NONE, NORMAL_FACE, NORMAL_EDGE = 0, 1, 2
 NCOUNTERS = len(COUNTERS)
+NOALLOC_MAX_SLOTS = 196608  # GNAV_NOALLOC_MAX_SLOTS: grid * block limit of gnav_transport_batch_noalloc
 LOG_DTYPE = np.dtype([("touchable", np.int32), ("code", np.int32), ("step", np.float64),
                       ("edep", np.float64), ("energy", np.float64)])
 DIGEST_DTYPE = np.dtype([("hash", np.uint64), ("n", np.int32), ("fate", np.int32),
@@ -103,6 +104,7 @@ def _load():
         "gnav_tally_reset": ([P, P, P], C.c_int32),
         "gnav_tally_free": ([P, P], C.c_int32),
         "gnav_transport_batch": ([P, C.POINTER(gnav_batch), P, P], C.c_int32),
+        "gnav_transport_batch_noalloc": ([P, C.POINTER(gnav_batch), P, P], C.c_int32),
         "gnav_read_tallies": ([P, P, P, P, P, P, P], C.c_int32),
         "gnav_autotune": ([P, C.POINTER(gnav_batch), P, C.c_int32, P, C.POINTER(gnav_tuning)],
                           C.c_int32),
@@ -144,6 +146,7 @@ gnav_tally_create = lib.gnav_tally_create
 gnav_tally_reset = lib.gnav_tally_reset
 gnav_tally_free = lib.gnav_tally_free
 gnav_transport_batch = lib.gnav_transport_batch
+gnav_transport_batch_noalloc = lib.gnav_transport_batch_noalloc
 gnav_read_tallies = lib.gnav_read_tallies
 gnav_autotune = lib.gnav_autotune
 gnav_graph_create = lib.gnav_graph_create
@@ -371,6 +374,13 @@ class Context:
         b = self._batch(geom_id, prim, **kw)
         self._check(gnav_transport_batch(self.h, C.byref(b), tally.h, _stream(stream)),
                     "gnav_transport_batch")
+
+    def transport_batch_noalloc(self, geom_id, prim, tally, stream=None, **kw):
+        """gnav_transport_batch_noalloc: the same transport with the library's fixed
+        per-device scratch (allocates nothing)."""
+        b = self._batch(geom_id, prim, **kw)
+        self._check(gnav_transport_batch_noalloc(self.h, C.byref(b), tally.h, _stream(stream)),
+                    "gnav_transport_batch_noalloc")
 
     def autotune(self, geom_id, prim, tally, trials=3, stream=None, **kw):
         """gnav_autotune: fastest {grid, chunk, sort_period} for this batch (cached in the
