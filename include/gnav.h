@@ -79,13 +79,22 @@ typedef int32_t gnav_status;
 #define GNAV_C_TRUNCATED 9      /* tracks stopped at max_steps_per_track */
 #define GNAV_C_TRACKS 10        /* tracks started (primaries + annihilation photons) */
 #define GNAV_C_SHORTCUTS 11     /* physics steps taken inside the safety (no ComputeStep) */
-#define GNAV_C_DIST_IN 12       /* daughter entry-distance evaluations */
-#define GNAV_C_DIST_OUT 13      /* mother exit-distance evaluations */
-#define GNAV_C_INSIDE 14        /* point-in-solid tests (locate / relocate) */
-#define GNAV_C_VOXEL_NODES 15   /* voxel nodes visited by the step walk */
+#define GNAV_C_DIST_IN 12       /* daughter entry-distance evaluations (count_work = 1) */
+#define GNAV_C_DIST_OUT 13      /* mother exit-distance evaluations (count_work = 1) */
+#define GNAV_C_INSIDE 14        /* point-in-solid tests, locate / relocate (count_work = 1) */
+#define GNAV_C_VOXEL_NODES 15   /* voxel nodes visited by the step walk (count_work = 1) */
 #define GNAV_C_INVALID 16       /* primaries skipped: bad event/geometry id, non-finite state, E <= 0 */
 #define GNAV_C_DIST_IN_F32 17   /* daughter entry distances evaluated in FP32 (FP32 precisions) */
-#define GNAV_NCOUNTERS 18
+#define GNAV_C_SCORED 18        /* learned order: steps whose start-node candidates the network ordered */
+/* Work by solid family (batches with count_work = 1; zero otherwise): slot
+ * base + GNAV_BOX .. base + GNAV_ORB. */
+#define GNAV_C_DIST_IN_BY 19    /* daughter entry distances (FP64 and FP32) by the daughter's family */
+#define GNAV_C_DIST_OUT_BY 23   /* mother exit distances by the mother's family */
+#define GNAV_C_SAFETY_BY 27     /* isotropic distances (mother and daughter safeties) by family */
+#define GNAV_C_INSIDE_BY 31     /* point-in-solid tests by family */
+#define GNAV_C_FRAME_MAPS 35    /* frame maps: one per daughter candidate examined, one per placement
+                                   level of each touchable frame formed (level by level, Sec. 3.2) */
+#define GNAV_NCOUNTERS 36
 
 /* Limiter codes of a step. */
 #define GNAV_LIM_MOTHER (-1)    /* left the current volume (>= 0: entered that daughter slot) */
@@ -447,6 +456,14 @@ gnav_status gnav_mlp_adam(gnav_ctx* ctx, gnav_mlp* mlp, float lr, void* stream);
 /* Logits [B][64] (float). */
 gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* mlp, int64_t batch, const float* x_dev,
                              const int32_t* cls_dev, float* logits_dev, void* stream);
+/* The ordering network as the transport and gnav_compute_step evaluate it
+ * (order 2): features x_dev [n][6] float rounded to bf16, classes cls_dev [n]
+ * (clamped to [0, n_class)), the layers on bf16 MFMA tiles of 16 rows with
+ * FP32 accumulation and bf16 hidden activations; logits_dev [n][64] float
+ * (or NULL) and pred_dev [n], the position of the highest logit, the lowest
+ * on ties (or NULL).  Any n >= 0. */
+gnav_status gnav_mlp_score(gnav_ctx* ctx, gnav_mlp* mlp, int64_t n, const float* x_dev,
+                           const int32_t* cls_dev, float* logits_dev, int32_t* pred_dev, void* stream);
 /* Host copy of the float parameters (synchronous). */
 gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* mlp, float* params_host);
 /* Free a network (after the device has passed its last use); every binding

@@ -49,7 +49,7 @@ struct TRec {
   int lv;          // logical volume (global)
   int parent;      // parent touchable, -1 for a world
   int child_base;  // touchable of daughter slot 0
-  int slot_kind;   // slot in the parent LV (low 16 bits) | transform kind << 16
+  int slot_kind;   // slot in the parent LV (low 16 bits) | transform kind << 16 | depth << 24
 };
 
 // Logical-volume record: solid, material, daughters and voxel grid together,
@@ -608,15 +608,56 @@ __device__ __forceinline__ int vox_axis_index(double p, double lo, double inv_w,
   return (int)x;
 }
 
-// Work counters for the roofline accounting; compiled out when not wanted.
+// Work counters for the roofline accounting, by solid family (the low two
+// bits of the solid info: box, tubs, cons, orb); compiled out when not
+// wanted.  `frames` counts frame maps: one per daughter candidate examined
+// (its entry distance, safety and inside test share one) and one per
+// placement level of every touchable frame.
 template <bool ON>
 struct NavCount {
-  unsigned dist_in = 0, dist_out = 0, inside = 0, nodes = 0, dist_in32 = 0;
-  __device__ __forceinline__ void in() { if (ON) dist_in++; }
-  __device__ __forceinline__ void in32() { if (ON) dist_in32++; }
-  __device__ __forceinline__ void out() { if (ON) dist_out++; }
-  __device__ __forceinline__ void ins() { if (ON) inside++; }
+  unsigned din[4] = {0, 0, 0, 0}, dout[4] = {0, 0, 0, 0}, dsaf[4] = {0, 0, 0, 0}, dins[4] = {0, 0, 0, 0};
+  unsigned frames = 0, nodes = 0, dist_in32 = 0;
+  __device__ __forceinline__ static void bump(unsigned (&a)[4], int info) {
+    const int t = info & 3;
+    a[0] += t == 0;
+    a[1] += t == 1;
+    a[2] += t == 2;
+    a[3] += t == 3;
+  }
+  // daughter entry distance (FP64 or FP32), with its candidate frame unless
+  // that was counted with the candidate's safety
+  __device__ __forceinline__ void in(int info, bool own_frame = true) {
+    if (ON) {
+      bump(din, info);
+      frames += own_frame ? 1u : 0u;
+    }
+  }
+  __device__ __forceinline__ void in32(int info) {
+    if (ON) {
+      bump(din, info);
+      frames++;
+      dist_in32++;
+    }
+  }
+  // mother exit distance
+  __device__ __forceinline__ void out(int info) { if (ON) bump(dout, info); }
+  // isotropic distance (safety); own_frame: a candidate examined for its safety alone
+  __device__ __forceinline__ void saf(int info, bool own_frame) {
+    if (ON) {
+      bump(dsaf, info);
+      frames += own_frame ? 1u : 0u;
+    }
+  }
+  // point-in-solid test; own_frame: a daughter candidate's
+  __device__ __forceinline__ void ins(int info, bool own_frame) {
+    if (ON) {
+      bump(dins, info);
+      frames += own_frame ? 1u : 0u;
+    }
+  }
+  __device__ __forceinline__ void levels(int n) { if (ON) frames += (unsigned)n; }
   __device__ __forceinline__ void node() { if (ON) nodes++; }
+  __device__ __forceinline__ unsigned total(const unsigned (&a)[4]) const { return a[0] + a[1] + a[2] + a[3]; }
 };
 
 template <bool C>
@@ -627,7 +668,7 @@ __device__ __forceinline__ bool daughter_holds(const DevGeom& G, int pv, V3 pl, 
   V3 pd = xf_point(P.m, kind, pl);
   V3 vd = xf_dir(P.m, kind, vl);
   const LRec& L = G.lv[P.lv];
-  nc.ins();
+  nc.ins(L.info, true);
   return solid_inside(L.info, L.par, pd, has_v, vd) == kIn;
 }
 
@@ -657,7 +698,8 @@ __device__ __forceinline__ int find_daughter(const DevGeom& G, const LRec& L, V3
   return -1;
 }
 
-__device__ __forceinline__ int trec_kind(const TRec& r) { return r.slot_kind >> 16; }
+__device__ __forceinline__ int trec_kind(const TRec& r) { return (r.slot_kind >> 16) & 0xFF; }
+__device__ __forceinline__ int trec_depth(const TRec& r) { return (int)((unsigned)r.slot_kind >> 24); }
 __device__ __forceinline__ int trec_slot(const TRec& r) { return r.slot_kind & 0xFFFF; }
 
 // Descend from touchable T (holding the point, given in T's frame).  Also
@@ -678,6 +720,7 @@ __device__ __forceinline__ int descend_local(const DevGeom& G, int T, V3 pl, boo
     int pk = P.kind;
     pl = xf_point(P.m, pk, pl);
     vl = xf_dir(P.m, pk, vl);
+    nc.levels(1);
     T = tr.child_base + k;
     blocked = -1;
   }
@@ -694,7 +737,9 @@ template <bool C>
 __device__ __forceinline__ int descend(const DevGeom& G, int T, V3 pg, bool has_v, V3 vg, int blocked,
                                        NavCount<C>& nc) {
   V3 pl, vl;
-  touchable_frame(G, T, trec_kind(G.t[T]), pg, vg, pl, vl);
+  const TRec tr = G.t[T];
+  touchable_frame(G, T, trec_kind(tr), pg, vg, pl, vl);
+  nc.levels(trec_depth(tr));
   return descend_local(G, T, pl, has_v, vl, blocked, nc);
 }
 
@@ -702,7 +747,7 @@ __device__ __forceinline__ int descend(const DevGeom& G, int T, V3 pg, bool has_
 template <bool C>
 __device__ __forceinline__ int locate(const DevGeom& G, int W, V3 pg, bool has_v, V3 vg, NavCount<C>& nc) {
   const LRec& L = G.lv[G.t[W].lv];
-  nc.ins();
+  nc.ins(L.info, false);
   if (solid_inside(L.info, L.par, pg, has_v, vg) == kOut) return -1;
   return descend_local(G, W, pg, has_v, vg, -1, nc);
 }
@@ -719,8 +764,9 @@ __device__ __forceinline__ int relocate(const DevGeom& G, int T, const TRec& tr,
     TRec pr = G.t[P];
     V3 pl, vl;
     touchable_frame(G, P, trec_kind(pr), pg, vg, pl, vl);
+    nc.levels(trec_depth(pr));
     const LRec& L = G.lv[pr.lv];
-    nc.ins();
+    nc.ins(L.info, false);
     if (solid_inside(L.info, L.par, pl, true, vl) != kOut)
       return descend_local(G, P, pl, true, vl, left_slot, nc);
     left_slot = trec_slot(pr);
@@ -743,11 +789,13 @@ __device__ __forceinline__ int navigate(const DevGeom& G, int mode, int T, int l
   V3 pl = x, vl = v;
   if (mode == kNavStart) {
     const LRec& L = G.lv[G.t[T].lv];
-    nc.ins();
+    nc.ins(L.info, false);
     if (solid_inside(L.info, L.par, x, true, v) != kOut) cur = T;  // world frame = global frame
   } else if (mode == kNavEnter) {
     cur = G.t[T].child_base + lim;
-    touchable_frame(G, cur, trec_kind(G.t[cur]), x, v, pl, vl);
+    const TRec tc = G.t[cur];
+    touchable_frame(G, cur, trec_kind(tc), x, v, pl, vl);
+    nc.levels(trec_depth(tc));
   } else {
     TRec tr = G.t[T];
     int left_slot = trec_slot(tr);
@@ -755,8 +803,9 @@ __device__ __forceinline__ int navigate(const DevGeom& G, int mode, int T, int l
     while (P >= 0) {
       TRec pr = G.t[P];
       touchable_frame(G, P, trec_kind(pr), x, v, pl, vl);
+      nc.levels(trec_depth(pr));
       const LRec& L = G.lv[pr.lv];
-      nc.ins();
+      nc.ins(L.info, false);
       if (solid_inside(L.info, L.par, pl, true, vl) != kOut) {
         cur = P;
         blocked = left_slot;
@@ -771,19 +820,27 @@ __device__ __forceinline__ int navigate(const DevGeom& G, int mode, int T, int l
 }
 
 // Entry distance and safety of daughter placement pv, mother frame (pl, vl).
-__device__ __forceinline__ double daughter_dist_in(const DevGeom& G, int pv, V3 pl, V3 vl) {
+// `own_frame`: the candidate is examined for its safety alone (its frame is
+// not already counted with an entry distance).
+template <bool C>
+__device__ __forceinline__ double daughter_dist_in(const DevGeom& G, int pv, V3 pl, V3 vl, NavCount<C>& nc,
+                                                   bool own_frame = true) {
   const PRec& P = G.pv[pv];
   int kind = P.kind;
   V3 pd = xf_point(P.m, kind, pl);
   V3 vd = xf_dir(P.m, kind, vl);
   const LRec& L = G.lv[P.lv];
+  nc.in(L.info, own_frame);
   return solid_dist_in(L.info, L.par, pd, vd);
 }
 
-__device__ __forceinline__ double daughter_safety_in(const DevGeom& G, int pv, V3 pl) {
+template <bool C>
+__device__ __forceinline__ double daughter_safety_in(const DevGeom& G, int pv, V3 pl, NavCount<C>& nc,
+                                                     bool own_frame = false) {
   const PRec& P = G.pv[pv];
   V3 pd = xf_point(P.m, P.kind, pl);
   const LRec& L = G.lv[P.lv];
+  nc.saf(L.info, own_frame);
   double d = solid_d(L.info, L.par, pd);
   return d > 0 ? d : 0.0;
 }
@@ -887,7 +944,8 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
   double s = solid_dist_out(info, L.par, pl, vl);
   double md = solid_d(info, L.par, pl);
   double saf = md < 0 ? -md : 0.0;
-  nc.out();
+  nc.out(info);
+  nc.saf(info, false);
   lim = kLimMother;
   if (start_node) *start_node = int2{0, 0};
   int cnt = L.dau_cnt;
@@ -898,9 +956,8 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
   int base = L.dau_base;
   if (!L.vox) {
     for (int k = 0; k < cnt; k++) {
-      double t = daughter_dist_in(G, base + k, pl, vl);
-      saf = dmin(saf, daughter_safety_in(G, base + k, pl));
-      nc.in();
+      double t = daughter_dist_in(G, base + k, pl, vl, nc);
+      saf = dmin(saf, daughter_safety_in(G, base + k, pl, nc));
       if (t < s) {
         s = t;
         lim = k;
@@ -945,9 +1002,8 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
       }
       {
         int k = G.vox_cand[nd.x + lead];
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        saf = dmin(saf, daughter_safety_in(G, base + k, pl));
-        nc.in();
+        double t = daughter_dist_in(G, base + k, pl, vl, nc);
+        saf = dmin(saf, daughter_safety_in(G, base + k, pl, nc));
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;
@@ -964,12 +1020,11 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
           saf = dmin(saf, lbc);
           continue;
         }
-        const double sf = daughter_safety_in(G, base + k, pl);
+        const double sf = daughter_safety_in(G, base + k, pl, nc, true);
         saf = dmin(saf, sf);
         // skip when the candidate's safety or its bounding box lies beyond the best
         if (sf * (1.0 - 1e-12) > s + kTol || box_beyond(G.pv[base + k], pl, vl, s)) continue;
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        nc.in();
+        double t = daughter_dist_in(G, base + k, pl, vl, nc, false);
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;
@@ -978,9 +1033,8 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, const LRec& L, 
     } else {
       for (int c = 0; c < nd.y; c++) {
         int k = G.vox_cand[nd.x + c];
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        nc.in();
-        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl));
+        double t = daughter_dist_in(G, base + k, pl, vl, nc);
+        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl, nc));
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;
@@ -1111,7 +1165,8 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
     double md = solid_d(info, L.par, pl);
     saf = md < 0 ? -md : 0.0;
   }
-  nc.out();
+  nc.out(info);
+  nc.saf(info, false);
   lim = kLimMother;
   const int cnt = L.dau_cnt;
   if (cnt == 0) {
@@ -1149,8 +1204,9 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
         V3f pd, vd;
         xf_local_f(P, pl, vl, pd, vd);
         double t = (double)solid_dist_in<float>(P.info, P.par, pd, vd);
-        nc.in32();
+        nc.in32(P.info);
         if (first) {
+          nc.saf(P.info, false);
           float d = solid_d<float>(P.info, P.par, pd);
           saf = dmin(saf, d > 0.f ? (double)d : 0.0);
         }
@@ -1163,9 +1219,8 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
       // too few candidates to gain from screening: FP64 as in compute_step
       for (int c = 0; c < nd.y; c++) {
         const int k = slot(c);
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        nc.in();
-        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl));
+        double t = daughter_dist_in(G, base + k, pl, vl, nc);
+        if (first) saf = dmin(saf, daughter_safety_in(G, base + k, pl, nc));
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;
@@ -1180,8 +1235,11 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
         V3f pd, vd;
         xf_local_f(P, pl, vl, pd, vd);
         float t = solid_dist_in<float>(P.info, P.par, pd, vd);
-        nc.in32();
-        if (first) saf = dmin(saf, (double)safety_lo_f(P, pd));
+        nc.in32(P.info);
+        if (first) {
+          nc.saf(P.info, false);
+          saf = dmin(saf, (double)safety_lo_f(P, pd));
+        }
         if (t < tl) {
           tl = t;
           lead = c;
@@ -1189,8 +1247,7 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
       }
       if (lead >= 0) {
         const int k = slot(lead);
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        nc.in();
+        double t = daughter_dist_in(G, base + k, pl, vl, nc);
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;
@@ -1204,8 +1261,7 @@ __device__ __forceinline__ double compute_step_f32(const DevGeom& G, const LRec&
         xf_local_f(P, pl, vl, pd, vd);
         double lb = lower_bound_f(P, pl, vl, pd);
         if (lb * (1.0 - 1e-6) - kTol > s) continue;
-        double t = daughter_dist_in(G, base + k, pl, vl);
-        nc.in();
+        double t = daughter_dist_in(G, base + k, pl, vl, nc);
         if (t < s || (t == s && lim >= 0 && k < lim)) {
           s = t;
           lim = k;

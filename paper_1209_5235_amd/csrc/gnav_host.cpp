@@ -1098,7 +1098,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
     tr.lv = gr.lv_base + gr.h_lv[i];
     tr.parent = gr.h_parent[i] < 0 ? -1 : gr.t_base + gr.h_parent[i];
     tr.child_base = gr.t_base + child[i];
-    tr.slot_kind = (slot[i] & 0xFFFF) | ((ident ? 0 : 1) << 16);
+    tr.slot_kind = (slot[i] & 0xFFFF) | ((ident ? 0 : 1) << 16) | (std::min(gr.h_depth[i], 127) << 24);
     c->t_rec.push_back(tr);
   }
   c->geom_tbase.push_back(gr.t_base);

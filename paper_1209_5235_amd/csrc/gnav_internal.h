@@ -63,6 +63,8 @@ struct TransportLaunch {
 };
 
 bool mlp_view(const gnav_mlp* m, MlpView* out);
+hipError_t launch_mlp_score(const MlpView& M, long n, const float* x, const int* cls, float* logits, int* pred,
+                            hipStream_t st);
 const gnav_ctx* mlp_owner(const gnav_mlp* m);
 // Drop every binding of `mlp` in context c (the network is being freed).
 void unbind_mlp(gnav_ctx* c, const gnav_mlp* mlp);

@@ -276,6 +276,43 @@ hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, 
   return hipGetLastError();
 }
 
+// The transport's candidate-ordering network on n rows of features (float
+// [n][6], rounded to bf16 as the transport rounds its features) and classes:
+// logits [n][64] (optional) and the predicted candidate position [n]
+// (optional), 256 rows per block.
+__global__ void __launch_bounds__(256) k_mlp_score(MlpView M, long n, const float* x, const int* cls,
+                                                   float* logits, int* pred) {
+  __shared__ uint16_t xf[256][6];
+  __shared__ uint16_t cl[256];
+  const int t = threadIdx.x;
+  const long row0 = (long)blockIdx.x * 256;
+  const long i = row0 + t;
+  if (i < n) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) xf[t][k] = lf2bf(x[6 * i + k]);
+    const int c = cls[i];
+    cl[t] = (uint16_t)(c < 0 ? 0 : (c >= M.n_class ? M.n_class - 1 : c));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; k++) xf[t][k] = 0;
+    cl[t] = 0;
+  }
+  __syncthreads();
+  const int rows = (int)std::min<long>(256, n - row0);
+  if (logits) learned_predict<4, true>(M, xf, cl, rows, logits + row0 * 64);
+  else learned_predict<4>(M, xf, cl, rows);
+  __syncthreads();
+  if (pred && i < n) pred[i] = cl[t];
+}
+
+hipError_t launch_mlp_score(const MlpView& M, long n, const float* x, const int* cls, float* logits, int* pred,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_score, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, n, x, cls, logits,
+                     pred);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t words, hipStream_t st) {
   if (words == 0) return hipSuccess;
   unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);

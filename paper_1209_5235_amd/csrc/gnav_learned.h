@@ -50,13 +50,27 @@ __device__ __forceinline__ lbf16x4 load_bf16x4(const uint16_t* p) {
 //
 // Kept out of line (the MFMA operands would otherwise raise the register
 // count of the calling loop); it takes the weights by value so that the
-// caller's argument block is never addressed from the call.
-template <int WAVES>
+// caller's argument block is never addressed from the call.  With LOGITS the
+// 64 logits of row i also go to logits[64 i + c] (float, global memory).
+// A zero the compiler cannot see through (one instruction).
+__device__ __forceinline__ long opaque_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return (long)z;
+}
+
+template <int WAVES, bool LOGITS = false>
 __device__ __attribute__((noinline)) void learned_predict(const MlpView M, uint16_t (*xf)[6], uint16_t* cls_io,
-                                                          int n) {
+                                                          int n, float* logits = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
   for (int row0 = 16 * w; row0 < n; row0 += 16 * WAVES) {
+    // The weight loads of each 16-row tile are issued inside its iteration
+    // and layer by layer: an opaque zero added to every weight address keeps
+    // the compiler from hoisting all of them out of the loop (they would hold
+    // some 130 registers at once, which an out-of-line function must save
+    // and restore around every call).
+    const long wz = opaque_zero();
     const int li = row0 + r;
     const bool valid = li < n;
     const int cls = valid ? cls_io[li] : 0;
@@ -74,7 +88,7 @@ __device__ __attribute__((noinline)) void learned_predict(const MlpView M, uint1
 #pragma unroll
       for (int j = 0; j < 4; j++) {
         const int k = 4 * q + j;
-        wa[j] = (short)(k < 6 ? M.w1x[(16 * t + r) * 6 + k] : 0);
+        wa[j] = (short)(k < 6 ? M.w1x[wz + (16 * t + r) * 6 + k] : 0);
       }
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, x, acc, 0, 0, 0);
@@ -91,7 +105,7 @@ __device__ __attribute__((noinline)) void learned_predict(const MlpView M, uint1
     for (int t = 0; t < 8; t++) {
       lbf16x4 wa[8];
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w2 + (16 * t + r) * 128 + 16 * kt + 4 * q);
+      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w2 + wz + (16 * t + r) * 128 + 16 * kt + 4 * q);
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h1[kt], acc, 0, 0, 0);
@@ -108,7 +122,7 @@ __device__ __attribute__((noinline)) void learned_predict(const MlpView M, uint1
     for (int t = 0; t < 4; t++) {
       lbf16x4 wa[8];
 #pragma unroll
-      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w3 + (16 * t + r) * 128 + 16 * kt + 4 * q);
+      for (int kt = 0; kt < 8; kt++) wa[kt] = load_bf16x4(M.w3 + wz + (16 * t + r) * 128 + 16 * kt + 4 * q);
       lf32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kt = 0; kt < 8; kt++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kt], h2[kt], acc, 0, 0, 0);
@@ -116,6 +130,7 @@ __device__ __attribute__((noinline)) void learned_predict(const MlpView M, uint1
       for (int j = 0; j < 4; j++) {
         const int c = 16 * t + 4 * q + j;
         const float v = acc[j] + M.b3[c];
+        if (LOGITS && valid) logits[(long)li * 64 + c] = v;
         if (best_c < 0 || v > best_v) {  // candidates arrive in increasing order
           best_v = v;
           best_c = c;

@@ -495,6 +495,17 @@ gnav_status gnav_mlp_forward(gnav_ctx* ctx, gnav_mlp* q, int64_t batch, const fl
   return hipGetLastError() == hipSuccess ? GNAV_OK : GNAV_EHIP;
 }
 
+gnav_status gnav_mlp_score(gnav_ctx* ctx, gnav_mlp* q, int64_t n, const float* x_dev, const int32_t* cls_dev,
+                           float* logits_dev, int32_t* pred_dev, void* stream) {
+  if (!ctx || !q || n < 0 || (n > 0 && (!x_dev || !cls_dev))) return GNAV_EINVAL;
+  if (n > (1L << 40)) return GNAV_EINVAL;
+  MlpView M;
+  if (!mlp_view(q, &M)) return GNAV_EINVAL;
+  return launch_mlp_score(M, (long)n, x_dev, cls_dev, logits_dev, pred_dev, (hipStream_t)stream) == hipSuccess
+             ? GNAV_OK
+             : GNAV_EHIP;
+}
+
 gnav_status gnav_mlp_get_params(gnav_ctx* ctx, gnav_mlp* q, float* params_host) {
   if (!ctx || !q || !params_host) return GNAV_EINVAL;
   if (hipDeviceSynchronize() != hipSuccess) return GNAV_EHIP;

@@ -88,6 +88,11 @@ constexpr int kDep = 4 * kPool;
 constexpr int kIntHold = kPool / 4;
 #endif
 
+// counters summed per block in LDS (the work counters of counting launches,
+// from GNAV_C_DIST_IN_BY on, go from each wave to the tally directly)
+constexpr int kBlockCounters = GNAV_C_SCORED + 1;
+static_assert(kBlockCounters <= kPool, "one counter per thread at the block's start and end");
+
 // slot status
 enum : int { kEmpty = 0, kNav = 1, kStep = 2, kInt = 3 };
 // process codes for kInt
@@ -117,7 +122,7 @@ struct Pool {
   int list[kPool];
   int wcnt[16 * kWaves];
   int total[16];
-  unsigned long long cnt[GNAV_NCOUNTERS];
+  unsigned long long cnt[kBlockCounters];
   long qr[4];          // block-claimed primaries not yet started: [qr0, qr1) then [qr2, qr3)
   int qopen;           // the device queue may still hold primaries
   int any_alive;
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   __shared__ Pool P;
   double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
 
-  if (tid < GNAV_NCOUNTERS) P.cnt[tid] = 0ull;
+  if (tid < kBlockCounters) P.cnt[tid] = 0ull;
   if (tid < 4) P.qr[tid] = 0;
   if (tid == 0) {
     P.qopen = 1;
@@ -526,6 +531,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         learned_predict<kWaves>(a.mlp, S.xf, S.cls, n);
         __syncthreads();
         if (tid < n) P.pred[P.list[tid]] = S.cls[tid];
+        if (tid == 0) atomicAdd(&P.cnt[GNAV_C_SCORED], (unsigned long long)n);
       }
       __syncthreads();
     }
@@ -590,6 +596,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           } else {
             V3 pl, vl;
             touchable_frame(G, T, lvk & 1, x, v, pl, vl);
+            if (COUNT) nc.levels(trec_depth(G.t[T]));
             double saf;
             int2 nd;
             s_geo = compute_step_p<COUNT, ORDER, PREC>(G, L, lvk >> 1, pl, vl, lim, saf, nc,
@@ -777,19 +784,29 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   for (int i = tid; i < kDep; i += kPool)
     if (P.dkey[i] >= 0 && P.dval[i] != 0.0) atomic_add_f64(a.edep_t + P.dkey[i], P.dval[i]);
   if (COUNT) {
-    unsigned vals[5] = {nc.dist_in, nc.dist_out, nc.inside, nc.nodes, nc.dist_in32};
-    const int slots[5] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
-                          GNAV_C_DIST_IN_F32};
+    constexpr int kNV = 22;
+    const unsigned vals[kNV] = {nc.total(nc.din), nc.total(nc.dout), nc.total(nc.dins), nc.nodes, nc.dist_in32,
+                                nc.din[0], nc.din[1], nc.din[2], nc.din[3],
+                                nc.dout[0], nc.dout[1], nc.dout[2], nc.dout[3],
+                                nc.dsaf[0], nc.dsaf[1], nc.dsaf[2], nc.dsaf[3],
+                                nc.dins[0], nc.dins[1], nc.dins[2], nc.dins[3], nc.frames};
+    const int slots[kNV] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
+                            GNAV_C_DIST_IN_F32,
+                            GNAV_C_DIST_IN_BY, GNAV_C_DIST_IN_BY + 1, GNAV_C_DIST_IN_BY + 2, GNAV_C_DIST_IN_BY + 3,
+                            GNAV_C_DIST_OUT_BY, GNAV_C_DIST_OUT_BY + 1, GNAV_C_DIST_OUT_BY + 2, GNAV_C_DIST_OUT_BY + 3,
+                            GNAV_C_SAFETY_BY, GNAV_C_SAFETY_BY + 1, GNAV_C_SAFETY_BY + 2, GNAV_C_SAFETY_BY + 3,
+                            GNAV_C_INSIDE_BY, GNAV_C_INSIDE_BY + 1, GNAV_C_INSIDE_BY + 2, GNAV_C_INSIDE_BY + 3,
+                            GNAV_C_FRAME_MAPS};
 #pragma unroll
-    for (int c = 0; c < 5; c++) {
+    for (int c = 0; c < kNV; c++) {
       unsigned long long sum = vals[c];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-      if (lane == 0 && sum) atomicAdd(&P.cnt[slots[c]], sum);
+      if (lane == 0 && sum) atomicAdd(a.counters + slots[c], sum);
     }
   }
   __syncthreads();
-  if (tid < GNAV_NCOUNTERS && P.cnt[tid]) atomicAdd(a.counters + tid, P.cnt[tid]);
+  if (tid < kBlockCounters && P.cnt[tid]) atomicAdd(a.counters + tid, P.cnt[tid]);
 }
 
 hipError_t launch(const TransportLaunch& L, hipStream_t st) {

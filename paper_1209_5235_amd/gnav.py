@@ -24,7 +24,11 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGEOM", -5: "EST
           -6: "EUNSUPPORTED"}
 COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
             "truncated", "tracks", "shortcuts", "dist_in", "dist_out", "inside", "voxel_nodes",
-            "invalid", "dist_in_f32"]
+            "invalid", "dist_in_f32", "scored",
+            "dist_in_box", "dist_in_tubs", "dist_in_cons", "dist_in_orb",
+            "dist_out_box", "dist_out_tubs", "dist_out_cons", "dist_out_orb",
+            "safety_box", "safety_tubs", "safety_cons", "safety_orb",
+            "inside_box", "inside_tubs", "inside_cons", "inside_orb", "frame_maps"]
 # distance arithmetic of ComputeStep (GNAV_PREC_*)
 PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
 LIM_MOTHER, LIM_PE, LIM_COMPTON, LIM_PAIR, LIM_MAX_STEP = -1, -2, -3, -4, -5
@@ -116,6 +120,7 @@ def _load():
         "gnav_mlp_grad": ([P, P, C.c_int64, P, P, P, P, P, P], C.c_int32),
         "gnav_mlp_adam": ([P, P, C.c_float, P], C.c_int32),
         "gnav_mlp_forward": ([P, P, C.c_int64, P, P, P, P], C.c_int32),
+        "gnav_mlp_score": ([P, P, C.c_int64, P, P, P, P, P], C.c_int32),
         "gnav_mlp_get_params": ([P, P, P], C.c_int32),
         "gnav_mlp_free": ([P, P], C.c_int32),
         "gnav_ordering_classes": ([P, C.c_int32, _i32p], C.c_int32),
@@ -157,6 +162,7 @@ gnav_mlp_n_params = lib.gnav_mlp_n_params
 gnav_mlp_grad = lib.gnav_mlp_grad
 gnav_mlp_adam = lib.gnav_mlp_adam
 gnav_mlp_forward = lib.gnav_mlp_forward
+gnav_mlp_score = lib.gnav_mlp_score
 gnav_mlp_get_params = lib.gnav_mlp_get_params
 gnav_mlp_free = lib.gnav_mlp_free
 gnav_ordering_classes = lib.gnav_ordering_classes
@@ -447,6 +453,17 @@ class MLP:
         self.ctx._check(gnav_mlp_forward(self.ctx.h, self.h, x.shape[0], _ptr(x), _ptr(cls), _ptr(out),
                                          _stream(stream)), "gnav_mlp_forward")
         return out
+
+    def score(self, x, cls, stream=None):
+        """gnav_mlp_score: the network as the transport evaluates it; (logits [n][64],
+        predicted position [n])."""
+        import torch
+        n = x.shape[0]
+        logits = torch.empty((n, 64), dtype=torch.float32, device=x.device)
+        pred = torch.empty(n, dtype=torch.int32, device=x.device)
+        self.ctx._check(gnav_mlp_score(self.ctx.h, self.h, n, _ptr(x), _ptr(cls), _ptr(logits), _ptr(pred),
+                                       _stream(stream)), "gnav_mlp_score")
+        return logits, pred
 
     def params(self):
         flat = np.zeros(self.n_params, np.float32)

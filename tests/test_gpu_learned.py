@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests.gpu_common import EXACT, compare_logs
 
 pytestmark = pytest.mark.gpu
 
@@ -121,4 +122,61 @@ def test_training_learns_the_limiting_candidate(barrel):
           losses[-3:], flush=True)
     assert losses[-1] < losses[0]
     assert acc > base
+    net.free()
+
+
+@pytest.mark.parametrize("trained", [True, False])
+def test_learned_order_matches_oracle_per_track(barrel, oracle_lib, trained):
+    """Learned-order transport (bounding-box node lists, where the network
+    scores steps) against the oracle track by track: volume and limiter
+    sequences exact, lengths and deposits within 1e-9.  With an untrained
+    network the predictions are mostly wrong, which exercises the pruning of
+    the candidates it did not pick."""
+    torch, gnav, ctx, gid, desc = barrel
+    print_case("learned_vs_oracle", trained)
+    from oracle import mlp as omlp
+    from paper_1209_5235_amd import learned
+    gid_b, _ = ctx.upload_geometry(desc, voxel_lists=1)
+    n_class = ctx.ordering_classes(gid_b)
+    if trained:
+        _, tprim, _ = W.barrel(n=20000, seed=1)
+        rec = learned.record_crossings(ctx, gid_b, gnav.primaries_to_device(tprim, "cuda"), tprim.n_events,
+                                       capacity=600000, seed=1)
+        x, cls, label = learned.records_to_tensors(rec)
+        net, _ = learned.train(ctx, n_class, x, cls, label, epochs=1, batch=1024)
+    else:
+        net = gnav.MLP(ctx, n_class, omlp.init(n_class, seed=21), max_batch=64)
+    ctx.set_mlp(gid_b, net)
+    _, prim, _ = W.barrel(n=3000, seed=0)
+    cap = 512
+    got = _run(torch, gnav, ctx, gid_b, prim, cap, order=2)
+    ref = oracle_lib.Geometry(desc).transport(prim, seed=0, log_cap=cap)
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, cap)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert np.allclose(got["edep_event"], ref["edep_event"], rtol=1e-9, atol=1e-15)
+    print("scored steps", got["counters"]["scored"], "of", got["counters"]["steps"], flush=True)
+    assert got["counters"]["scored"] > 0
+    ctx.set_mlp(gid_b, None)
+    net.free()
+
+
+def test_learned_order_scores_nothing_without_wide_mothers(barrel):
+    """With shape-aware node lists no barrel mother holds three or more
+    candidates per node on average: order 2 then runs the bound order's walk,
+    and the scored-step counter says so."""
+    torch, gnav, ctx, gid, desc = barrel
+    print_case("learned_no_wide")
+    from oracle import mlp as omlp
+    n_class = ctx.ordering_classes(gid)
+    net = gnav.MLP(ctx, n_class, omlp.init(n_class, seed=21), max_batch=64)
+    ctx.set_mlp(gid, net)
+    _, prim, _ = W.barrel(n=2000, seed=0)
+    got = _run(torch, gnav, ctx, gid, prim, 64, order=2)
+    plain = _run(torch, gnav, ctx, gid, prim, 64, order=0)
+    assert got["counters"]["scored"] == 0
+    assert plain["counters"]["scored"] == 0
+    assert np.array_equal(got["log"]["touchable"], plain["log"]["touchable"])
+    ctx.set_mlp(gid, None)
     net.free()
