@@ -119,6 +119,8 @@ struct DevGeom {
                             //      the mother's z axis, rounded outward
   const PRecF* pvf;         // [PV] FP32 twins of the placements
   const float* lv_parf;     // [LV][12] FP32 twins of the LV solid parameters
+  const int* nbr;           // [T][6] face neighbours of box touchables (global id, -1: none): the
+                            //   touchable found just outside the centre of face 2 axis + (side > 0)
   double lnE0, dlnE;
 };
 
@@ -187,6 +189,26 @@ __device__ __forceinline__ R tmin(R a, R b) { return a < b ? a : b; }
 template <typename R>
 __device__ __forceinline__ R box_d(const R* h, Vec3<R> p) {
   return tmax(tmax(fabs(p.x) - h[0], fabs(p.y) - h[1]), fabs(p.z) - h[2]);
+}
+
+// Face of a box (half lengths h) nearest to the point q on or near its
+// boundary: 2 axis + (q on the positive side), the axis of the largest
+// |q_a| - h_a (the lowest axis on ties).
+__device__ __forceinline__ int box_face(const double* h, V3 q) {
+  const double sx = fabs(q.x) - h[0], sy = fabs(q.y) - h[1], sz = fabs(q.z) - h[2];
+  int a = 0;
+  double m = sx;
+  double c = q.x;
+  if (sy > m) {
+    a = 1;
+    m = sy;
+    c = q.y;
+  }
+  if (sz > m) {
+    a = 2;
+    c = q.z;
+  }
+  return 2 * a + (c > 0 ? 1 : 0);
 }
 
 __device__ __forceinline__ int box_inside(const double* h, V3 p, bool has_v, V3 v) {
@@ -780,13 +802,32 @@ __device__ __forceinline__ int relocate(const DevGeom& G, int T, const TRec& tr,
 // T, or leaving T (climb while outside the parent, then search it with the
 // left volume excluded).  Returns the new touchable (-1: outside the world)
 // and (its LV << 1) | transform kind.
+//
+// Leaving a box through face `face` (0-5, -1 unknown) first tries that face's
+// neighbour N from G.nbr: when N holds the point (the same inside test with
+// the direction rule), the answer is the descent from N, which is what the
+// climb and search would reach: in a geometry of non-overlapping volumes the
+// touchables holding a point under the direction rule form one chain from the
+// world, so the climb stops at an ancestor of N and the search then enters
+// N's branch.  Otherwise the climb and search run as usual.
 enum : int { kNavStart = 1, kNavEnter = 2, kNavExit = 3 };
 
 template <bool C>
 __device__ __forceinline__ int navigate(const DevGeom& G, int mode, int T, int lim, V3 x, V3 v, int& lvk_out,
-                                        NavCount<C>& nc) {
+                                        NavCount<C>& nc, int face = -1) {
   int cur = -1, blocked = -1;
   V3 pl = x, vl = v;
+  if (mode == kNavExit && face >= 0) {
+    const int N = G.nbr[(long)T * 6 + face];
+    if (N >= 0) {
+      const TRec tn = G.t[N];
+      touchable_frame(G, N, trec_kind(tn), x, v, pl, vl);
+      nc.levels(trec_depth(tn));
+      const LRec& L = G.lv[tn.lv];
+      nc.ins(L.info, false);
+      if (solid_inside(L.info, L.par, pl, true, vl) == kIn) return descend_local(G, N, pl, true, vl, -1, nc, &lvk_out);
+    }
+  }
   if (mode == kNavStart) {
     const LRec& L = G.lv[G.t[T].lv];
     nc.ins(L.info, false);

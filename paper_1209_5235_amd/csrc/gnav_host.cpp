@@ -596,7 +596,7 @@ struct gnav_ctx {
   double lnE0 = 0, dlnE = 0;
   // device copies
   DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_pv_cyl, d_lv_parf, d_vox_node, d_vox_cand, d_xs,
-      d_mat_rho, d_geom_tbase;
+      d_mat_rho, d_geom_tbase, d_nbr;
   DevBuf d_queue, d_pend;
   DevGeom G{};
   // Generations of what a captured graph holds: the resident tables (every
@@ -656,6 +656,60 @@ hipError_t scratch_address(int device, void** out) {
     if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
   } while (0)
 
+// Face neighbours of box touchables (G.nbr), the relocation shortcut: for
+// each face of each box touchable other than a world, the touchable that
+// LocateGlobalPoint finds 1e-6 mm outside the face's centre, moving outward
+// (global id, -1 outside the world).  A hint only: the transport uses it
+// after checking that the neighbour holds the crossing point.
+hipError_t build_face_neighbours(gnav_ctx* c, hipStream_t stream) {
+  const int nt = (int)c->t_rec.size();
+  std::vector<int> nbr((size_t)nt * 6, -1);
+  std::vector<double> pos, dir;
+  std::vector<int> slot;  // index into nbr of each query
+  constexpr double kOutside = 1e-6;
+  hipError_t e = hipSuccess;
+  for (const GeomRec& g : c->geoms) {
+    pos.clear();
+    dir.clear();
+    slot.clear();
+    for (int i = 1; i < g.n_t; i++) {
+      const int T = g.t_base + i;
+      const LRec& L = c->lv_rec[c->t_rec[T].lv];
+      if ((L.info & 15) != kBox) continue;
+      const double* m = &c->t_xf[(size_t)T * 12];  // local = M (x - t)
+      for (int f = 0; f < 6; f++) {
+        const int a = f / 2;
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        double ql[3] = {0.0, 0.0, 0.0}, vl[3] = {0.0, 0.0, 0.0};
+        ql[a] = sg * (L.par[a] + kOutside);
+        vl[a] = sg;
+        for (int r = 0; r < 3; r++) {  // x = M^T local + t (M orthonormal)
+          pos.push_back(m[r] * ql[0] + m[3 + r] * ql[1] + m[6 + r] * ql[2] + m[9 + r]);
+          dir.push_back(m[r] * vl[0] + m[3 + r] * vl[1] + m[6 + r] * vl[2]);
+        }
+        slot.push_back(T * 6 + f);
+      }
+    }
+    const long n = (long)slot.size();
+    if (n == 0) continue;
+    DevBuf dp, dd, dout;
+    if ((e = dp.upload(pos.data(), pos.size() * sizeof(double), stream)) != hipSuccess) return e;
+    if ((e = dd.upload(dir.data(), dir.size() * sizeof(double), stream)) != hipSuccess) return e;
+    if ((e = dout.upload(nullptr, n * sizeof(int), stream)) != hipSuccess) return e;
+    if ((e = launch_locate(c->G, g.t_base, g.t_base, n, dp.as<double>(), dd.as<double>(), dout.as<int>(), stream)) !=
+        hipSuccess)
+      return e;
+    std::vector<int> out(n);
+    if ((e = hipMemcpyAsync(out.data(), dout.p, n * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+    for (long q = 0; q < n; q++) nbr[slot[q]] = out[q] < 0 ? -1 : g.t_base + out[q];
+  }
+  if ((e = up(c->d_nbr, nbr, stream)) != hipSuccess) return e;
+  c->G.nbr = c->d_nbr.as<int>();
+  return hipStreamSynchronize(stream);
+}
+
 hipError_t upload_all(gnav_ctx* c, hipStream_t stream) {
   hipError_t e;
   c->tables_gen++;
@@ -688,7 +742,9 @@ hipError_t upload_all(gnav_ctx* c, hipStream_t stream) {
   G.mat_rho = c->d_mat_rho.as<double>();
   G.lnE0 = c->lnE0;
   G.dlnE = c->dlnE;
-  return hipStreamSynchronize(stream);
+  G.nbr = nullptr;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  return build_face_neighbours(c, stream);
 }
 
 // Nearest float not above / not below x.

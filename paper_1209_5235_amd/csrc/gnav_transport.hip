@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
       if (tid < n) {
         const int s = P.list[tid];
         const int mode = P.aux[s] & 3;
-        const int lim = P.aux[s] >> 2;
+        const int lim = P.aux[s] >> 2;  // entered slot, or (exits) the face left (-1 unknown)
         V3 x{P.x[s], P.y[s], P.z[s]}, v{P.vx[s], P.vy[s], P.vz[s]};
         if (mode == kNavStart) {
           digest_start<LOG>(P, a, s);
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           P.saf[s] = 0.0;
         }
         int lvk = 0;
-        int nt = navigate(G, mode, P.T[s], lim, x, v, lvk, nc);
+        int nt = navigate(G, mode, P.T[s], lim, x, v, lvk, nc, mode == kNavExit ? lim : -1);
         if (nt < 0) {
           atomic_add_f64(a.esc_ev + P.event[s], P.E[s]);
           end_track<LOG>(P, a, s, GNAV_FATE_ESCAPED, P.zero_steps[s] >> 8);
@@ -590,6 +590,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           bool phys;
           double s_geo = kInf;
           int lim = kLimMother;
+          int exit_face = -1;
           if (s_phys < safety - kTol) {
             phys = true;
             P.cnt_a[s] += 1u << 16;
@@ -603,6 +604,9 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
                                                        ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
             safety = saf;
             phys = s_phys <= s_geo;
+            // the face a box is left through, for the neighbour shortcut of the relocation
+            if (!phys && lim == kLimMother && (L.info & 15) == kBox)
+              exit_face = box_face(L.par, V3{pl.x + s_geo * vl.x, pl.y + s_geo * vl.y, pl.z + s_geo * vl.z});
             // crossing recorder: a daughter-limited step from a node with 2+ candidates
             if (a.rec && !phys && lim >= 0 && nd.y >= 2 && L.lclass >= 0) {
               int label = -1;
@@ -677,7 +681,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
                 P.cnt_b[s] += 1u << 24;
               }
               // relocation happens in the next iteration's navigation phase
-              P.aux[s] = (lim >= 0 ? kNavEnter : kNavExit) | (lim << 2);
+              P.aux[s] = lim >= 0 ? (kNavEnter | (lim << 2)) : (kNavExit | (exit_face << 2));
               P.status[s] = kNav;
             }
           }
