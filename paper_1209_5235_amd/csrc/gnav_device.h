@@ -804,12 +804,15 @@ __device__ __forceinline__ int relocate(const DevGeom& G, int T, const TRec& tr,
 // and (its LV << 1) | transform kind.
 //
 // Leaving a box through face `face` (0-5, -1 unknown) first tries that face's
-// neighbour N from G.nbr: when N holds the point (the same inside test with
-// the direction rule), the answer is the descent from N, which is what the
-// climb and search would reach: in a geometry of non-overlapping volumes the
-// touchables holding a point under the direction rule form one chain from the
-// world, so the climb stops at an ancestor of N and the search then enters
-// N's branch.  Otherwise the climb and search run as usual.
+// neighbour N from G.nbr (never an ancestor of the box): when N holds the
+// point (the same inside test with the direction rule), the answer is the
+// descent from N, which is what the climb and search reach.  In a geometry of
+// non-overlapping volumes the touchables other than the box left that hold a
+// point under the direction rule form one chain from the world (siblings
+// sharing a face are told apart by the sign of v.n), so the climb stops at
+// the lowest common ancestor of the box and N, whose search (the box's branch
+// excluded) enters N's branch, and the descent below N is the same.
+// Otherwise the climb and search run as usual.
 enum : int { kNavStart = 1, kNavEnter = 2, kNavExit = 3 };
 
 template <bool C>

@@ -659,7 +659,11 @@ hipError_t scratch_address(int device, void** out) {
 // Face neighbours of box touchables (G.nbr), the relocation shortcut: for
 // each face of each box touchable other than a world, the touchable that
 // LocateGlobalPoint finds 1e-6 mm outside the face's centre, moving outward
-// (global id, -1 outside the world).  A hint only: the transport uses it
+// (global id), or -1 when that is outside the world or an ancestor of the
+// box.  An ancestor is no shortcut: the relocation searches it with the box
+// excluded, and the box may still pass its own inside test at a point its
+// exit distance put on the face (within the tolerance), so a search that
+// did not exclude it could return to it.  A hint only: the transport uses it
 // after checking that the neighbour holds the crossing point.
 hipError_t build_face_neighbours(gnav_ctx* c, hipStream_t stream) {
   const int nt = (int)c->t_rec.size();
@@ -703,7 +707,13 @@ hipError_t build_face_neighbours(gnav_ctx* c, hipStream_t stream) {
     if ((e = hipMemcpyAsync(out.data(), dout.p, n * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
-    for (long q = 0; q < n; q++) nbr[slot[q]] = out[q] < 0 ? -1 : g.t_base + out[q];
+    for (long q = 0; q < n; q++) {
+      if (out[q] < 0) continue;
+      const int N = g.t_base + out[q];
+      int A = c->t_rec[slot[q] / 6].parent;
+      while (A >= 0 && A != N) A = c->t_rec[A].parent;
+      if (A < 0) nbr[slot[q]] = N;
+    }
   }
   if ((e = up(c->d_nbr, nbr, stream)) != hipSuccess) return e;
   c->G.nbr = c->d_nbr.as<int>();
