@@ -59,7 +59,7 @@ def algorithmic_flops(c, precision=0):
     saf = sum(UNIT_FLOPS["safety"][f] * (c["safety_" + f] + c["inside_" + f]) for f in FAMILIES)
     other = (UNIT_FLOPS["frame"] * c["frame_maps"] + UNIT_FLOPS["node"] * c["voxel_nodes"]
              + UNIT_FLOPS["step"] * c["steps"] + UNIT_FLOPS["interaction"] * (c["pe"] + c["compton"] + c["pair"]))
-    f32_share = c["dist_in_f32"] / max(c["dist_in"], 1) if precision else 0.0
+    f32_share = c["dist_in_f32"] / max(c["dist_in"] + c["dist_in_f32"], 1) if precision else 0.0
     f32 = din * f32_share + ((dout + saf) if precision == 2 else 0.0)
     f64 = din + dout + saf + other - f32
     return float(f64), float(f32)
@@ -265,7 +265,7 @@ def barrel_variants(ctx, gnav, n, reps, oracle_sample=0):
     def entry(ms, res, work, precision=0, order=0):
         k = kernel_name(64, False, precision, order)
         e = {"ms": ms, "steps_per_s": res["counters"]["steps"] / ms * 1e3, "speedup": base_ms / ms,
-             "dist_in_fp64": work["dist_in"] - work["dist_in_f32"], "dist_in_fp32": work["dist_in_f32"],
+             "dist_in_fp64": work["dist_in"], "dist_in_fp32": work["dist_in_f32"],
              "same_counters": _same_counters(res, base),
              "roofline": roofline(work, ms, k, precision, stored_traffic(k, wl))}
         d = np.abs(res["edep_event"] - base["edep_event"]) / np.maximum(base["edep_event"], 1e-300)

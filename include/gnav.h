@@ -79,7 +79,7 @@ typedef int32_t gnav_status;
 #define GNAV_C_TRUNCATED 9      /* tracks stopped at max_steps_per_track */
 #define GNAV_C_TRACKS 10        /* tracks started (primaries + annihilation photons) */
 #define GNAV_C_SHORTCUTS 11     /* physics steps taken inside the safety (no ComputeStep) */
-#define GNAV_C_DIST_IN 12       /* daughter entry-distance evaluations (count_work = 1) */
+#define GNAV_C_DIST_IN 12       /* daughter entry distances evaluated in FP64 (count_work = 1) */
 #define GNAV_C_DIST_OUT 13      /* mother exit-distance evaluations (count_work = 1) */
 #define GNAV_C_INSIDE 14        /* point-in-solid tests, locate / relocate (count_work = 1) */
 #define GNAV_C_VOXEL_NODES 15   /* voxel nodes visited by the step walk (count_work = 1) */

@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     if (P.dkey[i] >= 0 && P.dval[i] != 0.0) atomic_add_f64(a.edep_t + P.dkey[i], P.dval[i]);
   if (COUNT) {
     constexpr int kNV = 22;
-    const unsigned vals[kNV] = {nc.total(nc.din), nc.total(nc.dout), nc.total(nc.dins), nc.nodes, nc.dist_in32,
+    const unsigned vals[kNV] = {nc.total(nc.din) - nc.dist_in32, nc.total(nc.dout), nc.total(nc.dins), nc.nodes, nc.dist_in32,
                                 nc.din[0], nc.din[1], nc.din[2], nc.din[3],
                                 nc.dout[0], nc.dout[1], nc.dout[2], nc.dout[3],
                                 nc.dsaf[0], nc.dsaf[1], nc.dsaf[2], nc.dsaf[3],

@@ -49,7 +49,7 @@ def test_algorithmic_flops_counts_each_unit():
     cell = dict(zero, steps=1, frame_maps=3, dist_out_box=1, safety_box=1)
     assert sum(bench.algorithmic_flops(cell)) == 3 * 33 + 15 + 8 + 10
     # FP32 forms: the FP32 share of the entry distances (and, pure, exits and safeties)
-    c = dict(zero, dist_in=4, dist_in_f32=2, dist_in_tubs=4, dist_out_tubs=1, safety_tubs=1)
+    c = dict(zero, dist_in=2, dist_in_f32=2, dist_in_tubs=4, dist_out_tubs=1, safety_tubs=1)
     f64, f32 = bench.algorithmic_flops(c, precision=1)
     assert f32 == 2 * u["dist_in"]["tubs"] and f64 == 2 * u["dist_in"]["tubs"] + 90 + 20
     f64, f32 = bench.algorithmic_flops(c, precision=2)
@@ -62,7 +62,7 @@ def test_roofline_mixes_peaks_by_work():
     r = bench.roofline(c, 1.0, "k")
     assert r["peak"] == bench.PEAK_FP64_TFLOPS and abs(r["achieved"] - 10.0) < 1e-9
     assert r["frac"] == r["fp64_frac"] and r["traffic"] is None
-    c = dict(zero, dist_in=1, dist_in_f32=1, dist_in_box=10 ** 9)
+    c = dict(zero, dist_in=0, dist_in_f32=1, dist_in_box=10 ** 9)
     r = bench.roofline(c, 1.0, "k", precision=1, traffic=8e9)
     assert r["peak"] == bench.PEAK_FP32_TFLOPS and r["hbm_gbs"] == 8000.0 and r["hbm_frac"] == 1.0
 
