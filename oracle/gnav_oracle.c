@@ -39,6 +39,7 @@
 #define OG_TUBS 1
 #define OG_CONS 2
 #define OG_ORB 3
+#define OG_TRD 4
 
 #define OG_IN 1
 #define OG_SURF 0
@@ -186,6 +187,8 @@ typedef struct {
   double Ao, Bo, co, Ai, Bi, ci, dz;
   int has_inner, has_phi;
   double ns[2], ne[2]; /* outward normals of the start and end phi planes */
+  /* trapezoid: the six face planes n . p = h (n unit, outward): +x, -x, +y, -y, +z, -z */
+  double pn[6][3], ph[6];
 } og_solid;
 
 /* component slots */
@@ -200,6 +203,31 @@ static int solid_init(og_solid* s, int type, const double* par) {
   }
   if (type == OG_ORB) {
     return par[0] > 0 ? 0 : -1;
+  }
+  if (type == OG_TRD) {
+    /* half lengths dx1, dx2 (x at z = -dz, +dz), dy1, dy2, half length dz: the
+     * x faces are the planes |x| = ax + bx z, ax = (dx1 + dx2) / 2,
+     * bx = (dx2 - dx1) / (2 dz), likewise y */
+    double dx1 = par[0], dx2 = par[1], dy1 = par[2], dy2 = par[3], dz = par[4];
+    if (!(dx1 > 0 && dx2 > 0 && dy1 > 0 && dy2 > 0 && dz > 0)) return -1;
+    double a[2] = {0.5 * (dx1 + dx2), 0.5 * (dy1 + dy2)};
+    double b[2] = {(dx2 - dx1) / (2.0 * dz), (dy2 - dy1) / (2.0 * dz)};
+    for (int ax = 0; ax < 2; ax++) {
+      double c = 1.0 / sqrt(1.0 + b[ax] * b[ax]);
+      for (int sg = 0; sg < 2; sg++) {
+        double* n = s->pn[2 * ax + sg];
+        n[0] = n[1] = n[2] = 0.0;
+        n[ax] = (sg == 0 ? 1.0 : -1.0) * c;
+        n[2] = -b[ax] * c;
+        s->ph[2 * ax + sg] = a[ax] * c;
+      }
+    }
+    s->pn[4][0] = s->pn[4][1] = s->pn[5][0] = s->pn[5][1] = 0.0;
+    s->pn[4][2] = 1.0;
+    s->pn[5][2] = -1.0;
+    s->ph[4] = s->ph[5] = dz;
+    s->dz = dz;
+    return 0;
   }
   double rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi;
   if (type == OG_TUBS) {
@@ -286,6 +314,15 @@ static void rad_comps(const og_solid* s, const double* p, double k[K_N]) {
   }
 }
 
+/* Signed distance of p from face plane i of a trapezoid (negative inside). */
+static double trd_plane(const og_solid* s, int i, const double* p) {
+  return s->pn[i][0] * p[0] + s->pn[i][1] * p[1] + s->pn[i][2] * p[2] - s->ph[i];
+}
+
+static double trd_dot(const og_solid* s, int i, const double* v) {
+  return s->pn[i][0] * v[0] + s->pn[i][1] * v[1] + s->pn[i][2] * v[2];
+}
+
 /* The solid's signed value d(p). */
 double og_solid_d(const og_solid* s, const double* p) {
   if (s->type == OG_BOX) {
@@ -296,6 +333,11 @@ double og_solid_d(const og_solid* s, const double* p) {
   }
   if (s->type == OG_ORB) {
     return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - s->par[0];
+  }
+  if (s->type == OG_TRD) {
+    double d = -kInf;
+    for (int i = 0; i < 6; i++) d = max2(d, trd_plane(s, i, p));
+    return d;
   }
   double k[K_N];
   rad_comps(s, p, k);
@@ -356,6 +398,15 @@ int og_solid_inside(const og_solid* s, const double* p, const double* v) {
     NOTE_LEN(b, 0.0);
     return b < 0 ? OG_IN : OG_OUT;
   }
+  if (s->type == OG_TRD) {
+    for (int i = 0; i < 6; i++) {
+      double di = trd_plane(s, i, p);
+      NOTE_LEN(fabs(di), kHalf);
+      if (fabs(di) <= kHalf) note(trd_dot(s, i, v), 0.0, 1.0);
+      if (fabs(di) <= kHalf && trd_dot(s, i, v) >= 0) return OG_OUT;
+    }
+    return OG_IN;
+  }
   double k[K_N];
   rad_comps(s, p, k);
   return rad_moving_in(s, p, v, k) ? OG_IN : OG_OUT;
@@ -382,8 +433,8 @@ double og_solid_safety_out(const og_solid* s, const double* p) {
  * value is within the tolerance of the largest (1 on a face, 2 or more on an
  * edge or corner). */
 int og_solid_normal(const og_solid* s, const double* p, double n[3]) {
-  double val[K_N];
-  double grad[K_N][3];
+  double val[6];
+  double grad[6][3];
   int nf;
   memset(grad, 0, sizeof(grad));
   if (s->type == OG_BOX) {
@@ -391,6 +442,13 @@ int og_solid_normal(const og_solid* s, const double* p, double n[3]) {
     for (int i = 0; i < 3; i++) {
       val[i] = fabs(p[i]) - s->par[i];
       grad[i][i] = p[i] < 0 ? -1.0 : 1.0; /* d|p_i|/dp_i */
+    }
+  } else if (s->type == OG_TRD) {
+    /* faces in order +x, -x, +y, -y, +z, -z */
+    nf = 6;
+    for (int i = 0; i < 6; i++) {
+      val[i] = trd_plane(s, i, p);
+      for (int c = 0; c < 3; c++) grad[i][c] = s->pn[i][c];
     }
   } else if (s->type == OG_ORB) {
     double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
@@ -699,10 +757,52 @@ static double rad_dist_out(const og_solid* s, const double* p, const double* v) 
   return t;
 }
 
+/* Trapezoid, a convex solid of six planes: entering distance as the latest
+ * plane entry before the earliest plane exit, with the box's tolerance rules
+ * (a face whose band holds p, or beyond it, that the ray does not cross
+ * inward can never be crossed: no entry; a start point on the band moving in
+ * gives 0). */
+static double trd_dist_in(const og_solid* s, const double* p, const double* v) {
+  double dv[6], dp[6];
+  for (int i = 0; i < 6; i++) {
+    dp[i] = trd_plane(s, i, p);
+    dv[i] = trd_dot(s, i, v);
+    NOTE_LEN(dp[i], -kHalf);
+    if (dp[i] >= -kHalf) note(dv[i], 0.0, 1.0);
+    if (dp[i] >= -kHalf && dv[i] >= 0) return kInf;
+  }
+  double te = -kInf, tx = kInf;
+  for (int i = 0; i < 6; i++) {
+    if (dv[i] == 0.0) continue;
+    double t = -dp[i] / dv[i];
+    if (dv[i] < 0) te = max2(te, t);
+    else tx = min2(tx, t);
+  }
+  if (te > -kInf && tx < kInf) NOTE_LEN(te, tx - kHalf);
+  if (te >= tx - kHalf) return kInf;
+  NOTE_LEN(te, kHalf);
+  return te < kHalf ? 0.0 : te;
+}
+
+/* Leaving distance: the earliest plane exit; 0 on a face band moving out. */
+static double trd_dist_out(const og_solid* s, const double* p, const double* v) {
+  double t = kInf;
+  for (int i = 0; i < 6; i++) {
+    double dv = trd_dot(s, i, v);
+    if (!(dv > 0)) continue;
+    double sd = -trd_plane(s, i, p);
+    NOTE_LEN(sd, kHalf);
+    if (sd <= kHalf) return 0.0;
+    t = min2(t, sd / dv);
+  }
+  return t;
+}
+
 double og_solid_dist_in(const og_solid* s, const double* p, const double* v) {
   switch (s->type) {
     case OG_BOX: return box_dist_in(s, p, v);
     case OG_ORB: return orb_dist_in(s, p, v);
+    case OG_TRD: return trd_dist_in(s, p, v);
     default: return rad_dist_in(s, p, v);
   }
 }
@@ -711,6 +811,7 @@ double og_solid_dist_out(const og_solid* s, const double* p, const double* v) {
   switch (s->type) {
     case OG_BOX: return box_dist_out(s, p, v);
     case OG_ORB: return orb_dist_out(s, p, v);
+    case OG_TRD: return trd_dist_out(s, p, v);
     default: return rad_dist_out(s, p, v);
   }
 }
@@ -1008,6 +1109,16 @@ typedef struct og_vgrid {
  * directions the segment spans. */
 static void solid_box(const og_solid* s, double lo[3], double hi[3]) {
   const double* p = s->par;
+  if (s->type == OG_TRD) {
+    const double hx = max2(p[0], p[1]), hy = max2(p[2], p[3]);
+    lo[0] = -hx;
+    hi[0] = hx;
+    lo[1] = -hy;
+    hi[1] = hy;
+    lo[2] = -p[4];
+    hi[2] = p[4];
+    return;
+  }
   if (s->type == OG_BOX || s->type == OG_ORB) {
     for (int i = 0; i < 3; i++) {
       double h = s->type == OG_BOX ? p[i] : p[0];
@@ -1813,6 +1924,7 @@ int og_transport(const og_geom* g, int64_t n, const int32_t* event, const int32_
     const og_solid* w = lv_solid_of(g, g->world_lv);
     double e = w->par[0];
     if (w->type == OG_BOX) e = max2(w->par[0], max2(w->par[1], w->par[2]));
+    else if (w->type == OG_TRD) e = max2(max2(max2(w->par[0], w->par[1]), max2(w->par[2], w->par[3])), w->par[4]);
     else if (w->type != OG_ORB) e = max2(w->Ao + fabs(w->Bo) * w->dz, w->dz);
     og_scale = max2(1.0, e);
   }

@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-BOX, TUBS, CONS, ORB = 0, 1, 2, 3
+BOX, TUBS, CONS, ORB, TRD = 0, 1, 2, 3, 4
 
 
 def _phi_member(p, sphi, dphi):
@@ -36,6 +36,19 @@ def member(stype, par, p):
     if stype == ORB:
         r = np.linalg.norm(p, axis=1)
         return r < par[0], np.abs(r - par[0])
+    if stype == TRD:
+        # half widths interpolated end to end between z = -dz and z = +dz
+        dx1, dx2, dy1, dy2, dz = par[:5]
+        z = p[:, 2]
+        f = (z + dz) / (2 * dz)
+        hx = dx1 + (dx2 - dx1) * f
+        hy = dy1 + (dy2 - dy1) * f
+        inside = (np.abs(z) < dz) & (np.abs(p[:, 0]) < hx) & (np.abs(p[:, 1]) < hy)
+        tx = math.atan2(dx2 - dx1, 2 * dz)
+        ty = math.atan2(dy2 - dy1, 2 * dz)
+        m = np.minimum(np.abs(np.abs(z) - dz), np.abs(hx - np.abs(p[:, 0])) * math.cos(tx))
+        m = np.minimum(m, np.abs(hy - np.abs(p[:, 1])) * math.cos(ty))
+        return inside, m
     if stype == TUBS:
         rmin1 = rmin2 = par[0]
         rmax1 = rmax2 = par[1]

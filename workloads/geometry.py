@@ -19,7 +19,7 @@ import math
 import numpy as np
 
 # Solid type codes shared by the flat description.
-BOX, TUBS, CONS, ORB = 0, 1, 2, 3
+BOX, TUBS, CONS, ORB, TRD = 0, 1, 2, 3, 4
 NPAR = 8
 
 # Material composition table: name -> (density g/cm3, [(Z, A g/mol, mass fraction)]).
@@ -377,6 +377,39 @@ def solids_zoo(seed=5):
     for i, ((st, par), c) in enumerate(zip(shapes, centres)):
         s = b.solid(st, *par)
         lv = b.lv(s, mats[i % 3], f"zoo{i}")
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        w, x, y, z = q
+        R = np.array([
+            [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+            [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+            [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+        ])
+        off = rng.uniform(-60.0, 60.0, size=3)
+        b.place(world, lv, R, tuple(np.array(c) + off))
+    return b.build(world)
+
+
+def solids_zoo_more(seed=6):
+    """The solid families beyond the paper's boxes, tubes, cones and balls: one
+    rotated and translated daughter each (trapezoids of both tapers, and a
+    near-box) in a box world, for the per-solid tests of those families."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    b = Builder("zoo_more")
+    s_world = b.solid(BOX, 1000.0, 1000.0, 1000.0)
+    world = b.lv(s_world, "vacuum", "world")
+    shapes = [
+        (TRD, (60.0, 120.0, 90.0, 40.0, 80.0)),
+        (TRD, (100.0, 30.0, 70.0, 70.0, 50.0)),
+        (TRD, (80.0, 80.0, 80.0, 80.0, 80.0)),
+        (TRD, (20.0, 140.0, 120.0, 10.0, 110.0)),
+    ]
+    centres = [(-500.0, -500.0, -500.0), (500.0, -500.0, 500.0), (-500.0, 500.0, 500.0),
+               (500.0, 500.0, -500.0)]
+    mats = ["water", "lead", "silicon"]
+    for i, ((st, par), c) in enumerate(zip(shapes, centres)):
+        s = b.solid(st, *par)
+        lv = b.lv(s, mats[i % 3], f"more{i}")
         q = rng.normal(size=4)
         q /= np.linalg.norm(q)
         w, x, y, z = q
