@@ -47,17 +47,23 @@ typedef int32_t gnav_status;
 #define GNAV_ESTATE (-5)       /* call out of order (e.g. no geometry yet) */
 #define GNAV_EUNSUPPORTED (-6) /* valid request the library does not implement */
 
-/* Solid families (Sec. 3.5 names boxes, tubes, cones and balls).
+/* Solid families (Sec. 3.5 names boxes, tubes, cones and balls, and its CMS
+ * case other Geant4 solids such as trapezoids).
  * Parameters, 8 doubles per solid:
  *   GNAV_BOX  hx, hy, hz                               (half lengths)
  *   GNAV_TUBS rmin, rmax, dz, sphi, dphi               (tube section, half length dz)
  *   GNAV_CONS rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi (cone section; 1 at -dz, 2 at +dz)
  *   GNAV_ORB  r                                        (full ball)
+ *   GNAV_TRD  dx1, dx2, dy1, dy2, dz                   (trapezoid: x half width dx1 at
+ *                                                       z = -dz, dx2 at +dz, linear between;
+ *                                                       likewise y; all positive)
  * Sections need 0 <= rmin < rmax at both ends and dphi in (0, pi] or 2 pi. */
 #define GNAV_BOX 0
 #define GNAV_TUBS 1
 #define GNAV_CONS 2
 #define GNAV_ORB 3
+#define GNAV_TRD 4
+#define GNAV_NFAMILIES 6 /* family slots of the work counters (slot 5 reserved) */
 
 /* Surface tolerance (mm): points within half of it of a surface lie on it. */
 #define GNAV_TOLERANCE 1e-9
@@ -87,14 +93,14 @@ typedef int32_t gnav_status;
 #define GNAV_C_DIST_IN_F32 17   /* daughter entry distances evaluated in FP32 (FP32 precisions) */
 #define GNAV_C_SCORED 18        /* learned order: steps whose start-node candidates the network ordered */
 /* Work by solid family (batches with count_work = 1; zero otherwise): slot
- * base + GNAV_BOX .. base + GNAV_ORB. */
+ * base + family (GNAV_BOX .. GNAV_TRD; GNAV_NFAMILIES slots each). */
 #define GNAV_C_DIST_IN_BY 19    /* daughter entry distances (FP64 and FP32) by the daughter's family */
-#define GNAV_C_DIST_OUT_BY 23   /* mother exit distances by the mother's family */
-#define GNAV_C_SAFETY_BY 27     /* isotropic distances (mother and daughter safeties) by family */
-#define GNAV_C_INSIDE_BY 31     /* point-in-solid tests by family */
-#define GNAV_C_FRAME_MAPS 35    /* frame maps: one per daughter candidate examined, one per placement
+#define GNAV_C_DIST_OUT_BY 25   /* mother exit distances by the mother's family */
+#define GNAV_C_SAFETY_BY 31     /* isotropic distances (mother and daughter safeties) by family */
+#define GNAV_C_INSIDE_BY 37     /* point-in-solid tests by family */
+#define GNAV_C_FRAME_MAPS 43    /* frame maps: one per daughter candidate examined, one per placement
                                    level of each touchable frame formed (level by level, Sec. 3.2) */
-#define GNAV_NCOUNTERS 36
+#define GNAV_NCOUNTERS 44
 
 /* Limiter codes of a step. */
 #define GNAV_LIM_MOTHER (-1)    /* left the current volume (>= 0: entered that daughter slot) */

@@ -19,6 +19,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "gnav.h"
 
 namespace gnav {
 
@@ -32,7 +33,7 @@ constexpr int kZeroPush = 10;
 constexpr int kZeroKill = 25;
 constexpr int kMaxComptonTrials = 1000;
 
-enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3 };
+enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3, kTrd = 4 };
 enum : int { kOut = -1, kIn = 1 };
 enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4, kLimMaxStep = -5 };
 
@@ -259,6 +260,96 @@ __device__ __forceinline__ R box_dist_out(const R* h, Vec3<R> p, Vec3<R> v) {
     else continue;
     if (sd <= ht) return zero;
     t = tmin(t, sd / fabs(vc[i]));
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Trapezoid: x and y half widths linear in z between -dz and +dz, a convex
+// solid of six face planes +x, -x, +y, -y, +z, -z with unit outward normals
+// (+-cx, 0, nzx), (0, +-cy, nzy), (0, 0, +-1) and offsets hx, hx, hy, hy, dz,
+// dz, from q = {cx, nzx, hx, cy, nzy, hy, dz}.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R trd_plane(const R* q, int i, Vec3<R> p) {
+  switch (i) {
+    case 0: return (q[0] * p.x + q[1] * p.z) - q[2];
+    case 1: return (-q[0] * p.x + q[1] * p.z) - q[2];
+    case 2: return (q[3] * p.y + q[4] * p.z) - q[5];
+    case 3: return (-q[3] * p.y + q[4] * p.z) - q[5];
+    case 4: return p.z - q[6];
+    default: return -p.z - q[6];
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R trd_dot(const R* q, int i, Vec3<R> v) {
+  switch (i) {
+    case 0: return q[0] * v.x + q[1] * v.z;
+    case 1: return -q[0] * v.x + q[1] * v.z;
+    case 2: return q[3] * v.y + q[4] * v.z;
+    case 3: return -q[3] * v.y + q[4] * v.z;
+    case 4: return v.z;
+    default: return -v.z;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R trd_d(const R* q, Vec3<R> p) {
+  R d = trd_plane(q, 0, p);
+#pragma unroll
+  for (int i = 1; i < 6; i++) d = tmax(d, trd_plane(q, i, p));
+  return d;
+}
+
+__device__ __forceinline__ int trd_inside(const double* q, V3 p, bool has_v, V3 v) {
+  const double d = trd_d(q, p);
+  if (d < -kHalfTol) return kIn;
+  if (d > kHalfTol) return kOut;
+  if (!has_v) return kIn;
+#pragma unroll
+  for (int i = 0; i < 6; i++)
+    if (fabs(trd_plane(q, i, p)) <= kHalfTol && trd_dot(q, i, v) >= 0) return kOut;
+  return kIn;
+}
+
+// Entry: the latest plane entry before the earliest plane exit; no entry
+// through a face whose band holds p (or beyond it) that the ray does not
+// cross inward; a start on the band moving in gives 0.
+template <typename R>
+__device__ __forceinline__ R trd_dist_in(const R* q, Vec3<R> p, Vec3<R> v) {
+  const R ht = half_tol<R>(), inf = R(kInf), zero = R(0);
+  R dp[6], dv[6];
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    dp[i] = trd_plane(q, i, p);
+    dv[i] = trd_dot(q, i, v);
+    if (dp[i] >= -ht && dv[i] >= zero) return inf;
+  }
+  R te = -inf, tx = inf;
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    if (dv[i] == zero) continue;
+    const R t = -dp[i] / dv[i];
+    if (dv[i] < zero) te = tmax(te, t);
+    else tx = tmin(tx, t);
+  }
+  if (te >= tx - ht) return inf;
+  return te < ht ? zero : te;
+}
+
+template <typename R>
+__device__ __forceinline__ R trd_dist_out(const R* q, Vec3<R> p, Vec3<R> v) {
+  const R ht = half_tol<R>(), zero = R(0);
+  R t = R(kInf);
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    const R dv = trd_dot(q, i, v);
+    if (!(dv > zero)) continue;
+    const R sd = -trd_plane(q, i, p);
+    if (sd <= ht) return zero;
+    t = tmin(t, sd / dv);
   }
   return t;
 }
@@ -514,6 +605,28 @@ __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<
 
 __device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3& n) {
 #ifndef GNAV_AXIS_BOXES
+  if ((info & 15) == kTrd) {
+    double c[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) c[i] = trd_plane(q, i, p);
+    int m = 0;
+#pragma unroll
+    for (int i = 1; i < 6; i++)
+      if (c[i] > c[m]) m = i;
+    int faces = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+      if (c[i] >= c[m] - kTol) faces++;
+    switch (m) {
+      case 0: n = V3{q[0], 0.0, q[1]}; break;
+      case 1: n = V3{-q[0], 0.0, q[1]}; break;
+      case 2: n = V3{0.0, q[3], q[4]}; break;
+      case 3: n = V3{0.0, -q[3], q[4]}; break;
+      case 4: n = V3{0.0, 0.0, 1.0}; break;
+      default: n = V3{0.0, 0.0, -1.0}; break;
+    }
+    return faces;
+  }
   if ((info & 15) == kOrb) {
     const double r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
     n = r > 0 ? V3{p.x / r, p.y / r, p.z / r} : V3{0.0, 0.0, 1.0};
@@ -575,6 +688,7 @@ __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, boo
   switch (info & 15) {
     case kBox: return box_inside(q, p, has_v, v);
     case kOrb: return orb_inside(q[0], p, has_v, v);
+    case kTrd: return trd_inside(q, p, has_v, v);
     default: return rad_inside(q, info, p, has_v, v);
   }
 #endif
@@ -588,6 +702,7 @@ __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
   switch (info & 15) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
+    case kTrd: return trd_d(q, p);
     default: return rad_dmax(rad_comps(q, info, p));
   }
 #endif
@@ -601,6 +716,7 @@ __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3
   switch (info & 15) {
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
+    case kTrd: return trd_dist_in(q, p, v);
     default: return rad_dist_in(q, info, p, v);
   }
 #endif
@@ -614,6 +730,7 @@ __device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec
   switch (info & 15) {
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
+    case kTrd: return trd_dist_out(q, p, v);
     default: return rad_dist_out(q, info, p, v);
   }
 #endif
@@ -637,14 +754,13 @@ __device__ __forceinline__ int vox_axis_index(double p, double lo, double inv_w,
 // placement level of every touchable frame.
 template <bool ON>
 struct NavCount {
-  unsigned din[4] = {0, 0, 0, 0}, dout[4] = {0, 0, 0, 0}, dsaf[4] = {0, 0, 0, 0}, dins[4] = {0, 0, 0, 0};
+  static constexpr int F = GNAV_NFAMILIES;
+  unsigned din[F] = {}, dout[F] = {}, dsaf[F] = {}, dins[F] = {};
   unsigned frames = 0, nodes = 0, dist_in32 = 0;
-  __device__ __forceinline__ static void bump(unsigned (&a)[4], int info) {
-    const int t = info & 3;
-    a[0] += t == 0;
-    a[1] += t == 1;
-    a[2] += t == 2;
-    a[3] += t == 3;
+  __device__ __forceinline__ static void bump(unsigned (&a)[F], int info) {
+    const int t = info & 15;
+#pragma unroll
+    for (int f = 0; f < F; f++) a[f] += t == f;
   }
   // daughter entry distance (FP64 or FP32), with its candidate frame unless
   // that was counted with the candidate's safety
@@ -679,7 +795,12 @@ struct NavCount {
   }
   __device__ __forceinline__ void levels(int n) { if (ON) frames += (unsigned)n; }
   __device__ __forceinline__ void node() { if (ON) nodes++; }
-  __device__ __forceinline__ unsigned total(const unsigned (&a)[4]) const { return a[0] + a[1] + a[2] + a[3]; }
+  __device__ __forceinline__ unsigned total(const unsigned (&a)[F]) const {
+    unsigned s = 0;
+#pragma unroll
+    for (int f = 0; f < F; f++) s += a[f];
+    return s;
+  }
 };
 
 template <bool C>

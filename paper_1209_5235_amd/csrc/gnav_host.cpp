@@ -204,6 +204,32 @@ bool solid_prep(int type, const double* par, double* q /*16*/, int* info, Box3* 
     }
     return true;
   }
+  if (type == kTrd) {
+    // half widths dx1, dx2 (x at z = -dz, +dz), dy1, dy2, half length dz; the
+    // x faces are the planes |x| = a + b z with a = (dx1 + dx2) / 2 and
+    // b = (dx2 - dx1) / (2 dz), unit normal (+-1, 0, -b) / sqrt(1 + b^2)
+    if (!(par[0] > 0 && par[1] > 0 && par[2] > 0 && par[3] > 0 && par[4] > 0)) {
+      why = "trapezoid half lengths must be positive";
+      return false;
+    }
+    const double dz = par[4];
+    for (int ax = 0; ax < 2; ax++) {
+      const double d1 = par[2 * ax], d2 = par[2 * ax + 1];
+      const double a = 0.5 * (d1 + d2);
+      const double b = (d2 - d1) / (2.0 * dz);
+      const double c = 1.0 / std::sqrt(1.0 + b * b);
+      q[3 * ax] = c;
+      q[3 * ax + 1] = -b * c;
+      q[3 * ax + 2] = a * c;
+      ext->lo[ax] = -std::max(d1, d2);
+      ext->hi[ax] = std::max(d1, d2);
+    }
+    q[6] = dz;
+    ext->lo[2] = -dz;
+    ext->hi[2] = dz;
+    *info = kTrd;
+    return true;
+  }
   double rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi;
   if (type == kTubs) {
     rmin1 = rmin2 = par[0];
@@ -385,6 +411,18 @@ bool shape_meets_box(const DauShape& d, const Box3& b, double pad) {
         s2 += e * e;
       }
       return s2 <= q[0] * q[0];
+    }
+    case kTrd: {
+      // separating face plane: every corner of the (padded, daughter-frame)
+      // box outside one face plane n . p = h
+      const double nrm[6][4] = {{q[0], 0.0, q[1], q[2]}, {-q[0], 0.0, q[1], q[2]}, {0.0, q[3], q[4], q[5]},
+                                {0.0, -q[3], q[4], q[5]}, {0.0, 0.0, 1.0, q[6]}, {0.0, 0.0, -1.0, q[6]}};
+      for (int f = 0; f < 6; f++) {
+        double mn = 0.0;
+        for (int a = 0; a < 3; a++) mn += nrm[f][a] * (nrm[f][a] > 0 ? lo[a] : hi[a]);
+        if (mn > nrm[f][3]) return false;
+      }
+      return true;
     }
     default: {
       double dz = q[R_DZ];

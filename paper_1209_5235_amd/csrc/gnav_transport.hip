@@ -788,19 +788,33 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   for (int i = tid; i < kDep; i += kPool)
     if (P.dkey[i] >= 0 && P.dval[i] != 0.0) atomic_add_f64(a.edep_t + P.dkey[i], P.dval[i]);
   if (COUNT) {
-    constexpr int kNV = 22;
-    const unsigned vals[kNV] = {nc.total(nc.din) - nc.dist_in32, nc.total(nc.dout), nc.total(nc.dins), nc.nodes, nc.dist_in32,
-                                nc.din[0], nc.din[1], nc.din[2], nc.din[3],
-                                nc.dout[0], nc.dout[1], nc.dout[2], nc.dout[3],
-                                nc.dsaf[0], nc.dsaf[1], nc.dsaf[2], nc.dsaf[3],
-                                nc.dins[0], nc.dins[1], nc.dins[2], nc.dins[3], nc.frames};
-    const int slots[kNV] = {GNAV_C_DIST_IN, GNAV_C_DIST_OUT, GNAV_C_INSIDE, GNAV_C_VOXEL_NODES,
-                            GNAV_C_DIST_IN_F32,
-                            GNAV_C_DIST_IN_BY, GNAV_C_DIST_IN_BY + 1, GNAV_C_DIST_IN_BY + 2, GNAV_C_DIST_IN_BY + 3,
-                            GNAV_C_DIST_OUT_BY, GNAV_C_DIST_OUT_BY + 1, GNAV_C_DIST_OUT_BY + 2, GNAV_C_DIST_OUT_BY + 3,
-                            GNAV_C_SAFETY_BY, GNAV_C_SAFETY_BY + 1, GNAV_C_SAFETY_BY + 2, GNAV_C_SAFETY_BY + 3,
-                            GNAV_C_INSIDE_BY, GNAV_C_INSIDE_BY + 1, GNAV_C_INSIDE_BY + 2, GNAV_C_INSIDE_BY + 3,
-                            GNAV_C_FRAME_MAPS};
+    constexpr int F = GNAV_NFAMILIES;
+    constexpr int kNV = 6 + 4 * F;
+    unsigned vals[kNV];
+    int slots[kNV];
+    vals[0] = nc.total(nc.din) - nc.dist_in32;
+    slots[0] = GNAV_C_DIST_IN;
+    vals[1] = nc.total(nc.dout);
+    slots[1] = GNAV_C_DIST_OUT;
+    vals[2] = nc.total(nc.dins);
+    slots[2] = GNAV_C_INSIDE;
+    vals[3] = nc.nodes;
+    slots[3] = GNAV_C_VOXEL_NODES;
+    vals[4] = nc.dist_in32;
+    slots[4] = GNAV_C_DIST_IN_F32;
+    vals[5] = nc.frames;
+    slots[5] = GNAV_C_FRAME_MAPS;
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      vals[6 + f] = nc.din[f];
+      slots[6 + f] = GNAV_C_DIST_IN_BY + f;
+      vals[6 + F + f] = nc.dout[f];
+      slots[6 + F + f] = GNAV_C_DIST_OUT_BY + f;
+      vals[6 + 2 * F + f] = nc.dsaf[f];
+      slots[6 + 2 * F + f] = GNAV_C_SAFETY_BY + f;
+      vals[6 + 3 * F + f] = nc.dins[f];
+      slots[6 + 3 * F + f] = GNAV_C_INSIDE_BY + f;
+    }
 #pragma unroll
     for (int c = 0; c < kNV; c++) {
       unsigned long long sum = vals[c];

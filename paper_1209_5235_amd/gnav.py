@@ -24,11 +24,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGEOM", -5: "EST
           -6: "EUNSUPPORTED"}
 COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", "pushes", "stuck",
             "truncated", "tracks", "shortcuts", "dist_in", "dist_out", "inside", "voxel_nodes",
-            "invalid", "dist_in_f32", "scored",
-            "dist_in_box", "dist_in_tubs", "dist_in_cons", "dist_in_orb",
-            "dist_out_box", "dist_out_tubs", "dist_out_cons", "dist_out_orb",
-            "safety_box", "safety_tubs", "safety_cons", "safety_orb",
-            "inside_box", "inside_tubs", "inside_cons", "inside_orb", "frame_maps"]
+            "invalid", "dist_in_f32", "scored"] + \
+    [f"{w}_{f}" for w in ("dist_in", "dist_out", "safety", "inside")
+     for f in ("box", "tubs", "cons", "orb", "trd", "family5")] + ["frame_maps"]
 # distance arithmetic of ComputeStep (GNAV_PREC_*)
 PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
 LIM_MOTHER, LIM_PE, LIM_COMPTON, LIM_PAIR, LIM_MAX_STEP = -1, -2, -3, -4, -5

@@ -33,6 +33,8 @@ GEOMS = {
     "calorimeter": lambda: W.geometry.calorimeter(),
     "barrel": lambda: W.geometry.barrel(),
     "barrel_v103": lambda: W.geometry.barrel_variant(103),
+    "zoo_more": lambda: W.geometry.solids_zoo_more(),
+    "endcap": lambda: W.geometry.endcap(),
 }
 
 def geom(ctx, name, oracle_lib):

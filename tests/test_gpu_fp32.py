@@ -59,7 +59,7 @@ def test_screened_step_equals_fp64(ctx, torch_dev, oracle_lib, name):
 
 
 @pytest.mark.parametrize("name,n,cap", [("tiny", 10000, 64), ("calorimeter", 4000, 400),
-                                        ("barrel", 3000, 512)])
+                                        ("barrel", 3000, 512), ("endcap", 4000, 256)])
 def test_screened_transport_matches_oracle(ctx, torch_dev, oracle_lib, name, n, cap):
     torch = torch_dev
     desc, gid, nt, og = geom(ctx, name, oracle_lib)

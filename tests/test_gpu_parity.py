@@ -114,7 +114,7 @@ def test_safety_is_lower_bound(ctx, torch_dev, oracle_lib, name, precision):
 
 
 @pytest.mark.parametrize("name,n,cap", [("tiny", 10000, 64), ("calorimeter", 4000, 400),
-                                        ("barrel", 3000, 512)])
+                                        ("barrel", 3000, 512), ("endcap", 4000, 256)])
 def test_transport_parity_per_track(ctx, torch_dev, oracle_lib, name, n, cap):
     torch = torch_dev
     desc, gid, nt, og = geom(ctx, name, oracle_lib)

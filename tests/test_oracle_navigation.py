@@ -11,6 +11,8 @@ GEOMS = {
     "zoo": lambda: W.geometry.solids_zoo(),
     "calorimeter": lambda: W.geometry.calorimeter(n_layers=8, n_cells=6),
     "barrel": lambda: W.geometry.barrel(n_layers=8, n_seg=16, n_rings=4, n_orbs=8),
+    "zoo_more": lambda: W.geometry.solids_zoo_more(),
+    "endcap": lambda: W.geometry.endcap(n_wedges=12),
 }
 
 
@@ -163,7 +165,7 @@ def test_voxel_mode_equals_bruteforce(oracle_lib, name):
     assert np.array_equal(la, lb) and np.array_equal(na, nb)
 
 
-@pytest.mark.parametrize("name,n", [("tiny", 3000), ("calorimeter", 1500), ("barrel", 400)])
+@pytest.mark.parametrize("name,n", [("tiny", 3000), ("calorimeter", 1500), ("barrel", 400), ("endcap", 1500)])
 def test_voxel_mode_transport_identical(oracle_lib, name, n):
     """Whole transports in voxel mode reproduce the brute-force per-step logs."""
     geoms, prim, _ = W.WORKLOADS[name](n=n)

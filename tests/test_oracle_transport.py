@@ -69,7 +69,7 @@ def test_alg1_paper_mode_aluminium(oracle_lib):
     assert abs(T - (np.linalg.norm(c) - 100 + Y / mu)) < 1e-11 * T
 
 
-@pytest.mark.parametrize("name,n", [("tiny", 4000), ("calorimeter", 3000), ("barrel", 1500)])
+@pytest.mark.parametrize("name,n", [("tiny", 4000), ("calorimeter", 3000), ("barrel", 1500), ("endcap", 3000)])
 def test_energy_conservation_per_event(oracle_lib, name, n):
     geoms, prim, _ = W.WORKLOADS[name](n=n)
     g = oracle_lib.Geometry(geoms[0])

@@ -37,4 +37,10 @@ def batched(n_events=4096, seed=0, plan_seed=2):
     return geoms, prim, event_geom
 
 
-WORKLOADS = {"tiny": tiny, "calorimeter": calorimeter, "barrel": barrel, "batched": batched}
+def endcap(n=20_000, seed=0):
+    """Trapezoid endcaps around a tube: photons from the origin, isotropic,
+    log-uniform 0.05-20 MeV."""
+    return [geometry.endcap()], primaries.origin_iso(n, seed), None
+
+
+WORKLOADS = {"tiny": tiny, "calorimeter": calorimeter, "barrel": barrel, "batched": batched, "endcap": endcap}

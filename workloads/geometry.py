@@ -423,6 +423,53 @@ def solids_zoo_more(seed=6):
     return b.build(world)
 
 
+def endcap(n_wedges=36, n_crystals=4, r_in=400.0, r_out=800.0, half_t=60.0, z_c=900.0):
+    """Two endcap discs of trapezoid wedges (the tapered modules of a CMS-like
+    endcap, Sec. 3.5's CMS case) around a central tube, in a vacuum world.
+
+    Each disc at z = +-z_c holds ``n_wedges`` trapezoid wedges around the z
+    axis, their local z pointing radially outward (x half width growing from
+    the inner to the outer radius, y half width = disc half thickness); each
+    wedge holds ``n_crystals`` trapezoid crystals stacked radially.  Materials
+    alternate lead / silicon wedge by wedge, crystals lead.  A silicon tube
+    layer (r 300-320, half length 700) sits between the discs.
+    """
+    b = Builder("endcap")
+    s_world = b.solid(BOX, 1200.0, 1200.0, 1200.0)
+    world = b.lv(s_world, "vacuum", "world")
+    s_tube = b.solid(TUBS, 300.0, 320.0, 700.0, 0.0, 2 * math.pi)
+    b.place(world, b.lv(s_tube, "silicon", "tube"))
+    half_phi = math.pi / n_wedges
+    dz = 0.5 * (r_out - r_in)
+    # wedge half widths at the inner and outer radius, kept inside the phi slice
+    dx1 = 0.98 * r_in * math.tan(half_phi)
+    dx2 = 0.98 * r_out * math.tan(half_phi)
+    wedges = []
+    for m, mat in enumerate(("lead", "silicon")):
+        s_w = b.solid(TRD, dx1, dx2, half_t, half_t, dz)
+        lv_w = b.lv(s_w, mat, f"wedge_{mat}")
+        # crystals: radial slices of the wedge, shrunk by 0.5 mm on every side
+        pitch = 2 * dz / n_crystals
+        for k in range(n_crystals):
+            z0 = -dz + k * pitch + 0.5
+            z1 = -dz + (k + 1) * pitch - 0.5
+            w0 = dx1 + (dx2 - dx1) * (z0 + dz) / (2 * dz) - 0.5
+            w1 = dx1 + (dx2 - dx1) * (z1 + dz) / (2 * dz) - 0.5
+            s_c = b.solid(TRD, w0, w1, half_t - 0.5, half_t - 0.5, 0.5 * (z1 - z0))
+            lv_c = b.lv(s_c, "lead", f"crystal_{mat}_{k}")
+            b.place(lv_w, lv_c, None, (0.0, 0.0, 0.5 * (z0 + z1)))
+        wedges.append(lv_w)
+    rc = 0.5 * (r_in + r_out)
+    for side in (1.0, -1.0):
+        for j in range(n_wedges):
+            ph = (j + 0.5) * 2 * half_phi
+            c, s_ = math.cos(ph), math.sin(ph)
+            # local x tangential, local y along the global z axis, local z radial
+            R = np.array([[-s_, 0.0, c], [c, 0.0, s_], [0.0, 1.0, 0.0]])
+            b.place(world, wedges[j % 2], R, (rc * c, rc * s_, side * z_c))
+    return b.build(world)
+
+
 def spheres(n_per_axis=20, radius=100.0, half=2500.0):
     """The paper's Spheres geometry: aluminium balls on a regular grid in a vacuum cube.
 

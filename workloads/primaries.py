@@ -87,6 +87,14 @@ def barrel_source(n=10_000_000, seed=0, half_z=2000.0, e_lo=0.05, e_hi=20.0):
     return one_per_event(pos, d, e)
 
 
+def origin_iso(n=20_000, seed=0, e_lo=0.05, e_hi=20.0):
+    """Point source at the origin, isotropic, log-uniform energy."""
+    rng = _rng(seed)
+    d = isotropic(rng, n)
+    e = log_uniform(rng, n, e_lo, e_hi)
+    return one_per_event(np.zeros((n, 3)), d, e)
+
+
 def pencil(n, pos, direction, energy):
     pos = np.broadcast_to(np.asarray(pos, dtype=np.float64), (n, 3)).copy()
     d = np.broadcast_to(np.asarray(direction, dtype=np.float64), (n, 3)).copy()
