@@ -40,6 +40,7 @@
 #define OG_CONS 2
 #define OG_ORB 3
 #define OG_TRD 4
+#define OG_SPHERE 5
 
 #define OG_IN 1
 #define OG_SURF 0
@@ -189,7 +190,19 @@ typedef struct {
   double ns[2], ne[2]; /* outward normals of the start and end phi planes */
   /* trapezoid: the six face planes n . p = h (n unit, outward): +x, -x, +y, -y, +z, -z */
   double pn[6][3], ph[6];
+  /* sphere section: radii, and the two theta bounds as cone surfaces rho = B z
+   * (B = tan theta, perpendicular factor c = |cos theta|) or the plane z = 0 */
+  double srmin, srmax;
+  int tkind[2];
+  double tB[2], tc[2];
 } og_solid;
+
+/* Kinds of a sphere section's theta bound: none; a cone whose solid inside
+ * (rho <= B z on the sheet B z >= 0) is the allowed region (outer); a cone
+ * whose outside is (inner); the half-space z <= 0 or z >= 0 (theta = pi/2). */
+enum { T_NONE = 0, T_OUTER, T_INNER, T_ZLE, T_ZGE };
+/* sphere component slots */
+enum { S_RO = 0, S_RI, S_PA, S_PB, S_T1, S_T2, S_N };
 
 /* component slots */
 enum { K_RO = 0, K_RI, K_Z, K_PA, K_PB, K_N };
@@ -227,6 +240,44 @@ static int solid_init(og_solid* s, int type, const double* par) {
     s->pn[5][2] = -1.0;
     s->ph[4] = s->ph[5] = dz;
     s->dz = dz;
+    return 0;
+  }
+  if (type == OG_SPHERE) {
+    /* rmin, rmax, sphi, dphi, stheta, dtheta */
+    double rmin = par[0], rmax = par[1], sphi = par[2], dphi = par[3], st = par[4], dt = par[5];
+    const double twopi = 2.0 * M_PI;
+    if (!(rmin >= 0) || !(rmax > rmin) || (rmin > 0 && rmin < kTol)) return -1;
+    if (!(dphi > 0) || dphi > twopi || (dphi < twopi && dphi > M_PI)) return -1;
+    if (!(st >= 0) || !(dt > 0) || st + dt > M_PI * (1.0 + 1e-15)) return -1;
+    s->srmin = rmin;
+    s->srmax = rmax;
+    s->has_inner = rmin > 0;
+    s->has_phi = dphi < twopi;
+    if (s->has_phi) {
+      double ephi = sphi + dphi;
+      s->ns[0] = sin(sphi);
+      s->ns[1] = -cos(sphi);
+      s->ne[0] = -sin(ephi);
+      s->ne[1] = cos(ephi);
+    }
+    const double th[2] = {st, st + dt};
+    for (int j = 0; j < 2; j++) {
+      /* lower bound theta >= th[0]: a bound only above 0; upper bound
+       * theta <= th[1]: only below pi */
+      int present = j == 0 ? th[0] > 0 : th[1] < M_PI;
+      s->tkind[j] = T_NONE;
+      if (!present) continue;
+      if (th[j] == 0.5 * M_PI) {
+        s->tkind[j] = j == 0 ? T_ZLE : T_ZGE;
+        continue;
+      }
+      s->tB[j] = tan(th[j]);
+      s->tc[j] = 1.0 / sqrt(1.0 + s->tB[j] * s->tB[j]);
+      int lower_half = th[j] > 0.5 * M_PI;
+      /* theta >= th below the equator and theta <= th above it keep the
+       * outside of the cone; the other two its inside */
+      s->tkind[j] = (j == 0) != lower_half ? T_INNER : T_OUTER;
+    }
     return 0;
   }
   double rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi;
@@ -323,6 +374,55 @@ static double trd_dot(const og_solid* s, int i, const double* v) {
   return s->pn[i][0] * v[0] + s->pn[i][1] * v[1] + s->pn[i][2] * v[2];
 }
 
+/* Component values of a sphere section at p (-inf for absent faces). */
+static void sph_comps(const og_solid* s, const double* p, double k[S_N]) {
+  double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
+  k[S_RO] = r - s->srmax;
+  k[S_RI] = s->has_inner ? s->srmin - r : -kInf;
+  if (s->has_phi) {
+    k[S_PA] = p[0] * s->ns[0] + p[1] * s->ns[1];
+    k[S_PB] = p[0] * s->ne[0] + p[1] * s->ne[1];
+  } else {
+    k[S_PA] = -kInf;
+    k[S_PB] = -kInf;
+  }
+  for (int j = 0; j < 2; j++) {
+    double* kj = &k[S_T1 + j];
+    switch (s->tkind[j]) {
+      case T_OUTER: *kj = (rho - (0.0 + s->tB[j] * p[2])) * s->tc[j]; break;
+      case T_INNER: *kj = ((0.0 + s->tB[j] * p[2]) - rho) * s->tc[j]; break;
+      case T_ZLE: *kj = p[2]; break;
+      case T_ZGE: *kj = -p[2]; break;
+      default: *kj = -kInf; break;
+    }
+  }
+}
+
+/* Gradient (unnormalised where noted in sph_normal) dot v of sphere component i. */
+static double sph_comp_dot(const og_solid* s, int i, const double* p, const double* v) {
+  double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
+  double pv = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+  double rv = rho > 0 ? (p[0] * v[0] + p[1] * v[1]) / rho : 0.0;
+  switch (i) {
+    case S_RO: return r > 0 ? pv / r : 0.0;
+    case S_RI: return r > 0 ? -pv / r : 0.0;
+    case S_PA: return v[0] * s->ns[0] + v[1] * s->ns[1];
+    case S_PB: return v[0] * s->ne[0] + v[1] * s->ne[1];
+    default: {
+      int j = i - S_T1;
+      switch (s->tkind[j]) {
+        case T_OUTER: return rv - s->tB[j] * v[2];
+        case T_INNER: return -rv + s->tB[j] * v[2];
+        case T_ZLE: return v[2];
+        case T_ZGE: return -v[2];
+        default: return 0.0;
+      }
+    }
+  }
+}
+
 /* The solid's signed value d(p). */
 double og_solid_d(const og_solid* s, const double* p) {
   if (s->type == OG_BOX) {
@@ -337,6 +437,13 @@ double og_solid_d(const og_solid* s, const double* p) {
   if (s->type == OG_TRD) {
     double d = -kInf;
     for (int i = 0; i < 6; i++) d = max2(d, trd_plane(s, i, p));
+    return d;
+  }
+  if (s->type == OG_SPHERE) {
+    double k[S_N];
+    sph_comps(s, p, k);
+    double d = k[0];
+    for (int i = 1; i < S_N; i++) d = max2(d, k[i]);
     return d;
   }
   double k[K_N];
@@ -407,6 +514,19 @@ int og_solid_inside(const og_solid* s, const double* p, const double* v) {
     }
     return OG_IN;
   }
+  if (s->type == OG_SPHERE) {
+    double k[S_N];
+    sph_comps(s, p, k);
+    for (int i = 0; i < S_N; i++) {
+      if (!(k[i] > -kInf)) continue;
+      NOTE_LEN(fabs(k[i]), kHalf);
+      if (fabs(k[i]) > kHalf) continue;
+      double dv = sph_comp_dot(s, i, p, v);
+      note(dv, 0.0, 1.0);
+      if (dv >= 0) return OG_OUT;
+    }
+    return OG_IN;
+  }
   double k[K_N];
   rad_comps(s, p, k);
   return rad_moving_in(s, p, v, k) ? OG_IN : OG_OUT;
@@ -449,6 +569,31 @@ int og_solid_normal(const og_solid* s, const double* p, double n[3]) {
     for (int i = 0; i < 6; i++) {
       val[i] = trd_plane(s, i, p);
       for (int c = 0; c < 3; c++) grad[i][c] = s->pn[i][c];
+    }
+  } else if (s->type == OG_SPHERE) {
+    nf = S_N;
+    sph_comps(s, p, val);
+    double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    double rho = sqrt(p[0] * p[0] + p[1] * p[1]);
+    double ex = rho > 0 ? p[0] / rho : 1.0, ey = rho > 0 ? p[1] / rho : 0.0;
+    for (int c = 0; c < 3; c++) {
+      grad[S_RO][c] = r > 0 ? p[c] / r : (c == 2 ? 1.0 : 0.0);
+      grad[S_RI][c] = -grad[S_RO][c];
+    }
+    grad[S_PA][0] = s->ns[0];
+    grad[S_PA][1] = s->ns[1];
+    grad[S_PB][0] = s->ne[0];
+    grad[S_PB][1] = s->ne[1];
+    for (int j = 0; j < 2; j++) {
+      double* g = grad[S_T1 + j];
+      double c = s->tc[j], B = s->tB[j];
+      switch (s->tkind[j]) {
+        case T_OUTER: g[0] = c * ex; g[1] = c * ey; g[2] = -c * B; break;
+        case T_INNER: g[0] = -c * ex; g[1] = -c * ey; g[2] = c * B; break;
+        case T_ZLE: g[2] = 1.0; break;
+        case T_ZGE: g[2] = -1.0; break;
+        default: break;
+      }
     }
   } else if (s->type == OG_ORB) {
     double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
@@ -784,6 +929,196 @@ static double trd_dist_in(const og_solid* s, const double* p, const double* v) {
   return te < kHalf ? 0.0 : te;
 }
 
+/* All sphere components except `skip` hold (within tolerance) at p + t v. */
+static int sph_ok_except(const og_solid* s, const double* p, const double* v, double t, int skip) {
+  double q[3] = {p[0] + t * v[0], p[1] + t * v[1], p[2] + t * v[2]};
+  double k[S_N];
+  sph_comps(s, q, k);
+  for (int i = 0; i < S_N; i++) {
+    if (i == skip) continue;
+    if (k[i] > -kInf) NOTE_LEN(k[i], kHalf);
+    if (k[i] > kHalf) return 0;
+  }
+  return 1;
+}
+
+/* Sphere section entry, surface by surface (as for tube and cone sections): a
+ * crossing through one face counts if every other component holds there.
+ * The regions r <= rmax, a phi wedge, the inside of a cone and a half-space
+ * are convex, so a ray that does not cross one of those faces inward from
+ * its band or beyond never enters; r >= rmin and the outside of a cone are
+ * not. */
+static double sph_dist_in(const og_solid* s, const double* p, const double* v) {
+  double k[S_N];
+  sph_comps(s, p, k);
+  double d = k[0];
+  for (int i = 1; i < S_N; i++) d = max2(d, k[i]);
+  NOTE_LEN(d, -kHalf);
+  if (d < -kHalf) return 0.0;
+  double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double b = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+  double best = kInf;
+  for (int i = 0; i < S_N; i++)
+    if (k[i] > -kInf) NOTE_LEN(k[i], -kHalf);
+  /* outer sphere: the ball's entry */
+  if (k[S_RO] >= -kHalf) {
+    NOTE_LEN(b, 0.0);
+    if (b >= 0) return kInf;
+    double c = rr - s->srmax * s->srmax;
+    double disc = b * b - c;
+    note(disc, 0.0, og_scale * og_scale);
+    if (disc <= 0) return kInf;
+    double sq = sqrt(disc);
+    double t = c / (sq - b);
+    if (t < 0) t = 0;
+    if (sph_ok_except(s, p, v, t, S_RO)) best = min2(best, t);
+  }
+  /* inner sphere: leaving the inner ball */
+  if (s->has_inner) {
+    double t = -1.0;
+    double c = rr - s->srmin * s->srmin;
+    double disc = b * b - c;
+    NOTE_LEN(fabs(k[S_RI]), kHalf);
+    if (fabs(k[S_RI]) <= kHalf) {
+      NOTE_LEN(b, 0.0);
+      if (b > 0) t = 0.0;
+      else if (b < 0 && disc > 0) t = sqrt(disc) - b;
+    } else if (disc > 0) {
+      double sq = sqrt(disc);
+      t = (b > 0) ? -c / (b + sq) : sq - b;
+    }
+    if (t >= 0 && t < kInf && sph_ok_except(s, p, v, t, S_RI)) best = min2(best, t);
+  }
+  /* phi planes (wedge no wider than pi: convex) */
+  if (s->has_phi) {
+    for (int q = 0; q < 2; q++) {
+      const double* n = q == 0 ? s->ns : s->ne;
+      double dp = q == 0 ? k[S_PA] : k[S_PB];
+      if (dp >= -kHalf) {
+        double dv = v[0] * n[0] + v[1] * n[1];
+        note(dv, 0.0, 1.0);
+        if (dv >= 0) return kInf;
+        double t = dp / (-dv);
+        if (t < 0) t = 0;
+        if (sph_ok_except(s, p, v, t, q == 0 ? S_PA : S_PB)) best = min2(best, t);
+      }
+    }
+  }
+  /* theta bounds */
+  for (int j = 0; j < 2; j++) {
+    const int i = S_T1 + j;
+    const int kind = s->tkind[j];
+    if (kind == T_NONE) continue;
+    if (kind == T_OUTER) {
+      if (k[i] >= -kHalf) {
+        double vn = sph_comp_dot(s, i, p, v);
+        note(vn, 0.0, 1.0);
+        if (vn >= 0) return kInf;
+        double t = radial_entry(0.0, s->tB[j], p, v);
+        if (t == kInf) return kInf;
+        if (t < 0) t = 0;
+        if (sph_ok_except(s, p, v, t, i)) best = min2(best, t);
+      }
+    } else if (kind == T_INNER) {
+      double t = -1.0;
+      NOTE_LEN(fabs(k[i]), kHalf);
+      if (fabs(k[i]) <= kHalf) {
+        double vn = sph_comp_dot(s, i, p, v);
+        note(vn, 0.0, 1.0);
+        if (vn < 0) t = 0.0;
+        else if (vn > 0) t = radial_root(0.0, s->tB[j], p, v, +1);
+      } else {
+        t = radial_root(0.0, s->tB[j], p, v, +1);
+      }
+      if (t >= 0 && t < kInf && sph_ok_except(s, p, v, t, i)) best = min2(best, t);
+    } else {
+      /* half-space z <= 0 (T_ZLE) or z >= 0 (T_ZGE), component k = +-z */
+      if (k[i] >= -kHalf) {
+        double vn = kind == T_ZLE ? v[2] : -v[2];
+        NOTE_LEN(vn, 0.0);
+        if (vn >= 0) return kInf;
+        double t = k[i] / (-vn);
+        if (t < 0) t = 0;
+        if (sph_ok_except(s, p, v, t, i)) best = min2(best, t);
+      }
+    }
+  }
+  if (best < kInf) NOTE_LEN(best, kHalf);
+  return best < kHalf ? 0.0 : best;
+}
+
+/* Sphere section exit: the first outward crossing over its components; 0 on
+ * a face band when not moving strictly inward. */
+static double sph_dist_out(const og_solid* s, const double* p, const double* v) {
+  double k[S_N];
+  sph_comps(s, p, k);
+  double rr = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double b = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+  double t = kInf;
+  /* outer sphere */
+  NOTE_LEN(k[S_RO], -kHalf);
+  if (k[S_RO] >= -kHalf) NOTE_LEN(b, 0.0);
+  if (k[S_RO] >= -kHalf && b >= 0) return 0.0;
+  {
+    double c = rr - s->srmax * s->srmax;
+    double disc = b * b - c;
+    if (disc < 0) disc = 0;
+    double sq = sqrt(disc);
+    double to = (b > 0) ? -c / (b + sq) : sq - b;
+    t = min2(t, to > 0 ? to : 0.0);
+  }
+  /* inner sphere: entering the inner ball */
+  if (s->has_inner) {
+    NOTE_LEN(k[S_RI], -kHalf);
+    if (k[S_RI] >= -kHalf) NOTE_LEN(b, 0.0);
+    if (k[S_RI] >= -kHalf && b <= 0) return 0.0;
+    if (b < 0) {
+      double c = rr - s->srmin * s->srmin;
+      double disc = b * b - c;
+      note(disc, 0.0, og_scale * og_scale);
+      if (disc > 0) {
+        double ti = c / (sqrt(disc) - b);
+        t = min2(t, ti > 0 ? ti : 0.0);
+      }
+    }
+  }
+  if (s->has_phi) {
+    for (int q = 0; q < 2; q++) {
+      const double* n = q == 0 ? s->ns : s->ne;
+      double dp = q == 0 ? k[S_PA] : k[S_PB];
+      double dv = v[0] * n[0] + v[1] * n[1];
+      NOTE_LEN(dp, -kHalf);
+      note(dv, 0.0, 1.0);
+      if (dp >= -kHalf && dv >= 0) return 0.0;
+      if (dv > 0) {
+        double tp = -dp / dv;
+        if (tp < 0) tp = 0;
+        t = min2(t, tp);
+      }
+    }
+  }
+  for (int j = 0; j < 2; j++) {
+    const int i = S_T1 + j;
+    const int kind = s->tkind[j];
+    if (kind == T_NONE) continue;
+    double vn = sph_comp_dot(s, i, p, v);
+    NOTE_LEN(k[i], -kHalf);
+    note(vn, 0.0, 1.0);
+    if (k[i] >= -kHalf && vn >= 0) return 0.0;
+    if (kind == T_OUTER) {
+      t = min2(t, radial_root(0.0, s->tB[j], p, v, +1));
+    } else if (kind == T_INNER) {
+      t = min2(t, radial_root(0.0, s->tB[j], p, v, -1));
+    } else if (vn > 0) {
+      double sd = -k[i];
+      NOTE_LEN(sd, kHalf);
+      if (sd <= kHalf) return 0.0;
+      t = min2(t, sd / vn);
+    }
+  }
+  return t;
+}
+
 /* Leaving distance: the earliest plane exit; 0 on a face band moving out. */
 static double trd_dist_out(const og_solid* s, const double* p, const double* v) {
   double t = kInf;
@@ -803,6 +1138,7 @@ double og_solid_dist_in(const og_solid* s, const double* p, const double* v) {
     case OG_BOX: return box_dist_in(s, p, v);
     case OG_ORB: return orb_dist_in(s, p, v);
     case OG_TRD: return trd_dist_in(s, p, v);
+    case OG_SPHERE: return sph_dist_in(s, p, v);
     default: return rad_dist_in(s, p, v);
   }
 }
@@ -812,6 +1148,7 @@ double og_solid_dist_out(const og_solid* s, const double* p, const double* v) {
     case OG_BOX: return box_dist_out(s, p, v);
     case OG_ORB: return orb_dist_out(s, p, v);
     case OG_TRD: return trd_dist_out(s, p, v);
+    case OG_SPHERE: return sph_dist_out(s, p, v);
     default: return rad_dist_out(s, p, v);
   }
 }
@@ -1117,6 +1454,13 @@ static void solid_box(const og_solid* s, double lo[3], double hi[3]) {
     hi[1] = hy;
     lo[2] = -p[4];
     hi[2] = p[4];
+    return;
+  }
+  if (s->type == OG_SPHERE) {
+    for (int i = 0; i < 3; i++) {
+      lo[i] = -p[1];
+      hi[i] = p[1];
+    }
     return;
   }
   if (s->type == OG_BOX || s->type == OG_ORB) {
@@ -1925,6 +2269,7 @@ int og_transport(const og_geom* g, int64_t n, const int32_t* event, const int32_
     double e = w->par[0];
     if (w->type == OG_BOX) e = max2(w->par[0], max2(w->par[1], w->par[2]));
     else if (w->type == OG_TRD) e = max2(max2(max2(w->par[0], w->par[1]), max2(w->par[2], w->par[3])), w->par[4]);
+    else if (w->type == OG_SPHERE) e = w->par[1];
     else if (w->type != OG_ORB) e = max2(w->Ao + fabs(w->Bo) * w->dz, w->dz);
     og_scale = max2(1.0, e);
   }

@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-BOX, TUBS, CONS, ORB, TRD = 0, 1, 2, 3, 4
+BOX, TUBS, CONS, ORB, TRD, SPHERE = 0, 1, 2, 3, 4, 5
 
 
 def _phi_member(p, sphi, dphi):
@@ -36,6 +36,23 @@ def member(stype, par, p):
     if stype == ORB:
         r = np.linalg.norm(p, axis=1)
         return r < par[0], np.abs(r - par[0])
+    if stype == SPHERE:
+        # spherical coordinates: r, polar angle from +z, azimuth
+        rmin, rmax, sphi, dphi, st, dt = par[:6]
+        r = np.linalg.norm(p, axis=1)
+        th = np.arccos(np.clip(p[:, 2] / np.maximum(r, 1e-300), -1.0, 1.0))
+        inr = (r < rmax) & ((r > rmin) | (rmin == 0))
+        lo_ok = (th > st) | (st == 0)
+        hi_ok = (th < st + dt) | (st + dt >= math.pi)
+        inphi, mphi = _phi_member(p, sphi, dphi)
+        m = np.abs(r - rmax)
+        if rmin > 0:
+            m = np.minimum(m, np.abs(r - rmin))
+        for tb, on in ((st, st > 0), (st + dt, st + dt < math.pi)):
+            if on:
+                m = np.minimum(m, r * np.abs(np.sin(np.minimum(np.abs(th - tb), math.pi / 2))))
+        m = np.minimum(m, mphi)
+        return inr & lo_ok & hi_ok & inphi, m
     if stype == TRD:
         # half widths interpolated end to end between z = -dz and z = +dz
         dx1, dx2, dy1, dy2, dz = par[:5]

@@ -1,7 +1,7 @@
-"""Pins of the oracle's trapezoid (the Sec. 3.5 CMS case's solids beyond
-boxes, tubes, cones and balls): closed-form distances and normals, ray
-marching and sampling against an independent membership test, placement
-invariance."""
+"""Pins of the oracle's trapezoid and sphere section (solids of the Sec. 3.5
+CMS case beyond boxes, tubes, cones and balls): closed-form distances and
+normals, ray marching and sampling against an independent membership test
+(angles by arccos and atan2), placement invariance."""
 import math
 
 import numpy as np
@@ -108,12 +108,12 @@ def _march(st, par, p, v, tmax, first_inside, dt=0.02):
 
 
 @pytest.mark.parametrize("k", range(len(MORE_SOLIDS)))
-def test_trd_ray_marching(oracle_lib, k):
+def test_ray_marching(oracle_lib, k):
     st, par = MORE_SOLIDS[k]
     rng = np.random.Generator(np.random.Philox(key=300 + k))
     checked_in = checked_out = 0
-    while checked_in < 60:
-        p = rng.uniform(-250, 250, 3)
+    while checked_in < 60 or checked_out < 30:
+        p = rng.uniform(-160, 160, 3)
         v = rng.normal(size=3)
         v /= np.linalg.norm(v)
         if member(st, par, p[None])[1][0] < 1e-6:
@@ -138,7 +138,7 @@ def test_trd_ray_marching(oracle_lib, k):
 
 
 @pytest.mark.parametrize("k", range(len(MORE_SOLIDS)))
-def test_trd_inside_and_safety_sampling(oracle_lib, k):
+def test_inside_and_safety_sampling(oracle_lib, k):
     st, par = MORE_SOLIDS[k]
     rng = np.random.Generator(np.random.Philox(key=400 + k))
     pts = rng.uniform(-250, 250, (4000, 3))
@@ -158,7 +158,7 @@ def test_trd_inside_and_safety_sampling(oracle_lib, k):
         assert not np.any(member(st, par, p + 0.999999 * s * sph)[0])
 
 
-def test_trd_distances_invariant_under_placement(oracle_lib):
+def test_distances_invariant_under_placement(oracle_lib):
     g = oracle_lib.Geometry(MORE)
     rng = np.random.Generator(np.random.Philox(key=17))
     n = 2000
@@ -181,3 +181,68 @@ def test_trd_distances_invariant_under_placement(oracle_lib):
         s_id = MORE.lv_solid[MORE.pv_lv[l]]
         loc = ev(oracle_lib, int(MORE.solid_type[s_id]), MORE.solid_par[s_id], "dist_in", pl, vl)[0]
         assert abs(loc - s[i]) <= 1e-9 * max(1.0, s[i])
+
+
+SPHERE = 5
+
+
+def test_sphere_closed_forms(oracle_lib):
+    o = oracle_lib
+    shell = [50.0, 100.0, 0.0, 2 * math.pi, 0.0, math.pi]
+    assert close(ev(o, SPHERE, shell, "dist_in", [-200, 0, 0], [1, 0, 0])[0], 100.0)
+    assert close(ev(o, SPHERE, shell, "dist_out", [75, 0, 0], [1, 0, 0])[0], 25.0)
+    assert close(ev(o, SPHERE, shell, "dist_out", [75, 0, 0], [-1, 0, 0])[0], 25.0)
+    # from the bore the ray enters through the inner sphere
+    assert close(ev(o, SPHERE, shell, "dist_in", [0, 0, 0], [0, 1, 0])[0], 50.0)
+    # chord through the shell missing the bore: impact parameter 60 > rmin
+    b = 60.0
+    assert close(ev(o, SPHERE, shell, "dist_out", [-math.sqrt(90.0 ** 2 - b * b), b, 0], [1, 0, 0])[0],
+                 math.sqrt(90.0 ** 2 - b * b) + math.sqrt(100.0 ** 2 - b * b))
+    # a 45 degree cone around +z (theta in [0, pi/4])
+    cone = [0.0, 100.0, 0.0, 2 * math.pi, 0.0, math.pi / 4]
+    assert close(ev(o, SPHERE, cone, "dist_out", [0, 0, 50], [1, 0, 0])[0], 50.0)
+    assert close(ev(o, SPHERE, cone, "dist_out", [0, 0, 50], [0, 0, 1])[0], 50.0)
+    assert close(ev(o, SPHERE, cone, "dist_in", [60, 0, 10], [-1, 0, 0])[0], 50.0)
+    assert ev(o, SPHERE, cone, "dist_in", [0, 0, -10], [1, 0, 0])[0] == INF
+    # the band 45 to 135 degrees around the equator
+    band = [0.0, 100.0, 0.0, 2 * math.pi, math.pi / 4, math.pi / 2]
+    assert close(ev(o, SPHERE, band, "dist_out", [50, 0, 0], [0, 0, 1])[0], 50.0)
+    assert close(ev(o, SPHERE, band, "dist_out", [50, 0, 0], [0, 0, -1])[0], 50.0)
+    assert close(ev(o, SPHERE, band, "dist_in", [0, 0, 40], [1, 0, 0])[0], 40.0)
+    # upper hemisphere: the equatorial plane
+    hemi = [0.0, 100.0, 0.0, 2 * math.pi, 0.0, math.pi / 2]
+    assert close(ev(o, SPHERE, hemi, "dist_in", [0, 0, -50], [0, 0, 1])[0], 50.0)
+    assert close(ev(o, SPHERE, hemi, "dist_out", [0, 30, 20], [0, 0, -1])[0], 20.0)
+    # a phi wedge [0, pi/2]: leaving through the phi = pi/2 plane
+    wedge = [0.0, 100.0, 0.0, math.pi / 2, 0.0, math.pi]
+    assert close(ev(o, SPHERE, wedge, "dist_out", [20, 10, 0], [-1, 0, 0])[0], 20.0)
+    assert close(ev(o, SPHERE, wedge, "dist_in", [-30, 10, 0], [1, 0, 0])[0], 30.0)
+    # signed value: perpendicular distance to the cone surface
+    assert close(ev(o, SPHERE, cone, "d", [0, 0, 50])[0], -50 * math.sin(math.pi / 4), 1e-12)
+    assert close(ev(o, SPHERE, band, "d", [0, 0, 80])[0], 80 * math.sin(math.pi / 4), 1e-12)
+
+
+def test_sphere_normals(oracle_lib):
+    o = oracle_lib
+    cone = [20.0, 100.0, 0.0, 2 * math.pi, 0.0, math.pi / 4]
+    pts = np.array([[0, 0, 100.0], [0, 0, 20.0], [30 * math.cos(0.3), 30 * math.sin(0.3), 30.0]])
+    n, faces = o.solid_normal(SPHERE, cone, pts)
+    # outer sphere radial, inner sphere inward, the cone's outward normal (cos, sin tilted by 45 deg)
+    s = math.sqrt(0.5)
+    ref = np.array([[0, 0, 1.0], [0, 0, -1.0], [s * math.cos(0.3), s * math.sin(0.3), -s]])
+    assert np.allclose(n, ref, atol=1e-15) and np.all(faces == 1)
+    band = [0.0, 100.0, 0.0, 2 * math.pi, 2.0, 1.0]  # theta in [2, 3]: below the equator
+    q = 50 * np.array([math.sin(2.0), 0.0, math.cos(2.0)])  # on the theta = 2 cone
+    n, faces = o.solid_normal(SPHERE, band, q[None])
+    # outward = towards smaller theta: -(d/dtheta) of the unit position
+    ref = -np.array([math.cos(2.0), 0.0, -math.sin(2.0)])
+    assert np.allclose(n[0], ref, atol=1e-14) and faces[0] == 1
+    hemi = [0.0, 100.0, 0.0, 2 * math.pi, 0.0, math.pi / 2]
+    n, faces = o.solid_normal(SPHERE, hemi, np.array([[10.0, 5.0, 0.0]]))
+    assert np.allclose(n[0], [0, 0, -1.0]) and faces[0] == 1
+
+
+def test_sphere_rejects_bad_parameters(oracle_lib):
+    for par in ([50, 40, 0, 1, 0, 1], [0, 10, 0, 4.0, 0, 1], [0, 10, 0, 1, 2.0, 1.5], [0, 10, 0, 1, 0, 0]):
+        with pytest.raises(ValueError):
+            oracle_lib.solid_eval(SPHERE, par, "d", np.zeros((1, 3)))

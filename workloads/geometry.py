@@ -19,7 +19,7 @@ import math
 import numpy as np
 
 # Solid type codes shared by the flat description.
-BOX, TUBS, CONS, ORB, TRD = 0, 1, 2, 3, 4
+BOX, TUBS, CONS, ORB, TRD, SPHERE = 0, 1, 2, 3, 4, 5
 NPAR = 8
 
 # Material composition table: name -> (density g/cm3, [(Z, A g/mol, mass fraction)]).
@@ -391,9 +391,11 @@ def solids_zoo(seed=5):
 
 
 def solids_zoo_more(seed=6):
-    """The solid families beyond the paper's boxes, tubes, cones and balls: one
-    rotated and translated daughter each (trapezoids of both tapers, and a
-    near-box) in a box world, for the per-solid tests of those families."""
+    """The solid families beyond the paper's boxes, tubes, cones and balls, one
+    rotated and translated daughter each, in a box world: trapezoids of both
+    tapers and a near-box; sphere sections (full shell, phi wedge, theta bands
+    above, across and below the equator, the upper hemisphere, a band with a
+    phi wedge), for the per-solid tests of those families."""
     rng = np.random.Generator(np.random.Philox(key=seed))
     b = Builder("zoo_more")
     s_world = b.solid(BOX, 1000.0, 1000.0, 1000.0)
@@ -403,9 +405,18 @@ def solids_zoo_more(seed=6):
         (TRD, (100.0, 30.0, 70.0, 70.0, 50.0)),
         (TRD, (80.0, 80.0, 80.0, 80.0, 80.0)),
         (TRD, (20.0, 140.0, 120.0, 10.0, 110.0)),
+        # sphere sections: rmin, rmax, sphi, dphi, stheta, dtheta
+        (SPHERE, (40.0, 120.0, 0.0, 2 * math.pi, 0.0, math.pi)),
+        (SPHERE, (0.0, 110.0, 0.4, 2.2, 0.0, math.pi)),
+        (SPHERE, (30.0, 130.0, 0.0, 2 * math.pi, 0.3, 0.9)),
+        (SPHERE, (50.0, 120.0, -0.7, 1.9, 0.8, 1.4)),
+        (SPHERE, (0.0, 100.0, 0.0, 2 * math.pi, 0.0, 0.5 * math.pi)),
+        (SPHERE, (20.0, 115.0, 1.0, 3.0, 1.9, 1.0)),
     ]
     centres = [(-500.0, -500.0, -500.0), (500.0, -500.0, 500.0), (-500.0, 500.0, 500.0),
-               (500.0, 500.0, -500.0)]
+               (500.0, 500.0, -500.0), (0.0, 0.0, 0.0), (-500.0, -500.0, 500.0),
+               (500.0, 500.0, 500.0), (-500.0, 500.0, -500.0), (500.0, -500.0, -500.0),
+               (0.0, 500.0, 0.0)]
     mats = ["water", "lead", "silicon"]
     for i, ((st, par), c) in enumerate(zip(shapes, centres)):
         s = b.solid(st, *par)
