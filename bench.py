@@ -33,12 +33,12 @@ sys.path.insert(0, ROOT)
 # advance of a step, and an interaction (attenuation lookup, sampling,
 # rotation).  The counts come from the kernel's work counters (a counting
 # launch of the same batch).
-FAMILIES = ("box", "tubs", "cons", "orb", "trd")
+FAMILIES = ("box", "tubs", "cons", "orb", "trd", "sphere")
 UNIT_FLOPS = {
     "frame": 33,
-    "dist_in": {"box": 30, "tubs": 110, "cons": 150, "orb": 20, "trd": 60},
-    "dist_out": {"box": 15, "tubs": 90, "cons": 120, "orb": 15, "trd": 40},
-    "safety": {"box": 8, "tubs": 20, "cons": 30, "orb": 7, "trd": 30},
+    "dist_in": {"box": 30, "tubs": 110, "cons": 150, "orb": 20, "trd": 60, "sphere": 200},
+    "dist_out": {"box": 15, "tubs": 90, "cons": 120, "orb": 15, "trd": 40, "sphere": 150},
+    "safety": {"box": 8, "tubs": 20, "cons": 30, "orb": 7, "trd": 30, "sphere": 30},
     "node": 8,
     "step": 10,
     "interaction": 150,

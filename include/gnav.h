@@ -57,13 +57,17 @@ typedef int32_t gnav_status;
  *   GNAV_TRD  dx1, dx2, dy1, dy2, dz                   (trapezoid: x half width dx1 at
  *                                                       z = -dz, dx2 at +dz, linear between;
  *                                                       likewise y; all positive)
+ *   GNAV_SPHERE rmin, rmax, sphi, dphi, stheta, dtheta (sphere section: shell, phi wedge,
+ *                                                       polar angles stheta .. stheta + dtheta
+ *                                                       from +z, within [0, pi])
  * Sections need 0 <= rmin < rmax at both ends and dphi in (0, pi] or 2 pi. */
 #define GNAV_BOX 0
 #define GNAV_TUBS 1
 #define GNAV_CONS 2
 #define GNAV_ORB 3
 #define GNAV_TRD 4
-#define GNAV_NFAMILIES 6 /* family slots of the work counters (slot 5 reserved) */
+#define GNAV_SPHERE 5
+#define GNAV_NFAMILIES 6 /* family slots of the work counters */
 
 /* Surface tolerance (mm): points within half of it of a surface lie on it. */
 #define GNAV_TOLERANCE 1e-9

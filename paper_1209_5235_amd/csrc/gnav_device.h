@@ -33,7 +33,7 @@ constexpr int kZeroPush = 10;
 constexpr int kZeroKill = 25;
 constexpr int kMaxComptonTrials = 1000;
 
-enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3, kTrd = 4 };
+enum : int { kBox = 0, kTubs = 1, kCons = 2, kOrb = 3, kTrd = 4, kSphere = 5 };
 enum : int { kOut = -1, kIn = 1 };
 enum : int { kLimMother = -1, kLimPE = -2, kLimCompton = -3, kLimPair = -4, kLimMaxStep = -5 };
 
@@ -594,6 +594,260 @@ __device__ __forceinline__ R rad_dist_out(const R* q, int info, Vec3<R> p, Vec3<
 }
 
 // ---------------------------------------------------------------------------
+// Sphere sections: shell rmin <= r <= rmax, phi wedge (optional, at most pi
+// wide), and up to two theta bounds, each the cone rho = B z (B = tan theta,
+// perpendicular factor c = |cos theta|) whose inside (outer kind) or outside
+// (inner kind) is kept, or for theta = pi/2 the half-space z <= 0 or z >= 0.
+// q = {rmax, rmin, ns0, ns1, ne0, ne1, B1, c1, B2, c2}; the bound kinds sit in
+// the solid info above the family bits.
+// ---------------------------------------------------------------------------
+
+enum : int { kTNone = 0, kTOuter = 1, kTInner = 2, kTZle = 3, kTZge = 4 };
+constexpr int kInfoTheta = 6;  // bit offset of the first theta bound's kind (3 bits each)
+
+__device__ __forceinline__ int sph_kind(int info, int j) { return (info >> (kInfoTheta + 3 * j)) & 7; }
+
+template <typename R>
+struct SphComps {
+  R k[6];  // outer sphere, inner sphere, start phi, end phi, theta bound 1, theta bound 2
+};
+
+template <typename R>
+__device__ __forceinline__ SphComps<R> sph_comps(const R* q, int info, Vec3<R> p) {
+  const R inf = R(kInf);
+  SphComps<R> c;
+  const R r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  const R rho = sqrt(p.x * p.x + p.y * p.y);
+  c.k[0] = r - q[0];
+  c.k[1] = (info & kInfoInner) ? q[1] - r : -inf;
+  if (info & kInfoPhi) {
+    c.k[2] = p.x * q[2] + p.y * q[3];
+    c.k[3] = p.x * q[4] + p.y * q[5];
+  } else {
+    c.k[2] = -inf;
+    c.k[3] = -inf;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    const R B = q[6 + 2 * j], cc = q[7 + 2 * j];
+    switch (sph_kind(info, j)) {
+      case kTOuter: c.k[4 + j] = (rho - (R(0) + B * p.z)) * cc; break;
+      case kTInner: c.k[4 + j] = ((R(0) + B * p.z) - rho) * cc; break;
+      case kTZle: c.k[4 + j] = p.z; break;
+      case kTZge: c.k[4 + j] = -p.z; break;
+      default: c.k[4 + j] = -inf; break;
+    }
+  }
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ R sph_dmax(const SphComps<R>& c) {
+  R d = c.k[0];
+#pragma unroll
+  for (int i = 1; i < 6; i++) d = tmax(d, c.k[i]);
+  return d;
+}
+
+// v . gradient of component i (unit gradients except that the cone's is
+// scaled by 1 / c, which keeps its sign).
+template <typename R>
+__device__ __forceinline__ R sph_comp_dot(const R* q, int info, int i, Vec3<R> p, Vec3<R> v) {
+  const R zero = R(0);
+  const R r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+  const R rho = sqrt(p.x * p.x + p.y * p.y);
+  const R pv = p.x * v.x + p.y * v.y + p.z * v.z;
+  const R rv = rho > zero ? (p.x * v.x + p.y * v.y) / rho : zero;
+  switch (i) {
+    case 0: return r > zero ? pv / r : zero;
+    case 1: return r > zero ? -pv / r : zero;
+    case 2: return v.x * q[2] + v.y * q[3];
+    case 3: return v.x * q[4] + v.y * q[5];
+    default: {
+      const int j = i - 4;
+      switch (sph_kind(info, j)) {
+        case kTOuter: return rv - q[6 + 2 * j] * v.z;
+        case kTInner: return -rv + q[6 + 2 * j] * v.z;
+        case kTZle: return v.z;
+        case kTZge: return -v.z;
+        default: return zero;
+      }
+    }
+  }
+}
+
+// The sphere section's inside test and distances are kept out of line: their
+// six components would otherwise raise the register count of every kernel
+// that dispatches over the solid families (the transport loop spills without
+// this), while only steps in or at sphere sections pay for the call.
+__device__ __attribute__((noinline)) int sph_inside(const double* q, int info, V3 p, bool has_v, V3 v) {
+  const SphComps<double> c = sph_comps(q, info, p);
+  const double d = sph_dmax(c);
+  if (d < -kHalfTol) return kIn;
+  if (d > kHalfTol) return kOut;
+  if (!has_v) return kIn;
+  bool out = false;
+#pragma unroll
+  for (int i = 0; i < 6; i++)
+    if (c.k[i] > -kInf && fabs(c.k[i]) <= kHalfTol && sph_comp_dot(q, info, i, p, v) >= 0) out = true;
+  return out ? kOut : kIn;
+}
+
+template <typename R>
+__device__ __forceinline__ bool sph_ok_except(const R* q, int info, Vec3<R> p, Vec3<R> v, R t, int skip) {
+  const R ht = half_tol<R>();
+  const SphComps<R> c = sph_comps(q, info, Vec3<R>{p.x + t * v.x, p.y + t * v.y, p.z + t * v.z});
+#pragma unroll
+  for (int i = 0; i < 6; i++)
+    if (i != skip && c.k[i] > ht) return false;
+  return true;
+}
+
+// Entry, surface by surface as for tube and cone sections; the regions
+// r <= rmax, the phi wedge, a cone's inside and a half-space are convex (no
+// entry when the ray does not cross their face inward from its band or
+// beyond), r >= rmin and a cone's outside are not.
+template <typename R>
+__device__ __attribute__((noinline)) R sph_dist_in(const R* q, int info, Vec3<R> p, Vec3<R> v) {
+  const R ht = half_tol<R>(), inf = R(kInf), zero = R(0);
+  const SphComps<R> c = sph_comps(q, info, p);
+  if (sph_dmax(c) < -ht) return zero;
+  const R rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  const R b = p.x * v.x + p.y * v.y + p.z * v.z;
+  R best = inf;
+  if (c.k[0] >= -ht) {
+    if (b >= zero) return inf;
+    const R cc = rr - q[0] * q[0];
+    const R disc = b * b - cc;
+    if (disc <= zero) return inf;
+    const R sq = sqrt(disc);
+    R t = cc / (sq - b);
+    if (t < zero) t = zero;
+    if (sph_ok_except(q, info, p, v, t, 0)) best = tmin(best, t);
+  }
+  if (info & kInfoInner) {
+    R t = R(-1);
+    const R cc = rr - q[1] * q[1];
+    const R disc = b * b - cc;
+    if (fabs(c.k[1]) <= ht) {
+      if (b > zero) t = zero;
+      else if (b < zero && disc > zero) t = sqrt(disc) - b;
+    } else if (disc > zero) {
+      const R sq = sqrt(disc);
+      t = (b > zero) ? -cc / (b + sq) : sq - b;
+    }
+    if (t >= zero && t < inf && sph_ok_except(q, info, p, v, t, 1)) best = tmin(best, t);
+  }
+  if (info & kInfoPhi) {
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const R dp = c.k[2 + j];
+      if (dp >= -ht) {
+        const R dv = v.x * q[2 + 2 * j] + v.y * q[3 + 2 * j];
+        if (dv >= zero) return inf;
+        R t = dp / (-dv);
+        if (t < zero) t = zero;
+        if (sph_ok_except(q, info, p, v, t, 2 + j)) best = tmin(best, t);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    const int i = 4 + j;
+    const int kind = sph_kind(info, j);
+    if (kind == kTNone) continue;
+    if (kind == kTOuter) {
+      if (c.k[i] >= -ht) {
+        if (sph_comp_dot(q, info, i, p, v) >= zero) return inf;
+        R t = radial_root(zero, q[6 + 2 * j], p, v, -1, -inf);
+        if (t == inf) return inf;
+        if (t < zero) t = zero;
+        if (sph_ok_except(q, info, p, v, t, i)) best = tmin(best, t);
+      }
+    } else if (kind == kTInner) {
+      R t = R(-1);
+      if (fabs(c.k[i]) <= ht) {
+        const R vn = sph_comp_dot(q, info, i, p, v);
+        if (vn < zero) t = zero;
+        else if (vn > zero) t = radial_root(zero, q[6 + 2 * j], p, v, +1, zero);
+      } else {
+        t = radial_root(zero, q[6 + 2 * j], p, v, +1, zero);
+      }
+      if (t >= zero && t < inf && sph_ok_except(q, info, p, v, t, i)) best = tmin(best, t);
+    } else {
+      if (c.k[i] >= -ht) {
+        const R vn = kind == kTZle ? v.z : -v.z;
+        if (vn >= zero) return inf;
+        R t = c.k[i] / (-vn);
+        if (t < zero) t = zero;
+        if (sph_ok_except(q, info, p, v, t, i)) best = tmin(best, t);
+      }
+    }
+  }
+  return best < ht ? zero : best;
+}
+
+template <typename R>
+__device__ __attribute__((noinline)) R sph_dist_out(const R* q, int info, Vec3<R> p, Vec3<R> v) {
+  const R ht = half_tol<R>(), zero = R(0);
+  const SphComps<R> c = sph_comps(q, info, p);
+  const R rr = p.x * p.x + p.y * p.y + p.z * p.z;
+  const R b = p.x * v.x + p.y * v.y + p.z * v.z;
+  R t = R(kInf);
+  if (c.k[0] >= -ht && b >= zero) return zero;
+  {
+    const R cc = rr - q[0] * q[0];
+    R disc = b * b - cc;
+    if (disc < zero) disc = zero;
+    const R sq = sqrt(disc);
+    const R to = (b > zero) ? -cc / (b + sq) : sq - b;
+    t = tmin(t, to > zero ? to : zero);
+  }
+  if (info & kInfoInner) {
+    if (c.k[1] >= -ht && b <= zero) return zero;
+    if (b < zero) {
+      const R cc = rr - q[1] * q[1];
+      const R disc = b * b - cc;
+      if (disc > zero) {
+        const R ti = cc / (sqrt(disc) - b);
+        t = tmin(t, ti > zero ? ti : zero);
+      }
+    }
+  }
+  if (info & kInfoPhi) {
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const R dp = c.k[2 + j];
+      const R dv = v.x * q[2 + 2 * j] + v.y * q[3 + 2 * j];
+      if (dp >= -ht && dv >= zero) return zero;
+      if (dv > zero) {
+        R tp = -dp / dv;
+        if (tp < zero) tp = zero;
+        t = tmin(t, tp);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    const int i = 4 + j;
+    const int kind = sph_kind(info, j);
+    if (kind == kTNone) continue;
+    const R vn = sph_comp_dot(q, info, i, p, v);
+    if (c.k[i] >= -ht && vn >= zero) return zero;
+    if (kind == kTOuter) {
+      t = tmin(t, radial_root(zero, q[6 + 2 * j], p, v, +1, zero));
+    } else if (kind == kTInner) {
+      t = tmin(t, radial_root(zero, q[6 + 2 * j], p, v, -1, zero));
+    } else if (vn > zero) {
+      const R sd = -c.k[i];
+      if (sd <= ht) return zero;
+      t = tmin(t, sd / vn);
+    }
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
 // Surface normal (Sec. 3.2 asks for the normal of the boundary surface at the
 // crossing point).  A solid's signed value is the largest of its components,
 // so at a surface point its outward normal is the gradient of the largest
@@ -624,6 +878,42 @@ __device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3&
       case 3: n = V3{0.0, -q[3], q[4]}; break;
       case 4: n = V3{0.0, 0.0, 1.0}; break;
       default: n = V3{0.0, 0.0, -1.0}; break;
+    }
+    return faces;
+  }
+  if ((info & 15) == kSphere) {
+    const SphComps<double> c = sph_comps(q, info, p);
+    int m = 0;
+    double km = c.k[0];
+#pragma unroll
+    for (int i = 1; i < 6; i++)
+      if (c.k[i] > km) {
+        m = i;
+        km = c.k[i];
+      }
+    int faces = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+      if (c.k[i] >= km - kTol) faces++;
+    const double r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+    const double rho = sqrt(p.x * p.x + p.y * p.y);
+    const double ex = rho > 0 ? p.x / rho : 1.0, ey = rho > 0 ? p.y / rho : 0.0;
+    const V3 u = r > 0 ? V3{p.x / r, p.y / r, p.z / r} : V3{0.0, 0.0, 1.0};
+    switch (m) {
+      case 0: n = u; break;
+      case 1: n = V3{-u.x, -u.y, -u.z}; break;
+      case 2: n = V3{q[2], q[3], 0.0}; break;
+      case 3: n = V3{q[4], q[5], 0.0}; break;
+      default: {
+        const int j = m - 4;
+        const double B = q[6 + 2 * j], cc = q[7 + 2 * j];
+        switch (sph_kind(info, j)) {
+          case kTOuter: n = V3{cc * ex, cc * ey, -cc * B}; break;
+          case kTInner: n = V3{-cc * ex, -cc * ey, cc * B}; break;
+          case kTZle: n = V3{0.0, 0.0, 1.0}; break;
+          default: n = V3{0.0, 0.0, -1.0}; break;
+        }
+      }
     }
     return faces;
   }
@@ -689,6 +979,7 @@ __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, boo
     case kBox: return box_inside(q, p, has_v, v);
     case kOrb: return orb_inside(q[0], p, has_v, v);
     case kTrd: return trd_inside(q, p, has_v, v);
+    case kSphere: return sph_inside(q, info, p, has_v, v);
     default: return rad_inside(q, info, p, has_v, v);
   }
 #endif
@@ -703,6 +994,7 @@ __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
     case kTrd: return trd_d(q, p);
+    case kSphere: return sph_dmax(sph_comps(q, info, p));
     default: return rad_dmax(rad_comps(q, info, p));
   }
 #endif
@@ -717,6 +1009,7 @@ __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
     case kTrd: return trd_dist_in(q, p, v);
+    case kSphere: return sph_dist_in(q, info, p, v);
     default: return rad_dist_in(q, info, p, v);
   }
 #endif
@@ -731,6 +1024,7 @@ __device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
     case kTrd: return trd_dist_out(q, p, v);
+    case kSphere: return sph_dist_out(q, info, p, v);
     default: return rad_dist_out(q, info, p, v);
   }
 #endif

@@ -230,6 +230,61 @@ bool solid_prep(int type, const double* par, double* q /*16*/, int* info, Box3* 
     *info = kTrd;
     return true;
   }
+  if (type == kSphere) {
+    // rmin, rmax, sphi, dphi, stheta, dtheta: q = {rmax, rmin, phi plane normals,
+    // B1, c1, B2, c2} (theta bound j as the cone rho = B z, B = tan theta,
+    // c = 1 / sqrt(1 + B^2)), bound kinds in the info bits
+    const double rmin = par[0], rmax = par[1], sp = par[2], dp = par[3], st = par[4], dt = par[5];
+    const double twopi = 2.0 * M_PI;
+    if (!(rmin >= 0) || !(rmax > rmin) || (rmin > 0 && rmin < kTol)) {
+      why = "sphere radii out of range";
+      return false;
+    }
+    if (!(dp > 0) || dp > twopi || (dp < twopi && dp > M_PI)) {
+      why = "phi sections must span (0, pi] or the full 2 pi";
+      return false;
+    }
+    if (!(st >= 0) || !(dt > 0) || st + dt > M_PI * (1.0 + 1e-15)) {
+      why = "theta section must lie in [0, pi]";
+      return false;
+    }
+    q[0] = rmax;
+    q[1] = rmin;
+    int inf = kSphere;
+    if (rmin > 0) inf |= kInfoInner;
+    if (dp < twopi) {
+      inf |= kInfoPhi;
+      const double ep = sp + dp;
+      q[2] = std::sin(sp);
+      q[3] = -std::cos(sp);
+      q[4] = -std::sin(ep);
+      q[5] = std::cos(ep);
+    }
+    const double th[2] = {st, st + dt};
+    for (int j = 0; j < 2; j++) {
+      const bool present = j == 0 ? th[0] > 0 : th[1] < M_PI;
+      int kind = kTNone;
+      if (present) {
+        if (th[j] == 0.5 * M_PI) {
+          kind = j == 0 ? kTZle : kTZge;
+        } else {
+          q[6 + 2 * j] = std::tan(th[j]);
+          q[7 + 2 * j] = 1.0 / std::sqrt(1.0 + q[6 + 2 * j] * q[6 + 2 * j]);
+          const bool lower_half = th[j] > 0.5 * M_PI;
+          // theta >= th below the equator and theta <= th above it keep the
+          // inside of the cone, the other two its outside
+          kind = (j == 0) != lower_half ? kTInner : kTOuter;
+        }
+      }
+      inf |= kind << (kInfoTheta + 3 * j);
+    }
+    *info = inf;
+    for (int a = 0; a < 3; a++) {
+      ext->lo[a] = -rmax;
+      ext->hi[a] = rmax;
+    }
+    return true;
+  }
   double rmin1, rmax1, rmin2, rmax2, dz, sphi, dphi;
   if (type == kTubs) {
     rmin1 = rmin2 = par[0];
@@ -411,6 +466,20 @@ bool shape_meets_box(const DauShape& d, const Box3& b, double pad) {
         s2 += e * e;
       }
       return s2 <= q[0] * q[0];
+    }
+    case kSphere: {
+      // the box against the shell: nearest point beyond rmax, or farthest
+      // point inside rmin
+      double n2 = 0, f2 = 0;
+      for (int i = 0; i < 3; i++) {
+        double e = lo[i] > 0 ? lo[i] : (hi[i] < 0 ? -hi[i] : 0.0);
+        double f = std::max(std::fabs(lo[i]), std::fabs(hi[i]));
+        n2 += e * e;
+        f2 += f * f;
+      }
+      if (n2 > q[0] * q[0]) return false;
+      if ((d.info & kInfoInner) && f2 < q[1] * q[1]) return false;
+      return true;
     }
     case kTrd: {
       // separating face plane: every corner of the (padded, daughter-frame)

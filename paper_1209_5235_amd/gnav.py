@@ -26,7 +26,7 @@ COUNTERS = ["steps", "pe", "compton", "pair", "crossings", "escaped", "cutoff", 
             "truncated", "tracks", "shortcuts", "dist_in", "dist_out", "inside", "voxel_nodes",
             "invalid", "dist_in_f32", "scored"] + \
     [f"{w}_{f}" for w in ("dist_in", "dist_out", "safety", "inside")
-     for f in ("box", "tubs", "cons", "orb", "trd", "family5")] + ["frame_maps"]
+     for f in ("box", "tubs", "cons", "orb", "trd", "sphere")] + ["frame_maps"]
 # distance arithmetic of ComputeStep (GNAV_PREC_*)
 PREC_FP64, PREC_FP32_SCREENED, PREC_FP32 = 0, 1, 2
 LIM_MOTHER, LIM_PE, LIM_COMPTON, LIM_PAIR, LIM_MAX_STEP = -1, -2, -3, -4, -5

@@ -443,13 +443,20 @@ def endcap(n_wedges=36, n_crystals=4, r_in=400.0, r_out=800.0, half_t=60.0, z_c=
     the inner to the outer radius, y half width = disc half thickness); each
     wedge holds ``n_crystals`` trapezoid crystals stacked radially.  Materials
     alternate lead / silicon wedge by wedge, crystals lead.  A silicon tube
-    layer (r 300-320, half length 700) sits between the discs.
+    layer (r 300-320, half length 700) sits between the discs, and a spherical
+    shell section (r 100-150, polar angles 0.5-2.6 rad, four phi quarters of
+    lead and water) around the origin.
     """
     b = Builder("endcap")
     s_world = b.solid(BOX, 1200.0, 1200.0, 1200.0)
     world = b.lv(s_world, "vacuum", "world")
     s_tube = b.solid(TUBS, 300.0, 320.0, 700.0, 0.0, 2 * math.pi)
     b.place(world, b.lv(s_tube, "silicon", "tube"))
+    # a spherical shell section around the source: polar band 0.5-2.6 rad, open
+    # at the poles, in four phi quarters of lead and water
+    for k in range(4):
+        s_sh = b.solid(SPHERE, 100.0, 150.0, 0.5 * math.pi * k, 0.5 * math.pi, 0.5, 2.1)
+        b.place(world, b.lv(s_sh, "lead" if k % 2 == 0 else "water", f"shell{k}"))
     half_phi = math.pi / n_wedges
     dz = 0.5 * (r_out - r_in)
     # wedge half widths at the inner and outer radius, kept inside the phi slice
