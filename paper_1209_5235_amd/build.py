@@ -16,10 +16,13 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgnav.so")
 
 # (source, object name, extra defines): the transport kernel is built once per
-# track-pool size.
-SOURCES = [("gnav_host.cpp", "gnav_host", ()), ("gnav_kernels.hip", "gnav_kernels", ()),
+# track-pool size, again per pool size with sphere sections, and once for
+# unrotated boxes.
+SOURCES = [("gnav_host.cpp", "gnav_host", ()), ("gnav_kernels.hip", "gnav_kernels", ("GNAV_SPHERES",)),
            ("gnav_mlp.hip", "gnav_mlp", ())] + \
           [("gnav_transport.hip", f"gnav_transport_pool{p}", (f"GNAV_POOL={p}",)) for p in (64, 128, 256)] + \
+          [("gnav_transport.hip", f"gnav_transport_pool{p}_spheres", (f"GNAV_POOL={p}", "GNAV_SPHERES"))
+           for p in (64, 128, 256)] + \
           [("gnav_transport.hip", "gnav_transport_pool64_axis_boxes", ("GNAV_POOL=64", "GNAV_AXIS_BOXES"))]
 
 # -ffp-contract=off: no fused multiply-add contraction, so each distance is

@@ -881,6 +881,7 @@ __device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3&
     }
     return faces;
   }
+#ifdef GNAV_SPHERES
   if ((info & 15) == kSphere) {
     const SphComps<double> c = sph_comps(q, info, p);
     int m = 0;
@@ -917,6 +918,7 @@ __device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3&
     }
     return faces;
   }
+#endif
   if ((info & 15) == kOrb) {
     const double r = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
     n = r > 0 ? V3{p.x / r, p.y / r, p.z / r} : V3{0.0, 0.0, 1.0};
@@ -962,6 +964,11 @@ __device__ __forceinline__ int solid_normal(int info, const double* q, V3 p, V3&
 // ---------------------------------------------------------------------------
 // Dispatch over solid families ("fork" by type code)
 //
+// Sphere sections are dispatched only in translation units built with
+// GNAV_SPHERES (the query kernels always; the transport kernel in builds of
+// its own that the host launches when a batch can reach a sphere section):
+// their code would otherwise cost every other geometry registers.
+//
 // A translation unit built with GNAV_AXIS_BOXES compiles the box code alone
 // and treats every placement as a translation (the point and direction maps
 // above): the host launches that build of the transport kernel only when
@@ -979,7 +986,9 @@ __device__ __forceinline__ int solid_inside(int info, const double* q, V3 p, boo
     case kBox: return box_inside(q, p, has_v, v);
     case kOrb: return orb_inside(q[0], p, has_v, v);
     case kTrd: return trd_inside(q, p, has_v, v);
+#ifdef GNAV_SPHERES
     case kSphere: return sph_inside(q, info, p, has_v, v);
+#endif
     default: return rad_inside(q, info, p, has_v, v);
   }
 #endif
@@ -994,7 +1003,9 @@ __device__ __forceinline__ R solid_d(int info, const R* q, Vec3<R> p) {
     case kBox: return box_d(q, p);
     case kOrb: return orb_d(q[0], p);
     case kTrd: return trd_d(q, p);
+#ifdef GNAV_SPHERES
     case kSphere: return sph_dmax(sph_comps(q, info, p));
+#endif
     default: return rad_dmax(rad_comps(q, info, p));
   }
 #endif
@@ -1009,7 +1020,9 @@ __device__ __forceinline__ R solid_dist_in(int info, const R* q, Vec3<R> p, Vec3
     case kBox: return box_dist_in(q, p, v);
     case kOrb: return orb_dist_in(q[0], p, v);
     case kTrd: return trd_dist_in(q, p, v);
+#ifdef GNAV_SPHERES
     case kSphere: return sph_dist_in(q, info, p, v);
+#endif
     default: return rad_dist_in(q, info, p, v);
   }
 #endif
@@ -1024,7 +1037,9 @@ __device__ __forceinline__ R solid_dist_out(int info, const R* q, Vec3<R> p, Vec
     case kBox: return box_dist_out(q, p, v);
     case kOrb: return orb_dist_out(q[0], p, v);
     case kTrd: return trd_dist_out(q, p, v);
+#ifdef GNAV_SPHERES
     case kSphere: return sph_dist_out(q, info, p, v);
+#endif
     default: return rad_dist_out(q, info, p, v);
   }
 #endif

@@ -674,6 +674,7 @@ struct GeomRec {
   int t_base, n_t;
   int n_class = 0;  // voxelised mothers (candidate-ordering classes)
   bool axis_boxes = false;  // every solid is a box and every placement a translation
+  bool spheres = false;     // some solid is a sphere section
   bool any_wide = false;    // some mother's voxel nodes hold enough candidates for ordered walks
   int lv_base, pv_base, solid_base, mat_base;
   std::vector<int> h_parent, h_pv, h_lv, h_depth;  // per-geometry ids
@@ -1073,6 +1074,7 @@ gnav_status gnav_upload_geometry(gnav_ctx* c, const gnav_geometry_desc* d, int32
   GeomRec gr;
   gr.t_base = (int)c->t_rec.size();
   gr.axis_boxes = std::all_of(d->solid_type, d->solid_type + d->n_solids, [](int32_t ty) { return ty == kBox; });
+  gr.spheres = std::any_of(d->solid_type, d->solid_type + d->n_solids, [](int32_t ty) { return ty == kSphere; });
   for (int p = 0; p < d->n_pv && gr.axis_boxes; p++) gr.axis_boxes = is_identity(d->pv_rot + 9L * p);
   gr.n_t = nt;
   gr.lv_base = (int)c->lv_rec.size();
@@ -1604,6 +1606,9 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
   L.axis_boxes = b->event_geom_dev ? std::all_of(c->geoms.begin(), c->geoms.end(),
                                                  [](const GeomRec& g) { return g.axis_boxes; })
                                    : c->geoms[b->geom_id].axis_boxes;
+  L.spheres = b->event_geom_dev ? std::any_of(c->geoms.begin(), c->geoms.end(),
+                                              [](const GeomRec& g) { return g.spheres; })
+                                : c->geoms[b->geom_id].spheres;
   return GNAV_OK;
 }
 

@@ -50,6 +50,7 @@ struct TransportLaunch {
   int block;
   int grid;
   bool axis_boxes;  // every solid the batch can reach is a box placed without rotation
+  bool spheres;     // some solid the batch can reach is a sphere section
   bool count;
   int order;
   int prec;  // kPrecFP64 / kPrecScreened / kPrecPure (FP32 forms use the plain order)
@@ -97,6 +98,9 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st);
 // the transport kernel built for track pools of 64, 128 and 256 slots
 hipError_t launch_transport_pool64(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_transport_pool64_axis_boxes(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool64_spheres(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool128_spheres(const TransportLaunch& L, hipStream_t st);
+hipError_t launch_transport_pool256_spheres(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_transport_pool128(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_transport_pool256(const TransportLaunch& L, hipStream_t st);
 hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, const double* dir,

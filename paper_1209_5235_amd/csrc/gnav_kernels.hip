@@ -323,6 +323,11 @@ hipError_t launch_zero(void* p, size_t words, hipStream_t st) {
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, L.queue, 1);
   if (L.n <= 0) return hipGetLastError();
+  if (L.spheres) {
+    if (L.block == 64) return launch_transport_pool64_spheres(L, st);
+    if (L.block == 128) return launch_transport_pool128_spheres(L, st);
+    return launch_transport_pool256_spheres(L, st);
+  }
   if (L.block == 64) return L.axis_boxes ? launch_transport_pool64_axis_boxes(L, st) : launch_transport_pool64(L, st);
   if (L.block == 128) return launch_transport_pool128(L, st);
   return launch_transport_pool256(L, st);

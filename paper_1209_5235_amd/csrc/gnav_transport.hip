@@ -2,7 +2,8 @@
 // (wave64), built once per track-pool size (GNAV_POOL slots per block: 64,
 // 128 or 256), each build in its own namespace, plus a 64-slot build for
 // geometries made of boxes placed without rotation (GNAV_AXIS_BOXES,
-// namespace pool64_axis_boxes).
+// namespace pool64_axis_boxes) and, per pool size, a build that also
+// handles sphere sections (GNAV_SPHERES, namespaces pool*_spheres).
 //
 // Transport follows Sec. 3.1: each photon draws an Exp(1) optical depth
 // (Alg. 1, steps 1-2), spends it boundary to boundary (S_j update, Eq. 6)
@@ -28,8 +29,10 @@
 #endif
 #define GNAV_CAT2(a, b) a##b
 #define GNAV_CAT(a, b) GNAV_CAT2(a, b)
-#ifdef GNAV_AXIS_BOXES
+#if defined(GNAV_AXIS_BOXES)
 #define GNAV_POOL_NS GNAV_CAT(GNAV_CAT(pool, GNAV_POOL), _axis_boxes)
+#elif defined(GNAV_SPHERES)
+#define GNAV_POOL_NS GNAV_CAT(GNAV_CAT(pool, GNAV_POOL), _spheres)
 #else
 #define GNAV_POOL_NS GNAV_CAT(pool, GNAV_POOL)
 #endif

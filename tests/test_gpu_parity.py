@@ -186,6 +186,23 @@ def test_transport_parity_pair_heavy(ctx, torch_dev, oracle_lib):
     assert np.allclose(got["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
 
 
+@pytest.mark.parametrize("block", [128, 256])
+def test_transport_parity_sphere_builds(ctx, torch_dev, oracle_lib, block):
+    """Geometries with sphere sections run the transport builds that dispatch
+    them, at every pool size: per-track parity on the endcap workload."""
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "endcap", oracle_lib)
+    print_case("transport_sphere_build", block)
+    _, prim, _ = W.endcap(n=2000, seed=4)
+    got = run_transport(ctx, torch, gid, prim, 256, block=block)
+    ref = og.transport(prim, seed=0, log_cap=256)
+    bad = compare_logs(got["log"], got["log_n"], got["log_fate"], ref, 256)
+    assert not bad, bad[:10]
+    for k in EXACT:
+        assert got["counters"][k] == ref["counters"][k], k
+    assert np.allclose(got["edep_touchable"], ref["edep_touchable"], rtol=RTOL, atol=1e-12)
+
+
 def test_transport_launch_shape_independent(ctx, torch_dev, oracle_lib):
     """Counter-keyed random numbers: any block/grid gives the same tracks."""
     torch = torch_dev
