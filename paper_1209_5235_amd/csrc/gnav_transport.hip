@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gnav_device.h"
 #include "gnav_internal.h"
@@ -114,7 +115,6 @@ struct Pool {
   int nrec[kPool];
   unsigned cnt_a[kPool];  // Compton scatters | shortcuts << 16
   unsigned cnt_b[kPool];  // crossings | pushes << 24
-  int pred[kPool];     // learned order: predicted candidate position of the next step
   double dep[kPool];   // deposits of the slot's current track, added to its event at the end
   // annihilation photons waiting for any free slot of the block (a stack)
   double sx[kStack], sy[kStack], sz[kStack], svx[kStack], svy[kStack], svz[kStack];
@@ -255,10 +255,14 @@ __device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, 
 // Learned order: the block gathers the features of its eligible steps here
 // and the network (gnav_learned.h) writes each step's predicted candidate
 // position over its class.
+// Block memory of the learned order only (the other instantiations leave it
+// out, which keeps the 64-slot box build within twelve blocks per CU).
 struct LearnScratch {
   uint16_t xf[kPool][6];  // bf16 features of the listed steps (mother-frame point, direction)
   uint16_t cls[kPool];    // their ordering classes in, the predicted candidate positions out
+  int pred[kPool];        // predicted candidate position of each slot's next step
 };
+struct NoScratch {};
 
 template <bool LOG, bool COUNT, int ORDER, int PREC>
 __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
@@ -267,6 +271,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   const int lane = tid & 63;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ Pool P;
+  __shared__ typename std::conditional<ORDER == kOrderLearned, LearnScratch, NoScratch>::type S;
   double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
 
   if (tid < kBlockCounters) P.cnt[tid] = 0ull;
@@ -507,13 +512,12 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
     // (only steps in mothers whose voxel nodes hold enough candidates on
     // average for an order to pay)
     if constexpr (ORDER == kOrderLearned) {
-      __shared__ LearnScratch S;
       bool elig = false;
       if (P.status[tid] == kStep) {
         const LRec& L = G.lv[P.lvk[tid] >> 1];
         elig = L.lclass >= 0 && L.wide;
       }
-      P.pred[tid] = -1;
+      S.pred[tid] = -1;
       int n = compact<1>(P, elig, 0);
       // Score only when a full 16-row tile is due: the out-of-line call saves
       // and restores the live registers of the loop through scratch memory,
@@ -533,7 +537,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         __syncthreads();
         learned_predict<kWaves>(a.mlp, S.xf, S.cls, n);
         __syncthreads();
-        if (tid < n) P.pred[P.list[tid]] = S.cls[tid];
+        if (tid < n) S.pred[P.list[tid]] = S.cls[tid];
         if (tid == 0) atomicAdd(&P.cnt[GNAV_C_SCORED], (unsigned long long)n);
       }
       __syncthreads();
@@ -603,8 +607,9 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             if (COUNT) nc.levels(trec_depth(G.t[T]));
             double saf;
             int2 nd;
-            s_geo = compute_step_p<COUNT, ORDER, PREC>(G, L, lvk >> 1, pl, vl, lim, saf, nc,
-                                                       ORDER == kOrderLearned ? P.pred[s] : -1, &nd);
+            int pred = -1;
+            if constexpr (ORDER == kOrderLearned) pred = S.pred[s];
+            s_geo = compute_step_p<COUNT, ORDER, PREC>(G, L, lvk >> 1, pl, vl, lim, saf, nc, pred, &nd);
             safety = saf;
             phys = s_phys <= s_geo;
             // the face a box is left through, for the neighbour shortcut of the relocation
