@@ -368,6 +368,11 @@ typedef struct {
                                  for this geometry, precision and order when present */
   gnav_digest* digest_dev;    /* optional [3 n] per-track digests (slots as for the log); the
                                  caller zeroes them; log_dev may then be NULL */
+  int32_t keep_order;         /* 0: blocks take the primaries in decreasing energy (half-octave
+                                 classes, sorted on the device before the transport, in a buffer
+                                 of the context), so that the tracks still running when the
+                                 batch runs dry are short ones; 1: in the order given (always so
+                                 in gnav_transport_batch_noalloc).  Results do not depend on it */
 } gnav_batch;
 
 /* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase

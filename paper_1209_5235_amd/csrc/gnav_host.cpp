@@ -705,11 +705,12 @@ struct gnav_ctx {
   // device copies
   DevBuf d_t_rec, d_t_xf, d_lv_rec, d_pv_rec, d_pvf, d_pv_cyl, d_lv_parf, d_vox_node, d_vox_cand, d_xs,
       d_mat_rho, d_geom_tbase, d_nbr;
-  DevBuf d_queue, d_pend;
+  DevBuf d_queue, d_pend, d_claim;
   DevGeom G{};
   // Generations of what a captured graph holds: the resident tables (every
-  // upload reallocates them) and the pending-photon buffer (reallocated when
-  // a batch needs a larger grid).
+  // upload reallocates them) and the launch buffers (the pending-photon
+  // buffer, reallocated when a batch needs a larger grid, and the claim
+  // order, reallocated when a batch holds more primaries).
   uint64_t tables_gen = 0, pend_gen = 0;
   // Launches of one context share d_queue and d_pend: a launch on another
   // stream than the previous one waits for it on the device.
@@ -1572,6 +1573,18 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
       c->pend_gen++;
     }
     L.pend = c->d_pend.as<double>();
+    if (!b->keep_order && b->n_primaries > 0) {
+      // claim order (int per primary) and the class counts and cursors
+      size_t claim_bytes = 2 * kClaimClasses * sizeof(unsigned) + (size_t)b->n_primaries * sizeof(int);
+      if (c->d_claim.bytes < claim_bytes) {
+        HIP_TRY(c, hipDeviceSynchronize(), "synchronize");
+        HIP_TRY(c, c->d_claim.upload(nullptr, claim_bytes, stream), "claim-order buffer");
+        HIP_TRY(c, hipStreamSynchronize(stream), "synchronize");
+        c->pend_gen++;
+      }
+      L.claim_cnt = c->d_claim.as<unsigned>();
+      L.claim = reinterpret_cast<int*>(c->d_claim.as<unsigned>() + 2 * kClaimClasses);
+    }
   }
   L.count = b->count_work != 0;
   if (b->order < 0 || b->order > 2) return fail(c, GNAV_EINVAL, "order must be 0, 1 or 2");
@@ -1836,7 +1849,8 @@ gnav_status gnav_graph_launch(gnav_ctx* c, gnav_graph* g, void* stream) {
   if (g->tables_gen != c->tables_gen)
     return fail(c, GNAV_ESTATE, "geometry tables were reallocated after the capture (capture again)");
   if (g->pend_gen != c->pend_gen)
-    return fail(c, GNAV_ESTATE, "pending-photon buffer was reallocated after the capture (capture again)");
+    return fail(c, GNAV_ESTATE, "launch buffers (pending photons, claim order) were reallocated after the capture "
+                                "(capture again)");
   if (g->uses_mlp && g->mlp_gen != c->geoms[g->geom_id].mlp_gen)
     return fail(c, GNAV_ESTATE, "network binding changed after the capture (capture again)");
   hipStream_t st = (hipStream_t)stream;

@@ -8,6 +8,9 @@
 
 namespace gnav {
 
+// Energy classes of the claim order: half octaves from 1 keV, highest first.
+constexpr int kClaimClasses = 64;
+
 // Device view of a candidate-ordering network (bf16 weights, float biases).
 struct MlpView {
   const uint16_t* w1x;  // [128][6]
@@ -23,6 +26,8 @@ struct MlpView {
 struct TransportLaunch {
   DevGeom G;
   long n;
+  int* claim;              // [n] queue order of the primaries (decreasing energy), or null: as given
+  unsigned* claim_cnt;     // [2 * kClaimClasses] class counts and cursors for building it
   const int* event;
   const int* prim_id;
   const double* pos;

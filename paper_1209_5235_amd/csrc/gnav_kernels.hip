@@ -320,9 +320,66 @@ hipError_t launch_zero(void* p, size_t words, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Energy class of a primary for the claim order: 0 for the highest energies.
+// Half octaves from 1 keV (class 63 holds everything at or below 1 keV, and
+// energies that are not positive finite numbers, which the transport rejects).
+__device__ __forceinline__ int claim_class(double E) {
+  if (!(E > 1e-3) || !(E < 1e300)) return kClaimClasses - 1;
+  const int h = (int)(2.0 * log2(E * 1e3));
+  return kClaimClasses - 1 - min(h, kClaimClasses - 1);
+}
+
+// Class counts of the batch (cnt[0..kClaimClasses), zeroed before).
+__global__ void __launch_bounds__(256) k_claim_count(const double* __restrict__ E, long n, unsigned* cnt) {
+  __shared__ unsigned h[kClaimClasses];
+  if (threadIdx.x < kClaimClasses) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    atomicAdd(&h[claim_class(E[i])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kClaimClasses && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+// Queue positions: the primaries of class c fill [start_c, start_c + cnt_c)
+// in the order their blocks reserve a range (cnt[kClaimClasses + c] is the
+// class's cursor, zeroed before); the order within a class is not fixed.
+__global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ E, long n, unsigned* cnt,
+                                                     int* __restrict__ claim) {
+  __shared__ unsigned start[kClaimClasses], h[kClaimClasses], base[kClaimClasses];
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int c = 0; c < kClaimClasses; c++) {
+      start[c] = acc;
+      acc += cnt[c];
+    }
+  }
+  for (long i0 = blockIdx.x * 256L; i0 < n; i0 += (long)gridDim.x * 256) {
+    if (threadIdx.x < kClaimClasses) h[threadIdx.x] = 0;
+    __syncthreads();
+    const long i = i0 + threadIdx.x;
+    const int c = i < n ? claim_class(E[i]) : -1;
+    const unsigned r = c >= 0 ? atomicAdd(&h[c], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x < kClaimClasses && h[threadIdx.x])
+      base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cnt[kClaimClasses + threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) claim[base[c] + r] = (int)i;
+    __syncthreads();
+  }
+}
+
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, L.queue, 1);
   if (L.n <= 0) return hipGetLastError();
+  if (L.claim) {
+    // claim order: primaries by decreasing energy, so that the tracks still
+    // running when the queue runs dry are short ones
+    const unsigned blocks = (unsigned)std::min<long>((L.n + 255) / 256, 1024);
+    hipError_t e = launch_zero(L.claim_cnt, kClaimClasses, st);  // 2 * kClaimClasses u32 = kClaimClasses words
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_claim_count, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
+    hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt, L.claim);
+  }
   if (L.spheres) {
     if (L.block == 64) return launch_transport_pool64_spheres(L, st);
     if (L.block == 128) return launch_transport_pool128_spheres(L, st);

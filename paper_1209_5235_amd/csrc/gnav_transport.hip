@@ -423,6 +423,9 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         }
       }
       if (idx >= 0) {
+        // queue position -> primary (the claim order hands out the primaries
+        // in decreasing energy when the library built one)
+        if (a.claim) idx = a.claim[idx];
         V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
         V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
         double E = a.energy[idx];
@@ -858,6 +861,7 @@ hipError_t launch(const TransportLaunch& L, hipStream_t st) {
   a.esc_ev = L.esc_ev;
   a.counters = L.counters;
   a.queue = L.queue;
+  a.claim = L.claim;
   a.pend = L.pend;
   a.log = L.log;
   a.log_cap = L.log_cap;

@@ -66,7 +66,7 @@ class gnav_batch(C.Structure):
         ("record_count_dev", C.c_void_p), ("log_dev", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_n_dev", C.c_void_p), ("log_fate_dev", C.c_void_p),
         ("chunk", C.c_int32), ("sort_period", C.c_int32), ("tuned", C.c_int32),
-        ("digest_dev", C.c_void_p),
+        ("digest_dev", C.c_void_p), ("keep_order", C.c_int32),
     ]
 
 
@@ -339,7 +339,7 @@ class Context:
 
     def _batch(self, geom_id, prim, seed=0, e_cut=1e-3, max_steps=0, precision=0, block=0, grid=0,
                log=None, event_geom=None, count_work=False, order=0, record=None, chunk=0,
-               sort_period=0, tuned=False, digest=None):
+               sort_period=0, tuned=False, digest=None, keep_order=False):
         b = gnav_batch()
         b.n_primaries = prim["energy"].shape[0]
         b.event_dev = prim["event"].data_ptr()
@@ -360,6 +360,7 @@ class Context:
         b.chunk = chunk
         b.sort_period = sort_period
         b.tuned = int(bool(tuned))
+        b.keep_order = int(bool(keep_order))
         if record is not None:
             b.record_dev = record["rec"].data_ptr()
             b.record_capacity = record["cap"]
