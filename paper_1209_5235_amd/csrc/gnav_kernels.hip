@@ -220,10 +220,13 @@ __global__ void __launch_bounds__(256) k_free_path(DevGeom G, int W, long n, con
   if (nb_out) nb_out[i] = nb;
 }
 
-// Zero a small device array (a kernel rather than a memset node, so the
-// launch sequence can be captured in a graph).
-__global__ void k_reset_u64(unsigned long long* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+// The work queue's counter and, when a claim order is built, its class
+// counts and cursors, zeroed in one launch (a kernel rather than a memset
+// node, so the launch sequence can be captured in a graph).
+__global__ void k_reset_launch(unsigned long long* queue, unsigned* claim_cnt) {
+  if (threadIdx.x == 0) queue[0] = 0ull;
+  if (claim_cnt)
+    for (int i = threadIdx.x; i < 2 * kClaimClasses; i += blockDim.x) claim_cnt[i] = 0u;
 }
 
 __global__ void k_zero_words(unsigned long long* p, size_t n) {
@@ -369,14 +372,12 @@ __global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ 
 }
 
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, st, L.queue, 1);
+  hipLaunchKernelGGL(k_reset_launch, dim3(1), dim3(128), 0, st, L.queue, L.n > 0 ? L.claim_cnt : nullptr);
   if (L.n <= 0) return hipGetLastError();
   if (L.claim) {
     // claim order: primaries by decreasing energy, so that the tracks still
     // running when the queue runs dry are short ones
     const unsigned blocks = (unsigned)std::min<long>((L.n + 255) / 256, 1024);
-    hipError_t e = launch_zero(L.claim_cnt, kClaimClasses, st);  // 2 * kClaimClasses u32 = kClaimClasses words
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_claim_count, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
     hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt, L.claim);
   }
