@@ -594,6 +594,7 @@ def headline(args, ctx, gnav, cpu, workers):
             "nav_steps_per_batch": steps_per_batch,
             "block": args.block or 64,
             "grid": args.grid or "default",
+            "claim_order": "decreasing energy (library default)",
         },
         "roofline": roof,
         "counters": c,

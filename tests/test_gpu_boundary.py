@@ -1,7 +1,10 @@
 """GPU: the C-ABI boundary's state rules and query arguments.
 
 * graphs refuse to replay (GNAV_ESTATE, no device work) once a table, the
-  pending-photon buffer or the bound network they captured is gone;
+  pending-photon buffer, the claim-order buffer or the bound network they
+  captured is gone;
+* the claim order (primaries taken in decreasing energy, the default) leaves
+  every track's result as with the order given;
 * max_steps_per_track above the packed counter range is rejected, and
   truncation itself matches the oracle;
 * gnav_compute_step's max_step limit, candidate orders and precision
@@ -52,6 +55,67 @@ def test_graph_is_stale_after_upload_and_larger_grid(torch_dev, oracle_lib):
     c.graph_free(g)
     t.free()
     c.close()
+
+
+def test_graph_is_stale_after_claim_buffer_grows(torch_dev, oracle_lib):
+    """A batch with more primaries than any before reallocates the claim-order
+    buffer (same grid, so the pending buffer stays): a graph captured before
+    refuses to replay; with keep_order the larger batch allocates nothing."""
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav
+    print_case("graph_stale_claim")
+    geoms, prim, _ = W.tiny(n=2000)
+    c = gnav.Context(0)
+    gid, _ = c.upload_geometry(geoms[0])
+    dev = gnav.primaries_to_device(prim, "cuda")
+    t = c.tally_create(prim.n_events)
+    g = c.graph_create(gid, dev, t, grid=64)
+    c.graph_launch(g)
+    bigger = W.tiny(n=5000)[1]
+    big = gnav.primaries_to_device(bigger, "cuda")
+    t2 = c.tally_create(bigger.n_events)
+    c.transport_batch(gid, big, t2, grid=64, keep_order=True)
+    torch.cuda.synchronize()
+    c.graph_launch(g)  # nothing reallocated
+    c.transport_batch(gid, big, t2, grid=64)
+    torch.cuda.synchronize()
+    with pytest.raises(gnav.GnavError, match="ESTATE"):
+        c.graph_launch(g)
+    c.graph_free(g)
+    t2.free()
+    t.free()
+    c.close()
+
+
+@pytest.mark.parametrize("name,n", [("calorimeter", 20000), ("barrel", 5000)])
+def test_claim_order_leaves_tracks_unchanged(ctx, torch_dev, oracle_lib, name, n):
+    """Every track's digest (record count, fate, hash of its volume and
+    limiter sequence, sums of steps and deposits) is the same whether the
+    blocks take the primaries in decreasing energy or in the order given, and
+    the counters equal the oracle's."""
+    torch = torch_dev
+    from paper_1209_5235_amd import gnav
+    desc, gid, nt, og = geom(ctx, name, oracle_lib)
+    print_case("claim_order", name)
+    _, prim, _ = W.WORKLOADS[name](n=n)
+    dev = gnav.primaries_to_device(prim, "cuda")
+    out = {}
+    for keep in (False, True):
+        d = gnav.make_digests(prim.n, "cuda")
+        t = ctx.tally_create(prim.n_events)
+        ctx.transport_batch(gid, dev, t, digest=d, keep_order=keep)
+        torch.cuda.synchronize()
+        out[keep] = (gnav.digests_to_numpy(d), t.read())
+        t.free()
+    (da, ta), (db, tb) = out[False], out[True]
+    for f in ("hash", "n", "fate"):
+        assert np.array_equal(da[f], db[f]), f
+    for f in ("sum_step", "sum_edep"):
+        assert np.allclose(da[f], db[f], rtol=1e-12, atol=1e-15), f
+    ref = og.transport(prim, seed=0)
+    for k in ("steps", "pe", "compton", "pair", "crossings", "escaped", "tracks"):
+        assert ta["counters"][k] == tb["counters"][k] == ref["counters"][k], k
+    assert np.allclose(ta["edep_event"], ref["edep_event"], rtol=RTOL, atol=1e-15)
 
 
 def test_graph_is_stale_after_network_freed(torch_dev):
