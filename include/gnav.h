@@ -372,7 +372,9 @@ typedef struct {
                                  classes, sorted on the device before the transport, in a buffer
                                  of the context), so that the tracks still running when the
                                  batch runs dry are short ones; 1: in the order given (always so
-                                 in gnav_transport_batch_noalloc).  Results do not depend on it */
+                                 in gnav_transport_batch_noalloc, and for batches with per-event
+                                 geometries, whose given order keeps the tracks of one geometry
+                                 together).  Results do not depend on it */
 } gnav_batch;
 
 /* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase

@@ -1573,7 +1573,7 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
       c->pend_gen++;
     }
     L.pend = c->d_pend.as<double>();
-    if (!b->keep_order && b->n_primaries > 0) {
+    if (!b->keep_order && !b->event_geom_dev && b->n_primaries > 0) {
       // claim order (int per primary) and the class counts and cursors
       size_t claim_bytes = 2 * kClaimClasses * sizeof(unsigned) + (size_t)b->n_primaries * sizeof(int);
       if (c->d_claim.bytes < claim_bytes) {
