@@ -11,6 +11,16 @@ namespace gnav {
 // Energy classes of the claim order: half octaves from 1 keV, highest first.
 constexpr int kClaimClasses = 64;
 
+// A primary copied into claim order, so that the transport reads the
+// primaries it claims contiguously (72 bytes).
+struct ClaimRec {
+  double pos[3], dir[3], energy;
+  int event, prim_id;
+  int index;  // position in the caller's arrays (log and digest slots)
+  int pad;
+};
+static_assert(sizeof(ClaimRec) == 72, "claim record layout");
+
 // Device view of a candidate-ordering network (bf16 weights, float biases).
 struct MlpView {
   const uint16_t* w1x;  // [128][6]
@@ -26,7 +36,7 @@ struct MlpView {
 struct TransportLaunch {
   DevGeom G;
   long n;
-  int* claim;              // [n] queue order of the primaries (decreasing energy), or null: as given
+  ClaimRec* claim;         // [n] the primaries in queue order (decreasing energy), or null: as given
   unsigned* claim_cnt;     // [2 * kClaimClasses] class counts and cursors for building it
   const int* event;
   const int* prim_id;

@@ -346,8 +346,12 @@ __global__ void __launch_bounds__(256) k_claim_count(const double* __restrict__ 
 // Queue positions: the primaries of class c fill [start_c, start_c + cnt_c)
 // in the order their blocks reserve a range (cnt[kClaimClasses + c] is the
 // class's cursor, zeroed before); the order within a class is not fixed.
-__global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ E, long n, unsigned* cnt,
-                                                     int* __restrict__ claim) {
+// Each primary is copied to its position (reads in the caller's order, one
+// 72-byte record written per primary).
+__global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ pos, const double* __restrict__ dir,
+                                                     const double* __restrict__ E, const int* __restrict__ event,
+                                                     const int* __restrict__ prim_id, long n, unsigned* cnt,
+                                                     ClaimRec* __restrict__ claim) {
   __shared__ unsigned start[kClaimClasses], h[kClaimClasses], base[kClaimClasses];
   if (threadIdx.x == 0) {
     unsigned acc = 0;
@@ -366,7 +370,20 @@ __global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ 
     if (threadIdx.x < kClaimClasses && h[threadIdx.x])
       base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cnt[kClaimClasses + threadIdx.x], h[threadIdx.x]);
     __syncthreads();
-    if (c >= 0) claim[base[c] + r] = (int)i;
+    if (c >= 0) {
+      ClaimRec q;
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        q.pos[k] = pos[3 * i + k];
+        q.dir[k] = dir[3 * i + k];
+      }
+      q.energy = E[i];
+      q.event = event[i];
+      q.prim_id = prim_id[i];
+      q.index = (int)i;
+      q.pad = 0;
+      claim[base[c] + r] = q;
+    }
     __syncthreads();
   }
 }
@@ -379,7 +396,8 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
     // running when the queue runs dry are short ones
     const unsigned blocks = (unsigned)std::min<long>((L.n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_claim_count, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
-    hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt, L.claim);
+    hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.pos, L.dir, L.energy, L.event, L.prim_id,
+                       L.n, L.claim_cnt, L.claim);
   }
   if (L.spheres) {
     if (L.block == 64) return launch_transport_pool64_spheres(L, st);

@@ -103,7 +103,7 @@ struct TransportArgs {
   double* esc_ev;
   unsigned long long* counters;
   unsigned long long* queue;  // [0]: next primary
-  const int* claim;           // [n] primary at each queue position, or null (queue order)
+  const ClaimRec* claim;      // [n] the primaries in queue order, or null (the caller's order)
   double* pend;               // [lanes][6]: pending annihilation photon position and direction
   gnav_logrec* log;
   long log_cap;

@@ -423,13 +423,26 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         }
       }
       if (idx >= 0) {
-        // queue position -> primary (the claim order hands out the primaries
-        // in decreasing energy when the library built one)
-        if (a.claim) idx = a.claim[idx];
-        V3 x{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
-        V3 v{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
-        double E = a.energy[idx];
-        int event = a.event[idx];
+        // the primary at this queue position: from the claim-order copy
+        // (decreasing energy) when the library built one
+        V3 x, v;
+        double E;
+        int event, prim_id;
+        if (a.claim) {
+          const ClaimRec& r = a.claim[idx];
+          x = V3{r.pos[0], r.pos[1], r.pos[2]};
+          v = V3{r.dir[0], r.dir[1], r.dir[2]};
+          E = r.energy;
+          event = r.event;
+          prim_id = r.prim_id;
+          idx = r.index;
+        } else {
+          x = V3{a.pos[3 * idx], a.pos[3 * idx + 1], a.pos[3 * idx + 2]};
+          v = V3{a.dir[3 * idx], a.dir[3 * idx + 1], a.dir[3 * idx + 2]};
+          E = a.energy[idx];
+          event = a.event[idx];
+          prim_id = a.prim_id[idx];
+        }
         int g = a.geom_default;
         bool ok = event >= 0 && event < a.n_events;
         if (ok && a.event_geom) g = a.event_geom[event];
@@ -444,7 +457,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
           P.vz[s] = v.z;
           P.E[s] = E;
           P.event[s] = event;
-          P.key[s] = a.prim_id[idx] << 2;
+          P.key[s] = prim_id << 2;
           P.tbase[s] = a.geom_tbase[g];
           P.prim[s] = (int)idx;
           P.sub_pend[s] = 0;
