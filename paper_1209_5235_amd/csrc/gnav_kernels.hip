@@ -394,8 +394,10 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   if (L.claim) {
     // claim order: primaries by decreasing energy, so that the tracks still
     // running when the queue runs dry are short ones
+    // (fewer blocks for the counts: each adds its histogram to the same 64 counters)
     const unsigned blocks = (unsigned)std::min<long>((L.n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_claim_count, dim3(blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
+    const unsigned count_blocks = std::min(blocks, 256u);
+    hipLaunchKernelGGL(k_claim_count, dim3(count_blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
     hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.pos, L.dir, L.energy, L.event, L.prim_id,
                        L.n, L.claim_cnt, L.claim);
   }
