@@ -360,29 +360,40 @@ __global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ 
       acc += cnt[c];
     }
   }
-  for (long i0 = blockIdx.x * 256L; i0 < n; i0 += (long)gridDim.x * 256) {
+  // kClaimSpan primaries per thread and pass: one reservation per class and
+  // pass for 256 * kClaimSpan primaries keeps the shared cursors uncontended
+  constexpr int kClaimSpan = 4;
+  for (long i0 = blockIdx.x * (256L * kClaimSpan); i0 < n; i0 += (long)gridDim.x * 256 * kClaimSpan) {
     if (threadIdx.x < kClaimClasses) h[threadIdx.x] = 0;
     __syncthreads();
-    const long i = i0 + threadIdx.x;
-    const int c = i < n ? claim_class(E[i]) : -1;
-    const unsigned r = c >= 0 ? atomicAdd(&h[c], 1u) : 0u;
+    int c[kClaimSpan];
+    unsigned r[kClaimSpan];
+#pragma unroll
+    for (int k = 0; k < kClaimSpan; k++) {
+      const long i = i0 + k * 256 + threadIdx.x;
+      c[k] = i < n ? claim_class(E[i]) : -1;
+      r[k] = c[k] >= 0 ? atomicAdd(&h[c[k]], 1u) : 0u;
+    }
     __syncthreads();
     if (threadIdx.x < kClaimClasses && h[threadIdx.x])
       base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cnt[kClaimClasses + threadIdx.x], h[threadIdx.x]);
     __syncthreads();
-    if (c >= 0) {
+#pragma unroll
+    for (int k = 0; k < kClaimSpan; k++) {
+      if (c[k] < 0) continue;
+      const long i = i0 + k * 256 + threadIdx.x;
       ClaimRec q;
 #pragma unroll
-      for (int k = 0; k < 3; k++) {
-        q.pos[k] = pos[3 * i + k];
-        q.dir[k] = dir[3 * i + k];
+      for (int j = 0; j < 3; j++) {
+        q.pos[j] = pos[3 * i + j];
+        q.dir[j] = dir[3 * i + j];
       }
       q.energy = E[i];
       q.event = event[i];
       q.prim_id = prim_id[i];
       q.index = (int)i;
       q.pad = 0;
-      claim[base[c] + r] = q;
+      claim[base[c[k]] + r[k]] = q;
     }
     __syncthreads();
   }
@@ -394,12 +405,12 @@ hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
   if (L.claim) {
     // claim order: primaries by decreasing energy, so that the tracks still
     // running when the queue runs dry are short ones
-    // (fewer blocks for the counts: each adds its histogram to the same 64 counters)
-    const unsigned blocks = (unsigned)std::min<long>((L.n + 255) / 256, 1024);
-    const unsigned count_blocks = std::min(blocks, 256u);
+    // (few blocks for the counts: each adds its histogram to the same 64 counters)
+    const unsigned count_blocks = (unsigned)std::min<long>((L.n + 255) / 256, 256);
     hipLaunchKernelGGL(k_claim_count, dim3(count_blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
-    hipLaunchKernelGGL(k_claim_place, dim3(blocks), dim3(256), 0, st, L.pos, L.dir, L.energy, L.event, L.prim_id,
-                       L.n, L.claim_cnt, L.claim);
+    const unsigned place_blocks = (unsigned)std::min<long>((L.n + 1023) / 1024, 1024);
+    hipLaunchKernelGGL(k_claim_place, dim3(place_blocks), dim3(256), 0, st, L.pos, L.dir, L.energy, L.event,
+                       L.prim_id, L.n, L.claim_cnt, L.claim);
   }
   if (L.spheres) {
     if (L.block == 64) return launch_transport_pool64_spheres(L, st);
