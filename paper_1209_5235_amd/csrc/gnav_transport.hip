@@ -85,11 +85,19 @@ constexpr int kWaves = kPool / 64;
 #ifdef GNAV_AXIS_BOXES
 constexpr int kStack = 16;       // block stack of annihilation photons (entries)
 constexpr int kDep = kPool;      // block cache of touchable deposits (direct mapped)
-constexpr int kIntHold = (3 * kPool) / 8;  // interact passes with fewer slots due wait a round
+// interact passes with fewer slots due than this wait a round (eighths of the
+// pool, settable at build time)
+#ifndef GNAV_INT_HOLD_EIGHTHS
+#define GNAV_INT_HOLD_EIGHTHS 3
+#endif
+constexpr int kIntHold = (GNAV_INT_HOLD_EIGHTHS * kPool) / 8;
 #else
 constexpr int kStack = 64;
 constexpr int kDep = 4 * kPool;
-constexpr int kIntHold = kPool / 4;
+#ifndef GNAV_INT_HOLD_EIGHTHS
+#define GNAV_INT_HOLD_EIGHTHS 2
+#endif
+constexpr int kIntHold = (GNAV_INT_HOLD_EIGHTHS * kPool) / 8;
 #endif
 
 // counters summed per block in LDS (the work counters of counting launches,
