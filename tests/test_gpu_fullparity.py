@@ -10,6 +10,7 @@ flips below 1e-5 of the tracks (the oracle runs in 16 processes):
 
 * calorimeter: all 1e6 photons;
 * barrel: the first 1e5 of its 1e7 photons;
+* endcap (trapezoids and sphere sections): 2e5 photons;
 * batched events: every 64th of the 4096 events, over their geometries.
 """
 import numpy as np
@@ -87,6 +88,22 @@ def test_barrel_first_1e5_tracks(ctx, torch_dev, oracle_lib):
     res = parity.full_check(desc, prim, dig, _logs_fn(ctx, torch, gid, prim, 4096), gpu_tally=tally)
     _report("barrel", res)
     assert res["tracks"] > 100_000
+    _assert_bar(res)
+
+
+def test_endcap_every_track(ctx, torch_dev, oracle_lib):
+    """The trapezoid endcap with its sphere-section shell (the sphere builds run):
+    every track of 2e5 photons from the origin."""
+    from oracle import parity
+    torch = torch_dev
+    desc, gid, nt, og = geom(ctx, "endcap", oracle_lib)
+    print_case("fullparity_endcap")
+    _, prim, _ = W.endcap(n=200_000, seed=3)
+    tally = run_transport(ctx, torch, gid, prim, 0)
+    dig = _gpu_digests(ctx, torch, gid, prim)
+    res = parity.full_check(desc, prim, dig, _logs_fn(ctx, torch, gid, prim, 4096), gpu_tally=tally)
+    _report("endcap", res)
+    assert res["tracks"] > 200_000
     _assert_bar(res)
 
 
