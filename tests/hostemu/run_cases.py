@@ -43,7 +43,7 @@ CASES = {
 # every launch shape and instantiation the library selects from batch fields
 CONFIGS = [dict(cap=64), dict(block=128, cap=64), dict(block=256, chunk=64, sort_period=2, cap=64),
            dict(count_work=True, digests=True), dict(order=1, cap=64), dict(precision=1, cap=64),
-           dict(precision=2, compare=False), dict(noalloc=True)]
+           dict(precision=2, compare=False), dict(noalloc=True), dict(keep_order=True, cap=64)]
 # blocks in concurrent processes: only tallies (device memory) come back
 FORK_CONFIGS = [dict(), dict(block=256, chunk=32), dict(count_work=True, sort_period=3)]
 
