@@ -371,10 +371,11 @@ typedef struct {
   int32_t keep_order;         /* 0: blocks take the primaries in decreasing energy (half-octave
                                  classes, sorted on the device before the transport, in a buffer
                                  of the context), so that the tracks still running when the
-                                 batch runs dry are short ones; 1: in the order given (always so
-                                 in gnav_transport_batch_noalloc, and for batches with per-event
-                                 geometries, whose given order keeps the tracks of one geometry
-                                 together).  Results do not depend on it */
+                                 batch runs dry are short ones; with per-event geometries sorted
+                                 by geometry first (a block's tracks stay in one geometry), for
+                                 up to 16 resident geometries; 1: in the order given (always so
+                                 in gnav_transport_batch_noalloc, and with more than 16
+                                 geometries).  Results do not depend on it */
 } gnav_batch;
 
 /* Transport a batch (Alg. 1 repeated after each interaction; Alg. 2 phase

@@ -1573,9 +1573,10 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
       c->pend_gen++;
     }
     L.pend = c->d_pend.as<double>();
-    if (!b->keep_order && !b->event_geom_dev && b->n_primaries > 0) {
-      // the class counts and cursors, then the primaries copied in claim order
-      size_t claim_bytes = 2 * kClaimClasses * sizeof(unsigned) + (size_t)b->n_primaries * sizeof(ClaimRec);
+    const int keys = b->event_geom_dev ? kClaimClasses * (int)c->geoms.size() : kClaimClasses;
+    if (!b->keep_order && b->n_primaries > 0 && keys <= kClaimMaxKeys) {
+      // the key counts and cursors, then the primaries copied in claim order
+      size_t claim_bytes = 2 * kClaimMaxKeys * sizeof(unsigned) + (size_t)b->n_primaries * sizeof(ClaimRec);
       if (c->d_claim.bytes < claim_bytes) {
         HIP_TRY(c, hipDeviceSynchronize(), "synchronize");
         HIP_TRY(c, c->d_claim.upload(nullptr, claim_bytes, stream), "claim-order buffer");
@@ -1583,7 +1584,8 @@ gnav_status prepare_transport(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, h
         c->pend_gen++;
       }
       L.claim_cnt = c->d_claim.as<unsigned>();
-      L.claim = reinterpret_cast<ClaimRec*>(c->d_claim.as<unsigned>() + 2 * kClaimClasses);
+      L.claim = reinterpret_cast<ClaimRec*>(c->d_claim.as<unsigned>() + 2 * kClaimMaxKeys);
+      L.claim_keys = keys;
     }
   }
   L.count = b->count_work != 0;

@@ -8,8 +8,11 @@
 
 namespace gnav {
 
-// Energy classes of the claim order: half octaves from 1 keV, highest first.
+// Energy classes of the claim order: half octaves from 1 keV, highest first;
+// a batch over several geometries sorts by geometry, then energy class (at
+// most kClaimMaxKeys keys: batches over more geometries keep their order).
 constexpr int kClaimClasses = 64;
+constexpr int kClaimMaxKeys = 1024;
 
 // A primary copied into claim order, so that the transport reads the
 // primaries it claims contiguously (72 bytes).
@@ -37,7 +40,8 @@ struct TransportLaunch {
   DevGeom G;
   long n;
   ClaimRec* claim;         // [n] the primaries in queue order (decreasing energy), or null: as given
-  unsigned* claim_cnt;     // [2 * kClaimClasses] class counts and cursors for building it
+  unsigned* claim_cnt;     // [2 * claim_keys] key counts and cursors for building it
+  int claim_keys;          // kClaimClasses, times the geometries for a batch with per-event geometries
   const int* event;
   const int* prim_id;
   const double* pos;

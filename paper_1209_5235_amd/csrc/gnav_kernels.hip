@@ -223,10 +223,10 @@ __global__ void __launch_bounds__(256) k_free_path(DevGeom G, int W, long n, con
 // The work queue's counter and, when a claim order is built, its class
 // counts and cursors, zeroed in one launch (a kernel rather than a memset
 // node, so the launch sequence can be captured in a graph).
-__global__ void k_reset_launch(unsigned long long* queue, unsigned* claim_cnt) {
+__global__ void k_reset_launch(unsigned long long* queue, unsigned* claim_cnt, int claim_words) {
   if (threadIdx.x == 0) queue[0] = 0ull;
   if (claim_cnt)
-    for (int i = threadIdx.x; i < 2 * kClaimClasses; i += blockDim.x) claim_cnt[i] = 0u;
+    for (int i = threadIdx.x; i < claim_words; i += blockDim.x) claim_cnt[i] = 0u;
 }
 
 __global__ void k_zero_words(unsigned long long* p, size_t n) {
@@ -332,51 +332,82 @@ __device__ __forceinline__ int claim_class(double E) {
   return kClaimClasses - 1 - min(h, kClaimClasses - 1);
 }
 
-// Class counts of the batch (cnt[0..kClaimClasses), zeroed before).
-__global__ void __launch_bounds__(256) k_claim_count(const double* __restrict__ E, long n, unsigned* cnt) {
-  __shared__ unsigned h[kClaimClasses];
-  if (threadIdx.x < kClaimClasses) h[threadIdx.x] = 0;
-  __syncthreads();
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
-    atomicAdd(&h[claim_class(E[i])], 1u);
-  __syncthreads();
-  if (threadIdx.x < kClaimClasses && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+// What the claim kernels read of a batch.
+struct ClaimArgs {
+  const double* pos;
+  const double* dir;
+  const double* E;
+  const int* event;
+  const int* prim_id;
+  const int* event_geom;  // null: one geometry
+  long n;
+  int n_events, n_geoms;
+  int n_keys;             // kClaimClasses, times the geometries when event_geom is given
+  unsigned* cnt;          // [n_keys] counts, then [n_keys] cursors
+  ClaimRec* claim;
+};
+
+// Sort key of primary i: its energy class, preceded by its event's geometry
+// when the batch spans several (the tracks of one geometry stay together, each
+// geometry's highest energies first).  Keys of events or geometries out of
+// range are those of geometry 0 (the transport rejects such primaries).
+__device__ __forceinline__ int claim_key(const ClaimArgs& a, long i) {
+  int k = claim_class(a.E[i]);
+  if (a.event_geom) {
+    const int ev = a.event[i];
+    int g = (ev >= 0 && ev < a.n_events) ? a.event_geom[ev] : 0;
+    if (g < 0 || g >= a.n_geoms) g = 0;
+    k += kClaimClasses * g;
+  }
+  return k;
 }
 
-// Queue positions: the primaries of class c fill [start_c, start_c + cnt_c)
-// in the order their blocks reserve a range (cnt[kClaimClasses + c] is the
-// class's cursor, zeroed before); the order within a class is not fixed.
-// Each primary is copied to its position (reads in the caller's order, one
-// 72-byte record written per primary).
-__global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ pos, const double* __restrict__ dir,
-                                                     const double* __restrict__ E, const int* __restrict__ event,
-                                                     const int* __restrict__ prim_id, long n, unsigned* cnt,
-                                                     ClaimRec* __restrict__ claim) {
-  __shared__ unsigned start[kClaimClasses], h[kClaimClasses], base[kClaimClasses];
+// Key counts of the batch (cnt[0..n_keys), zeroed before).
+__global__ void __launch_bounds__(256) k_claim_count(ClaimArgs a) {
+  __shared__ unsigned h[kClaimMaxKeys];
+  for (int c = threadIdx.x; c < a.n_keys; c += 256) h[c] = 0;
+  __syncthreads();
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < a.n; i += (long)gridDim.x * 256)
+    atomicAdd(&h[claim_key(a, i)], 1u);
+  __syncthreads();
+  for (int c = threadIdx.x; c < a.n_keys; c += 256)
+    if (h[c]) atomicAdd(&a.cnt[c], h[c]);
+}
+
+// Queue positions: the primaries of key c fill [start_c, start_c + cnt_c)
+// in the order their blocks reserve a range (cnt[n_keys + c] is the key's
+// cursor, zeroed before); the order within a key is not fixed.  Each primary
+// is copied to its position (reads in the caller's order, one 72-byte record
+// written per primary).
+__global__ void __launch_bounds__(256) k_claim_place(ClaimArgs a) {
+  __shared__ unsigned start[kClaimMaxKeys], h[kClaimMaxKeys], base[kClaimMaxKeys];
+  for (int c = threadIdx.x; c < a.n_keys; c += 256) start[c] = a.cnt[c];
+  __syncthreads();
   if (threadIdx.x == 0) {
     unsigned acc = 0;
-    for (int c = 0; c < kClaimClasses; c++) {
+    for (int c = 0; c < a.n_keys; c++) {
+      const unsigned k = start[c];
       start[c] = acc;
-      acc += cnt[c];
+      acc += k;
     }
   }
-  // kClaimSpan primaries per thread and pass: one reservation per class and
+  // kClaimSpan primaries per thread and pass: one reservation per key and
   // pass for 256 * kClaimSpan primaries keeps the shared cursors uncontended
   constexpr int kClaimSpan = 4;
-  for (long i0 = blockIdx.x * (256L * kClaimSpan); i0 < n; i0 += (long)gridDim.x * 256 * kClaimSpan) {
-    if (threadIdx.x < kClaimClasses) h[threadIdx.x] = 0;
+  for (long i0 = blockIdx.x * (256L * kClaimSpan); i0 < a.n; i0 += (long)gridDim.x * 256 * kClaimSpan) {
+    for (int c = threadIdx.x; c < a.n_keys; c += 256) h[c] = 0;
     __syncthreads();
     int c[kClaimSpan];
     unsigned r[kClaimSpan];
 #pragma unroll
     for (int k = 0; k < kClaimSpan; k++) {
       const long i = i0 + k * 256 + threadIdx.x;
-      c[k] = i < n ? claim_class(E[i]) : -1;
+      c[k] = i < a.n ? claim_key(a, i) : -1;
       r[k] = c[k] >= 0 ? atomicAdd(&h[c[k]], 1u) : 0u;
     }
     __syncthreads();
-    if (threadIdx.x < kClaimClasses && h[threadIdx.x])
-      base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cnt[kClaimClasses + threadIdx.x], h[threadIdx.x]);
+    for (int q = threadIdx.x; q < a.n_keys; q += 256)
+      if (h[q]) base[q] = start[q] + atomicAdd(&a.cnt[a.n_keys + q], h[q]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kClaimSpan; k++) {
@@ -385,32 +416,34 @@ __global__ void __launch_bounds__(256) k_claim_place(const double* __restrict__ 
       ClaimRec q;
 #pragma unroll
       for (int j = 0; j < 3; j++) {
-        q.pos[j] = pos[3 * i + j];
-        q.dir[j] = dir[3 * i + j];
+        q.pos[j] = a.pos[3 * i + j];
+        q.dir[j] = a.dir[3 * i + j];
       }
-      q.energy = E[i];
-      q.event = event[i];
-      q.prim_id = prim_id[i];
+      q.energy = a.E[i];
+      q.event = a.event[i];
+      q.prim_id = a.prim_id[i];
       q.index = (int)i;
       q.pad = 0;
-      claim[base[c[k]] + r[k]] = q;
+      a.claim[base[c[k]] + r[k]] = q;
     }
     __syncthreads();
   }
 }
 
 hipError_t launch_transport(const TransportLaunch& L, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_launch, dim3(1), dim3(128), 0, st, L.queue, L.n > 0 ? L.claim_cnt : nullptr);
+  hipLaunchKernelGGL(k_reset_launch, dim3(1), dim3(256), 0, st, L.queue, L.n > 0 ? L.claim_cnt : nullptr,
+                     2 * L.claim_keys);
   if (L.n <= 0) return hipGetLastError();
   if (L.claim) {
-    // claim order: primaries by decreasing energy, so that the tracks still
-    // running when the queue runs dry are short ones
-    // (few blocks for the counts: each adds its histogram to the same 64 counters)
+    // claim order: primaries by decreasing energy (per geometry), so that the
+    // tracks still running when the queue runs dry are short ones
+    ClaimArgs ca{L.pos, L.dir, L.energy, L.event, L.prim_id, L.event_geom, L.n, L.n_events, L.n_geoms,
+                 L.claim_keys, L.claim_cnt, L.claim};
+    // (few blocks for the counts: each adds its histogram to the same counters)
     const unsigned count_blocks = (unsigned)std::min<long>((L.n + 255) / 256, 256);
-    hipLaunchKernelGGL(k_claim_count, dim3(count_blocks), dim3(256), 0, st, L.energy, L.n, L.claim_cnt);
+    hipLaunchKernelGGL(k_claim_count, dim3(count_blocks), dim3(256), 0, st, ca);
     const unsigned place_blocks = (unsigned)std::min<long>((L.n + 1023) / 1024, 1024);
-    hipLaunchKernelGGL(k_claim_place, dim3(place_blocks), dim3(256), 0, st, L.pos, L.dir, L.energy, L.event,
-                       L.prim_id, L.n, L.claim_cnt, L.claim);
+    hipLaunchKernelGGL(k_claim_place, dim3(place_blocks), dim3(256), 0, st, ca);
   }
   if (L.spheres) {
     if (L.block == 64) return launch_transport_pool64_spheres(L, st);

@@ -48,6 +48,36 @@ CONFIGS = [dict(cap=64), dict(block=128, cap=64), dict(block=256, chunk=64, sort
 FORK_CONFIGS = [dict(), dict(block=256, chunk=32), dict(count_work=True, sort_period=3)]
 
 
+def multi_case(gnav, ctx, fork):
+    """Events over three geometries (per-event geometry ids): each geometry's
+    events against the oracle run on that geometry alone."""
+    import torch
+    geoms = [W.geometry.tiny(), W.geometry.calorimeter(), W.geometry.barrel()]
+    sources = [W.primaries.source_origin_iso, W.primaries.source_beam, W.primaries.source_axis_iso]
+    prim, event_geom = W.primaries.batched_events(n_events=24, n_geoms=3, seed=5, median=60.0, lo=10, hi=200,
+                                                  sources=sources)
+    gids = [ctx.upload_geometry(g, stream=STREAM)[0] for g in geoms]
+    eg = torch.from_numpy(np.asarray(event_geom, np.int32) + gids[0])
+    refs = []
+    for g, desc in enumerate(geoms):
+        sel = np.nonzero(np.asarray(event_geom)[prim.event] == g)[0]
+        refs.append((sel, oracle.Geometry(desc).transport(prim.subset(sel), seed=0, n_events=prim.n_events)))
+    n_bad = 0
+    for cfg in ([dict(), dict(block=128, chunk=32)] if fork else [dict(), dict(keep_order=True), dict(block=256)]):
+        got = run(gnav, ctx, gids[0], prim, event_geom=eg, **cfg)
+        bad = []
+        for k in EXACT:
+            if got["counters"][k] != sum(r["counters"][k] for _, r in refs):
+                bad.append(k)
+        for g, (sel, r) in enumerate(refs):
+            evs = np.unique(prim.event[sel])
+            if not np.allclose(got["edep_event"][evs], r["edep_event"][evs], rtol=1e-9, atol=1e-15):
+                bad.append(f"edep_event geometry {g}")
+        n_bad += bool(bad)
+        print("multi", cfg, "steps", got["counters"]["steps"], "OK" if not bad else "BAD " + ",".join(bad), flush=True)
+    return n_bad
+
+
 def load(emu_dir):
     spec = importlib.util.spec_from_file_location("gnav_hostemu", os.path.join(emu_dir, "gnav.py"))
     mod = importlib.util.module_from_spec(spec)
@@ -93,6 +123,9 @@ def main():
     ctx = gnav.Context(0)
     n_bad = 0
     for name in names:
+        if name == "multi":
+            n_bad += multi_case(gnav, ctx, fork)
+            continue
         desc, prim = CASES[name]()
         gid, _ = ctx.upload_geometry(desc, stream=STREAM)
         ref = oracle.Geometry(desc).transport(prim, seed=0, log_cap=64)

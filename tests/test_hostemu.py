@@ -19,10 +19,12 @@ sys.path.insert(0, os.path.join(HERE, "hostemu"))
 
 # (guard side, cases, blocks in concurrent processes)
 RUNS = [
-    ("end", ["tiny", "tiny_rot", "calorimeter", "pair_heavy", "barrel", "endcap"], False),
+    ("end", ["tiny", "tiny_rot", "calorimeter", "pair_heavy", "barrel", "endcap", "multi"], False),
     ("start", ["pair_heavy", "barrel", "endcap"], False),
-    ("end", ["calorimeter", "endcap"], True),
+    ("end", ["calorimeter", "endcap", "multi"], True),
 ]
+# configurations of the multi-geometry case (see run_cases.multi_case)
+MULTI = {False: 3, True: 2}
 
 
 @pytest.fixture(scope="module")
@@ -52,4 +54,6 @@ def test_transport_bounds_checked(emu_dir):
         assert p.returncode == 0, f"guard {guard}, fork {fork}: exit status {p.returncode}\n{report}"
         assert "BAD" not in out, report
         from run_cases import CONFIGS, FORK_CONFIGS
-        assert out.count("OK") == len(cases) * len(FORK_CONFIGS if fork else CONFIGS), report
+        single = [c for c in cases if c != "multi"]
+        want = len(single) * len(FORK_CONFIGS if fork else CONFIGS) + (MULTI[fork] if "multi" in cases else 0)
+        assert out.count("OK") == want, report
