@@ -731,6 +731,13 @@ struct gnav_tally {
 
 namespace {
 
+// The four tally arrays zeroed in one launch (a kernel, so a graph can hold it).
+hipError_t zero_tally(gnav_tally* t, hipStream_t st) {
+  void* const p[4] = {t->edep_t.p, t->edep_ev.p, t->esc_ev.p, t->counters.p};
+  const size_t w[4] = {t->edep_t.bytes / 8, t->edep_ev.bytes / 8, t->esc_ev.bytes / 8, t->counters.bytes / 8};
+  return launch_zero4(p, w, st);
+}
+
 gnav_status fail(gnav_ctx* c, gnav_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
@@ -1458,10 +1465,7 @@ gnav_status gnav_tally_create(gnav_ctx* c, int32_t n_events, gnav_tally** out) {
 gnav_status gnav_tally_reset(gnav_ctx* c, gnav_tally* t, void* stream) {
   if (!c || !t) return GNAV_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(c, launch_zero(t->edep_t.p, t->edep_t.bytes / 8, st), "tally reset");
-  HIP_TRY(c, launch_zero(t->edep_ev.p, t->edep_ev.bytes / 8, st), "tally reset");
-  HIP_TRY(c, launch_zero(t->esc_ev.p, t->esc_ev.bytes / 8, st), "tally reset");
-  HIP_TRY(c, launch_zero(t->counters.p, t->counters.bytes / 8, st), "tally reset");
+  HIP_TRY(c, zero_tally(t, st), "tally reset");
   return GNAV_OK;
 }
 
@@ -1818,14 +1822,10 @@ gnav_status gnav_graph_create(gnav_ctx* c, const gnav_batch* b, gnav_tally* t, v
   }
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t e1 = launch_zero(t->edep_t.p, t->edep_t.bytes / 8, cap);
-    hipError_t e2 = launch_zero(t->edep_ev.p, t->edep_ev.bytes / 8, cap);
-    hipError_t e3 = launch_zero(t->esc_ev.p, t->esc_ev.bytes / 8, cap);
-    hipError_t e4 = launch_zero(t->counters.p, t->counters.bytes / 8, cap);
-    hipError_t e5 = launch_transport(L, cap);
+    hipError_t e1 = zero_tally(t, cap);
+    hipError_t e2 = launch_transport(L, cap);
     hipError_t ee = hipStreamEndCapture(cap, &g->graph);
-    e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : e4 != hipSuccess ? e4
-        : e5 != hipSuccess ? e5 : ee;
+    e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : ee;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   g->ctx = c;

@@ -127,5 +127,7 @@ hipError_t launch_free_path(const DevGeom& G, int W, long n, const double* pos, 
                             hipStream_t st);
 // Zero `words` 8-byte words with a kernel (graph-capture safe, no memset node).
 hipError_t launch_zero(void* p, size_t words, hipStream_t st);
+// Zero up to four arrays of 8-byte words in one launch (null or empty ones skipped).
+hipError_t launch_zero4(void* const p[4], const size_t words[4], hipStream_t st);
 
 }  // namespace gnav

@@ -316,6 +316,30 @@ hipError_t launch_mlp_score(const MlpView& M, long n, const float* x, const int*
   return hipGetLastError();
 }
 
+__global__ void k_zero_words4(unsigned long long* p0, size_t n0, unsigned long long* p1, size_t n1,
+                              unsigned long long* p2, size_t n2, unsigned long long* p3, size_t n3) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = t; i < n0; i += stride) p0[i] = 0ull;
+  for (size_t i = t; i < n1; i += stride) p1[i] = 0ull;
+  for (size_t i = t; i < n2; i += stride) p2[i] = 0ull;
+  for (size_t i = t; i < n3; i += stride) p3[i] = 0ull;
+}
+
+hipError_t launch_zero4(void* const p[4], const size_t words[4], hipStream_t st) {
+  size_t n[4], most = 0;
+  for (int k = 0; k < 4; k++) {
+    n[k] = p[k] ? words[k] : 0;
+    most = std::max(most, n[k]);
+  }
+  if (most == 0) return hipSuccess;
+  unsigned blocks = (unsigned)std::min<size_t>((most + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_words4, dim3(blocks), dim3(256), 0, st, (unsigned long long*)p[0], n[0],
+                     (unsigned long long*)p[1], n[1], (unsigned long long*)p[2], n[2], (unsigned long long*)p[3],
+                     n[3]);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, size_t words, hipStream_t st) {
   if (words == 0) return hipSuccess;
   unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
