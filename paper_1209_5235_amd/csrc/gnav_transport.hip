@@ -112,7 +112,7 @@ enum : int { kProcPE = 0, kProcCompton = 1, kProcPair = 2 };
 
 struct Pool {
   double x[kPool], y[kPool], z[kPool], vx[kPool], vy[kPool], vz[kPool];
-  double E[kPool], nl[kPool], saf[kPool], mu[kPool], wmu[kPool], slast[kPool];
+  double E[kPool], nl[kPool], saf[kPool], mu[kPool], wmu[kPool];
   int T[kPool], lvk[kPool], tbase[kPool], event[kPool], key[kPool], draw[kPool];
   int status[kPool];  // kEmpty / kNav / kStep / kInt
   int aux[kPool];     // kNav: navigation mode | lim << 2 ; kInt: process
@@ -264,13 +264,21 @@ __device__ __forceinline__ void log_rec(Pool& P, const TransportArgs& a, int s, 
 // and the network (gnav_learned.h) writes each step's predicted candidate
 // position over its class.
 // Block memory of the learned order only (the other instantiations leave it
-// out, which keeps the 64-slot box build within twelve blocks per CU).
+// out).
 struct LearnScratch {
   uint16_t xf[kPool][6];  // bf16 features of the listed steps (mother-frame point, direction)
   uint16_t cls[kPool];    // their ordering classes in, the predicted candidate positions out
   int pred[kPool];        // predicted candidate position of each slot's next step
 };
 struct NoScratch {};
+// Block memory of logging launches only (per-track logs and digests): the
+// physics step that ended at each pending interaction.  Leaving this and the
+// learned order's memory out of the other instantiations keeps the 64-slot
+// box build at 12.6 KB of LDS, which twelve blocks per CU hold (at 13.1 KB
+// only eleven were resident).
+struct LogScratch {
+  double slast[kPool];
+};
 
 template <bool LOG, bool COUNT, int ORDER, int PREC>
 __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(TransportArgs a) {
@@ -280,6 +288,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ Pool P;
   __shared__ typename std::conditional<ORDER == kOrderLearned, LearnScratch, NoScratch>::type S;
+  __shared__ typename std::conditional<LOG, LogScratch, NoScratch>::type LS;
   double* const my_pend = a.pend + ((long)blockIdx.x * kPool + tid) * 6;
 
   if (tid < kBlockCounters) P.cnt[tid] = 0ull;
@@ -678,7 +687,7 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
             double u = rng_next(rs, a.seed_lo, a.seed_hi) * mu;
             P.draw[s] = (int)rs.draw;
             P.aux[s] = u < pe ? kProcPE : (u < pe + co ? kProcCompton : kProcPair);
-            P.slast[s] = s_phys;
+            if constexpr (LOG) LS.slast[s] = s_phys;
             P.status[s] = kInt;
           } else {
             // the pure FP32 form steps past the boundary by its surface band, so
@@ -737,7 +746,8 @@ __global__ void __launch_bounds__(kPool) GNAV_TRANSPORT_ATTR k_transport(Transpo
         const int T = P.T[s];
         const int event = P.event[s];
         const double E = P.E[s];
-        const double sl = P.slast[s];
+        double sl = 0.0;
+        if constexpr (LOG) sl = LS.slast[s];
         const int steps = P.zero_steps[s] >> 8;
         Philox rs{(uint32_t)event, (uint32_t)P.key[s], (uint32_t)P.draw[s]};
         if (proc == kProcPE) {
