@@ -46,3 +46,45 @@ def test_no_device_calls_without_gpu_fail_cleanly():
     h = ctypes.c_void_p()
     st = gnav.gnav_create(0, ctypes.byref(h))
     assert st != 0
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of `fields` in `struct`, from a C program built with gcc
+    against the public header."""
+    import subprocess
+    import tempfile
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gnav.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        with open(src, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+def test_binding_structs_match_the_header_layout():
+    """Every ctypes structure of the binding has the size and field offsets of the
+    C structure it mirrors (a field added on one side only fails here)."""
+    from paper_1209_5235_amd import gnav
+    for name in ("gnav_geometry_desc", "gnav_batch", "gnav_step_outputs", "gnav_tuning"):
+        cls = getattr(gnav, name)
+        fields = [f[0] for f in cls._fields_]
+        size, offsets = _c_layout(name, fields)
+        assert ctypes.sizeof(cls) == size, name
+        assert [getattr(cls, f).offset for f in fields] == offsets, name
+
+
+def test_record_dtypes_match_the_header_layout():
+    """The numpy views of device records (log, digest, crossing) have the C sizes and
+    field offsets."""
+    from paper_1209_5235_amd import gnav
+    for name, dt in (("gnav_logrec", gnav.LOG_DTYPE), ("gnav_digest", gnav.DIGEST_DTYPE),
+                     ("gnav_crossing", gnav.CROSSING_DTYPE)):
+        fields = list(dt.names)
+        size, offsets = _c_layout(name, fields)
+        assert dt.itemsize == size, name
+        assert [dt.fields[f][1] for f in fields] == offsets, name
