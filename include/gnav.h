@@ -313,7 +313,8 @@ gnav_status gnav_free_path(gnav_ctx* ctx, int32_t geom_id, int64_t n, const doub
                            double* t_dev, int32_t* n_bounds_dev, void* stream);
 
 /* Device energy tallies, sized to every touchable resident at creation and to
- * n_events events.  Created zeroed. */
+ * n_events events.  Created zeroed.  gnav_tally_reset zeroes them again on
+ * `stream` (one kernel launch, no memset node, so a graph may capture it). */
 gnav_status gnav_tally_create(gnav_ctx* ctx, int32_t n_events, gnav_tally** out);
 gnav_status gnav_tally_reset(gnav_ctx* ctx, gnav_tally* tally, void* stream);
 gnav_status gnav_tally_free(gnav_ctx* ctx, gnav_tally* tally);
