@@ -84,7 +84,8 @@ constexpr int kPool = GNAV_POOL;
 constexpr int kWaves = kPool / 64;
 #ifdef GNAV_AXIS_BOXES
 constexpr int kStack = 16;       // block stack of annihilation photons (entries)
-constexpr int kDep = kPool;      // block cache of touchable deposits (direct mapped)
+constexpr int kDep = kPool;      // block cache of touchable deposits
+constexpr int kDepProbes = 4;    // entries a touchable may take (hashed group)
 // interact passes with fewer slots due than this wait a round (eighths of the
 // pool, settable at build time)
 #ifndef GNAV_INT_HOLD_EIGHTHS
@@ -94,6 +95,7 @@ constexpr int kIntHold = (GNAV_INT_HOLD_EIGHTHS * kPool) / 8;
 #else
 constexpr int kStack = 64;
 constexpr int kDep = 4 * kPool;
+constexpr int kDepProbes = 1;    // direct mapped
 #ifndef GNAV_INT_HOLD_EIGHTHS
 #define GNAV_INT_HOLD_EIGHTHS 2
 #endif
@@ -174,18 +176,37 @@ __device__ __forceinline__ int compact(Pool& P, bool flag, int key) {
   return n;
 }
 
-// Deposit d in touchable T: summed in the block's LDS cache when T owns (or
-// can claim) its entry, else added to the device tally directly; the cache
-// is added to the tally when the block ends.
-__device__ __forceinline__ void deposit_t(Pool& P, const TransportArgs& a, int T, double d) {
-  const int h = T & (kDep - 1);
+static_assert((kDep & (kDep - 1)) == 0 && kDepProbes <= kDep, "deposit cache: power-of-two entries");
+
+// Add d to cache entry h if touchable T owns it or can claim it.
+__device__ __forceinline__ bool dep_try(Pool& P, int h, int T, double d) {
   int owner = P.dkey[h];
   if (owner == -1) {
     owner = atomicCAS(&P.dkey[h], -1, T);
     if (owner == -1) owner = T;
   }
-  if (owner == T) atomicAdd(&P.dval[h], d);
-  else atomic_add_f64(a.edep_t + T, d);
+  if (owner != T) return false;
+  atomicAdd(&P.dval[h], d);
+  return true;
+}
+
+// Deposit d in touchable T: summed in the block's LDS cache when T owns (or
+// can claim) one of its candidate entries, else added to the device tally
+// directly; the cache is added to the tally when the block ends.  A claimed
+// entry keeps its touchable until the block ends and the candidates are tried
+// in a fixed order, so a touchable holds at most one entry.  One candidate:
+// T mod kDep, which gives consecutive touchables (the phi segments of a ring)
+// distinct entries.  Several: an aligned group picked by a multiplicative
+// (Fibonacci) hash of T, so that touchables a fixed stride apart (the cells
+// of stacked layers) do not all fall on a few entries.
+__device__ __forceinline__ void deposit_t(Pool& P, const TransportArgs& a, int T, double d) {
+  int h;
+  if constexpr (kDepProbes == 1) h = T & (kDep - 1);
+  else h = (int)(((unsigned)T * 2654435769u) >> (32 - __builtin_ctz(kDep)));
+#pragma unroll
+  for (int k = 0; k < kDepProbes; k++)
+    if (dep_try(P, h ^ k, T, d)) return;
+  atomic_add_f64(a.edep_t + T, d);
 }
 
 template <bool LOG>
